@@ -1,0 +1,357 @@
+"""Seeded synthetic inputs for the nonlocal-exchange path.
+
+This module is shared by the CPU oracle, the tests and the benchmark. It only
+*draws* inputs -- lattices, q meshes, plane-wave sets, Coulomb-matrix blocks and
+the mixed-product-basis (MPB) projections M -- and contains none of the
+exchange method's arithmetic.
+
+Workloads (synthetic stand-ins for the paper's Si, ZnO and SrTiO3 systems, whose
+wavefunctions and Coulomb matrices are not available):
+
+* ``c1``  -- 1 k, 8 random non-Gamma q (sc a=10 bohr), 2 atoms x 25 LM channels
+  x 3 radial functions (150 MT), 150 plane waves, 16 bands, 8 occupied.
+* ``c2``  -- Si-like fcc a=10.26 bohr, 4x4x4 Gamma-centred q mesh, 8 irreducible k,
+  2 atoms with n_rad(l)=10-l for l<=4 (360 MT), 260 plane waves, 24 bands, 4 occ.
+* ``c3``  -- ZnO-like hexagonal a=6.14, c=9.84 bohr, 6x6x4 mesh, 21 irreducible k,
+  N_MB(q) ~ U{820..1400}, 4 atoms x 25 channels carrying a fixed MT count of
+  0.5 * mean N_MB, 60 bands, 18 occupied.
+* ``c4``  -- SrTiO3-like sc a=7.38 bohr, 6x6x6 mesh, 20 irreducible k,
+  N_MB(q) ~ U{2000..2600}, 5 atoms x 36 channels (l<=5) with 0.6 * mean N_MB MT
+  functions, 100 bands, 20 occupied.
+
+Index order inside the MPB follows the paper's Fig. 1 ordering (Sec. II.C
+"Sparsity of the Coulomb matrix"): all multipole-free MT functions grouped by
+(atom, L, M) channel, then one multipole-carrying MT function per channel, then
+the interstitial plane waves.
+
+Random numbers for M come from a counter-based SplitMix64 stream (Steele, Lea &
+Flood, OOPSLA 2014) turned into normals by the Box-Muller transform, so that any
+(k, q) block can be regenerated independently (on the host here, and by the
+device twin in ``synth/csrc/synth.hip``). Everything else uses
+``numpy.random.default_rng`` with explicit integer seeds.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Config", "make_config", "coulomb_blocks", "m_block", "m_all",
+    "splitmix64_stream", "normal_pairs", "CONFIG_NAMES",
+]
+
+MASK64 = (1 << 64) - 1
+GAMMA64 = 0x9E3779B97F4A7C15
+
+
+# ----------------------------------------------------------------------------
+# SplitMix64 (Steele, Lea & Flood 2014) in counter form.
+# ----------------------------------------------------------------------------
+def _mix64_int(z: int) -> int:
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def sm_int(seed: int, i: int) -> int:
+    """The (i+1)-th output of a SplitMix64 generator started at ``seed``."""
+    return _mix64_int((seed + (i + 1) * GAMMA64) & MASK64)
+
+
+def stream_seed(seed: int, cfg_tag: int, k: int, q: int) -> int:
+    """Seed of the (k, q) substream: SM(SM(SM(seed, cfg_tag), k), q)."""
+    return sm_int(sm_int(sm_int(seed, cfg_tag), k), q)
+
+
+def splitmix64_stream(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs ``start .. start+count-1`` of the counter-mode SplitMix64 stream."""
+    with np.errstate(over="ignore"):
+        i = np.arange(start, start + count, dtype=np.uint64)
+        z = np.uint64(seed) + (i + np.uint64(1)) * np.uint64(GAMMA64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def _uniform_open(x: np.ndarray) -> np.ndarray:
+    """Top 53 bits to a double in the open interval (0, 1)."""
+    return ((x >> np.uint64(11)).astype(np.float64) + 0.5) * (1.0 / 9007199254740992.0)
+
+
+def normal_pairs(seed: int, start_pair: int, count: int):
+    """Box-Muller: pair j uses stream outputs 2j (radius) and 2j+1 (angle).
+
+    Returns (z0, z1) = (r cos(2 pi u2), r sin(2 pi u2)), r = sqrt(-2 ln u1).
+    """
+    x = splitmix64_stream(seed, 2 * start_pair, 2 * count)
+    u1 = _uniform_open(x[0::2])
+    u2 = _uniform_open(x[1::2])
+    r = np.sqrt(-2.0 * np.log(u1))
+    t = 2.0 * math.pi * u2
+    return r * np.cos(t), r * np.sin(t)
+
+
+# ----------------------------------------------------------------------------
+# Configurations
+# ----------------------------------------------------------------------------
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "tiny", "small", "ragged")
+
+
+@dataclasses.dataclass
+class Config:
+    name: str
+    tag: int                       # integer identifying the workload in the RNG tree
+    seed: int
+    lattice: np.ndarray            # rows = real-space lattice vectors (bohr)
+    q_frac: np.ndarray             # [n_q, 3] q points in reciprocal-lattice coordinates
+    n_k: int
+    n_occ: int
+    n_bands: List[int]             # per irreducible k
+    ch_nrad: List[int]             # radial functions per (atom, L, M) channel (>=1)
+    n_pw: List[int]                # plane waves per q
+    w_q: Optional[np.ndarray] = None   # default 1/n_q
+    w_k: Optional[np.ndarray] = None   # default 1/n_k
+    m_dtype: str = "c128"          # dtype the caller hands to the library
+    description: str = ""
+
+    # -- derived sizes -------------------------------------------------------
+    @property
+    def n_q(self) -> int:
+        return int(self.q_frac.shape[0])
+
+    @property
+    def n_ch(self) -> int:
+        return len(self.ch_nrad)
+
+    @property
+    def n_s(self) -> int:
+        """Number of multipole-free MT functions (sum over channels of nrad-1)."""
+        return int(sum(b - 1 for b in self.ch_nrad))
+
+    def n_d(self, q: int) -> int:
+        """Size of the dense block: one multipole function per channel + PWs."""
+        return self.n_ch + int(self.n_pw[q])
+
+    def n_mb(self, q: int) -> int:
+        return self.n_s + self.n_d(q)
+
+    def weights_q(self) -> np.ndarray:
+        if self.w_q is not None:
+            return np.asarray(self.w_q, dtype=np.float64)
+        return np.full(self.n_q, 1.0 / self.n_q)
+
+    def weights_k(self) -> np.ndarray:
+        if self.w_k is not None:
+            return np.asarray(self.w_k, dtype=np.float64)
+        return np.full(self.n_k, 1.0 / self.n_k)
+
+    def recip(self) -> np.ndarray:
+        """Rows = reciprocal lattice vectors b_i with a_i . b_j = 2 pi delta_ij."""
+        return 2.0 * math.pi * np.linalg.inv(self.lattice).T
+
+    def q_cart(self) -> np.ndarray:
+        return self.q_frac @ self.recip()
+
+    def m_elems(self, k: int) -> int:
+        """Complex elements of M for one k (all q)."""
+        nb = self.n_bands[k]
+        return int(sum(self.n_occ * nb * self.n_mb(q) for q in range(self.n_q)))
+
+
+def _fcc(a):
+    return 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+
+
+def _sc(a):
+    return a * np.eye(3)
+
+
+def _hex(a, c):
+    return np.array([[a, 0.0, 0.0], [-0.5 * a, 0.5 * math.sqrt(3.0) * a, 0.0], [0.0, 0.0, c]])
+
+
+def _mesh(n1, n2, n3):
+    """Gamma-centred equidistant mesh in reciprocal-lattice coordinates."""
+    g = np.stack(np.meshgrid(np.arange(n1) / n1, np.arange(n2) / n2,
+                             np.arange(n3) / n3, indexing="ij"), axis=-1)
+    return g.reshape(-1, 3)
+
+
+def _even_split(total: int, parts: int) -> List[int]:
+    base, rem = divmod(total, parts)
+    return [base + (1 if c < rem else 0) for c in range(parts)]
+
+
+def _channels(n_atoms: int, lmax: int, nrad_of_l) -> List[int]:
+    out = []
+    for _a in range(n_atoms):
+        for l in range(lmax + 1):
+            out += [int(nrad_of_l(l))] * (2 * l + 1)
+    return out
+
+
+def make_config(name: str, seed: int = 0) -> Config:
+    """Build one of the named synthetic workloads (see module docstring)."""
+    rng = np.random.default_rng([seed, 7919, CONFIG_NAMES.index(name) if name in CONFIG_NAMES else 99])
+    if name == "c1":
+        q = rng.uniform(0.0, 1.0, size=(8, 3))
+        return Config(name, 1, seed, _sc(10.0), q, n_k=1, n_occ=8, n_bands=[16],
+                      ch_nrad=_channels(2, 4, lambda l: 3), n_pw=[150] * 8,
+                      description="oracle-sized: 1 k, 8 q, N_MB=300, 16 bands, 8 occ")
+    if name == "c2":
+        q = _mesh(4, 4, 4)
+        return Config(name, 2, seed, _fcc(10.26), q, n_k=8, n_occ=4, n_bands=[24] * 8,
+                      ch_nrad=_channels(2, 4, lambda l: 10 - l), n_pw=[260] * 64,
+                      description="Si-like fcc, 4x4x4 q, 8 k, N_MB=620, 24 bands, 4 occ")
+    if name in ("c3", "c4"):
+        if name == "c3":
+            lat, q, nk, nocc, nb = _hex(6.14, 9.84), _mesh(6, 6, 4), 21, 18, 60
+            lo, hi, fmt, n_atoms, lmax = 820, 1400, 0.5, 4, 4
+        else:
+            lat, q, nk, nocc, nb = _sc(7.38), _mesh(6, 6, 6), 20, 20, 100
+            lo, hi, fmt, n_atoms, lmax = 2000, 2600, 0.6, 5, 5
+        nq = q.shape[0]
+        nmb = rng.integers(lo, hi + 1, size=nq)
+        n_ch = n_atoms * (lmax + 1) ** 2
+        mt = int(round(fmt * 0.5 * (lo + hi)))
+        ch = [b for b in _even_split(mt, n_ch)]
+        n_pw = [int(x) - mt for x in nmb]
+        return Config(name, 3 if name == "c3" else 4, seed, lat, q, n_k=nk, n_occ=nocc,
+                      n_bands=[nb] * nk, ch_nrad=ch, n_pw=n_pw, m_dtype="c64",
+                      description=f"{name}: uneven N_MB in [{lo},{hi}], {nb} bands, {nocc} occ")
+    if name == "tiny":
+        q = rng.uniform(0.0, 1.0, size=(3, 3))
+        return Config(name, 5, seed, _sc(8.0), q, n_k=2, n_occ=2, n_bands=[3, 4],
+                      ch_nrad=[1, 3, 2], n_pw=[5, 4, 6],
+                      description="brute-force sized")
+    if name == "small":
+        q = _mesh(2, 2, 2)
+        return Config(name, 6, seed, _fcc(10.26), q, n_k=3, n_occ=3, n_bands=[8, 8, 8],
+                      ch_nrad=_channels(1, 2, lambda l: 4 - l), n_pw=[40] * 8,
+                      description="few tiles")
+    if name == "ragged":
+        # Uneven everything: bands per k, PW per q, channel sizes incl. nrad=1,
+        # sizes that are not multiples of any tile.
+        q = _mesh(3, 2, 1)
+        nq = q.shape[0]
+        n_pw = [int(x) for x in rng.integers(37, 131, size=nq)]
+        ch = [int(x) for x in rng.integers(1, 8, size=23)]
+        return Config(name, 7, seed, _hex(6.14, 9.84), q, n_k=3, n_occ=5,
+                      n_bands=[13, 37, 21], ch_nrad=ch, n_pw=n_pw,
+                      description="ragged tails in every dimension")
+    raise ValueError(f"unknown config {name!r}")
+
+
+# ----------------------------------------------------------------------------
+# Coulomb-matrix blocks
+# ----------------------------------------------------------------------------
+def pw_set(cfg: Config, q: int) -> np.ndarray:
+    """|q+G| of the N_PW(q) shortest nonzero q+G vectors (ascending)."""
+    b = cfg.recip()
+    qc = cfg.q_cart()[q]
+    need = int(cfg.n_pw[q])
+    nmax = 2
+    while True:
+        r = np.arange(-nmax, nmax + 1)
+        n = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+        g = np.linalg.norm(qc + n @ b, axis=1)
+        g = np.sort(g[g > 1e-10])
+        # the sphere of radius g[need] must lie inside the enumerated box
+        bmin = min(np.linalg.norm(b, axis=1))
+        if len(g) > need and g[need] < (nmax - 1) * bmin * 0.5:
+            return g[:need]
+        nmax *= 2
+
+
+def _shared_hermitian(cfg: Config, n: int) -> np.ndarray:
+    """Seeded random Hermitian matrix with spectral norm exactly 1."""
+    rng = np.random.default_rng([cfg.seed, cfg.tag, 31337])
+    g = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    h = 0.5 * (g + g.conj().T)
+    lam = np.linalg.eigvalsh(h)
+    return h / max(abs(lam[0]), abs(lam[-1]))
+
+
+def coulomb_blocks(cfg: Config):
+    """Synthetic Coulomb matrix in the transformed (sparse) MPB.
+
+    Returns ``(E, D, C)``:
+      * ``E[q]`` -- N_d(q) x N_d(q) complex128 Hermitian positive definite dense block
+        over [one multipole function per channel | plane waves of q].
+        E = S^1/2 (I + H/2) S^1/2, S = diag(m_c, 4 pi / |q+G|^2), ||H||_2 = 1,
+        H = P_q H0 P_q^H (principal submatrix of one shared H0 rotated by a
+        per-q diagonal phase P_q).
+      * ``D[c]`` -- (nrad_c-1)^2 Hermitian PD block among the multipole-free
+        functions of channel c (q-independent).
+      * ``C[c]`` -- (nrad_c-1) coupling of those functions to the channel's own
+        multipole function (q-independent), scaled so that
+        |C_c|^2 = lambda_min(D_c) * m_c / 8, keeping the full matrix PD.
+    """
+    rng = np.random.default_rng([cfg.seed, cfg.tag, 4242])
+    n_ch = cfg.n_ch
+    m_c = rng.uniform(1.0, 10.0, size=n_ch)
+    D, C = [], []
+    for c, b in enumerate(cfg.ch_nrad):
+        nb = b - 1
+        if nb == 0:
+            D.append(np.zeros((0, 0), np.complex128))
+            C.append(np.zeros((0,), np.complex128))
+            continue
+        x = rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))
+        s = rng.uniform(0.5, 2.0)
+        d = (x @ x.conj().T / nb + np.eye(nb)) * s
+        d = 0.5 * (d + d.conj().T)
+        lmin = np.linalg.eigvalsh(d)[0]
+        cv = rng.standard_normal(nb) + 1j * rng.standard_normal(nb)
+        cv *= math.sqrt(lmin * m_c[c] / 8.0) / np.linalg.norm(cv)
+        D.append(d)
+        C.append(cv)
+    nd_max = max(cfg.n_d(q) for q in range(cfg.n_q))
+    h0 = _shared_hermitian(cfg, nd_max)
+    E = []
+    for q in range(cfg.n_q):
+        nd = cfg.n_d(q)
+        g = pw_set(cfg, q)
+        s = np.concatenate([m_c, 4.0 * math.pi / g ** 2])
+        ph = np.exp(2j * math.pi * np.random.default_rng([cfg.seed, cfg.tag, 77, q]).uniform(size=nd))
+        h = (ph[:, None] * h0[:nd, :nd]) * ph.conj()[None, :]
+        rs = np.sqrt(s)
+        e = rs[:, None] * (np.eye(nd) + 0.5 * h) * rs[None, :]
+        E.append(0.5 * (e + e.conj().T))
+    return E, D, C
+
+
+# ----------------------------------------------------------------------------
+# MPB projections M
+# ----------------------------------------------------------------------------
+def m_block(cfg: Config, k: int, q: int, dtype=np.complex128) -> np.ndarray:
+    """M(k,q) as an array [n_occ][n_b(k)][N_MB(q)] (I fastest).
+
+    Element (n'', n, I) is (z_re + i z_im) * exp(-0.1 I / N_MB) where
+    (z_re, z_im) is Box-Muller pair e = (n'' n_b + n) N_MB + I of the
+    (k, q) SplitMix64 substream.
+    """
+    nb, nmb, nocc = cfg.n_bands[k], cfg.n_mb(q), cfg.n_occ
+    s = stream_seed(cfg.seed, cfg.tag, k, q)
+    n = nocc * nb * nmb
+    z0, z1 = normal_pairs(s, 0, n)
+    decay = np.exp(-0.1 * np.arange(nmb) / nmb)
+    out = (z0 + 1j * z1).reshape(nocc, nb, nmb) * decay
+    return out.astype(dtype, copy=False)
+
+
+def m_all(cfg: Config, k: int, dtype=np.complex128) -> np.ndarray:
+    """M for one k, all q blocks concatenated in mesh order (flat, complex)."""
+    return np.concatenate([m_block(cfg, k, q, dtype).ravel() for q in range(cfg.n_q)])
+
+
+def m_offsets(cfg: Config, k: int) -> np.ndarray:
+    """Start (in complex elements) of each q block inside ``m_all(cfg, k)``."""
+    nb = cfg.n_bands[k]
+    sizes = [cfg.n_occ * nb * cfg.n_mb(q) for q in range(cfg.n_q)]
+    return np.concatenate([[0], np.cumsum(sizes)])[:-1].astype(np.int64)
