@@ -1,0 +1,177 @@
+/*
+ * exchange.h -- C ABI of the MI355X (gfx950) nonlocal-exchange library.
+ *
+ * The library computes the Hartree-Fock exchange matrix of a hybrid functional
+ * in the wavefunction basis, the hot path of the PBE0-in-FLAPW method of
+ * Betzinger, Friedrich & Bluegel (arXiv:1003.0524):
+ *
+ *   V_{nn'}(k) = - sum_q w_q sum_{n'' occ} sum_{IJ} conj(M^{n n''}_I(k,q)) v_IJ(q) M^{n' n''}_J(k,q)
+ *
+ * (Sec. II.C, eq. "vec-mat-vec"; the q sum is the Brillouin-zone integration
+ * on the k mesh of Sec. I; v is the Coulomb matrix of the mixed product basis,
+ * eq. "coulomb matrix").
+ *
+ * Coulomb matrix layout (the transformed, sparse mixed product basis of
+ * Sec. II.C and its Fig. 1): the basis index I runs over
+ *   [ multipole-free MT functions, channel 0, channel 1, ... ]   N_s = sum_c (nrad_c - 1)
+ *   [ one multipole-carrying MT function per channel ]            n_channels
+ *   [ interstitial plane waves of q ]                            n_pw[q]
+ * A channel is one (atom, L, M) combination. Nonzero blocks of v(q):
+ *   D_c  (nrad_c-1)^2  among the multipole-free functions of channel c,
+ *   C_c  (nrad_c-1)    between those and the channel's own multipole function,
+ *   E(q) N_d(q)^2      dense block over [multipole functions | plane waves],
+ *                      N_d(q) = n_channels + n_pw[q].
+ * Multipole-free functions produce no potential outside their sphere, so only
+ * the on-site (lattice translation T = 0) term of the Bloch sum contributes to
+ * D_c and C_c: they are the same for every q and are passed once.
+ *
+ * All complex numbers are interleaved (re, im) pairs; matrices are column-major.
+ *
+ * Error behaviour: no function throws or aborts across the ABI. Every call
+ * returns an exc_status; a human-readable message for the last failure is
+ * available from exchange_last_error(ctx). On failure nothing is written to
+ * the caller's outputs. Calls on a destroyed or never-initialised context
+ * return EXC_ESTATE (a NULL ctx returns EXC_EINVAL).
+ *
+ * Asynchrony: exchange_matrix / exchange_matrix_all enqueue work on the given
+ * HIP stream (hipStream_t passed as void*, NULL = the default stream) and
+ * return without waiting when on_device = 1; inputs must stay valid and
+ * outputs must not be read until the stream has reached that point. With
+ * on_device = 0 the call copies from / to host memory and returns when the
+ * result is on the host.
+ */
+#ifndef EXCHANGE_H
+#define EXCHANGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EXC_OK = 0,
+  EXC_EINVAL = -1,        /* NULL pointer, negative or inconsistent size, bad enum  */
+  EXC_ENOMEM = -2,        /* device or host allocation failed                       */
+  EXC_ENOTPD = -3,        /* Cholesky pivot <= 0: v(q) is not positive definite     */
+  EXC_EHIP = -4,          /* a HIP runtime call failed                              */
+  EXC_ESTATE = -5,        /* context destroyed, not initialised, or result missing  */
+  EXC_EUNSUPPORTED = -6   /* valid request this build does not support              */
+} exc_status;
+
+/* Arithmetic of the bulk products (Cholesky, q sum and diagonal are always FP64). */
+typedef enum {
+  EXC_FP64 = 0,           /* FP64 MFMA throughout                                    */
+  EXC_FP32 = 1,           /* operands rounded to FP32, FP32 MFMA, FP32 accumulate    */
+  EXC_BF16X3 = 2,         /* x = hi + lo (bf16, RNE); hi*hi + hi*lo + lo*hi on BF16
+                             MFMA with FP32 accumulate (Henry, Tang & Heinecke 2019) */
+  EXC_BF16X6 = 3          /* x = hi + mid + lo; the six leading products             */
+} exc_precision;
+
+/* How the product with v(q) is organised. Both are exact re-arrangements of
+ * the vector-matrix-vector form. */
+typedef enum {
+  EXC_FORM_GEMM = 0,      /* W = v A (sparse blocks + dense E), V -= w_q A^H W; FP64 only */
+  EXC_FORM_CHOL_HERK = 1  /* v = L L^H once at init; Y = L^H A, V -= w_q Y^H Y            */
+} exc_form;
+
+typedef enum { EXC_C128 = 0, EXC_C64 = 1 } exc_dtype;   /* element type of M */
+
+typedef struct exc_ctx exc_ctx;   /* opaque; owned by the library */
+
+typedef struct {
+  int32_t n_k;              /* number of irreducible k points (>= 1)                    */
+  int32_t n_q;              /* number of q points of the mesh (>= 1)                     */
+  int32_t n_occ;            /* occupied bands n'' summed at every k-q (>= 1)             */
+  int32_t n_channels;       /* (atom, L, M) channels (>= 0)                              */
+  const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k (>= 1)                    */
+  const int32_t *n_pw;      /* [n_q] interstitial plane waves of q (>= 0)                */
+  const int32_t *ch_nrad;   /* [n_channels] radial functions per channel (>= 1):
+                               one multipole function + (nrad - 1) multipole-free ones  */
+  const double *w_q;        /* [n_q] q weights, host memory; NULL -> 1/n_q              */
+  int32_t precision;        /* exc_precision                                             */
+  int32_t form;             /* exc_form                                                  */
+  int32_t batched;          /* exchange_matrix_all: 1 = one persistent launch over all
+                               (k,q) work captured in a HIP graph; 0 = one launch per
+                               (k,q) pair, no graph                                      */
+  int32_t device;           /* HIP device ordinal                                        */
+} exc_desc;
+
+typedef struct {
+  const void *const *E;     /* [n_q] -> N_d(q)^2 complex128, column-major, Hermitian     */
+  const void *D;            /* concat over channels of (nrad_c-1)^2 complex128, col-major */
+  const void *C;            /* concat over channels of (nrad_c-1) complex128              */
+  int32_t on_device;        /* 0: host pointers, 1: device pointers (copied either way)   */
+} exc_coulomb;
+
+/*
+ * exchange_init -- validate sizes, copy v(q) to device memory and prepare it.
+ * The Coulomb matrix is independent of the wavefunctions and is prepared once
+ * per self-consistency cycle (Sec. II.C, after eq. "coulomb matrix"). With
+ * form = EXC_FORM_CHOL_HERK it is Cholesky-factored in FP64 on the GPU here;
+ * a non-positive pivot returns EXC_ENOTPD (the message names q). The caller's
+ * buffers may be freed after return. *out receives the new context (NULL on
+ * failure). The call synchronises `stream`.
+ */
+exc_status exchange_init(const exc_desc *desc, const exc_coulomb *coulomb, void *stream,
+                         exc_ctx **out);
+
+/*
+ * exchange_matrix -- V^x(k) for one irreducible k, summed over every q of the
+ * mesh (eq. "vec-mat-vec" with the band cutoff n, n' < n_b(k), Sec. II).
+ *   M  : the q blocks of k concatenated in mesh order; block q is
+ *        [n''< n_occ][n < n_b(k)][I < N_MB(q)] (I fastest), element type `dtype`,
+ *        holding M^{n n''}_I(k,q) = <M_I^q phi_{n'' k-q} | phi_{n k}>.
+ *   Vx : n_b(k)^2 complex128, column-major. The upper triangle is computed, the
+ *        lower triangle is its exact conjugate mirror and Im V_nn = 0.
+ *   on_device: 1 -> M and Vx are device pointers; 0 -> host pointers.
+ * The result also stays resident in the context for exchange_energy.
+ */
+exc_status exchange_matrix(exc_ctx *ctx, int32_t k, const void *M, int32_t dtype,
+                           int32_t on_device, void *Vx, void *stream);
+
+/*
+ * exchange_matrix_all -- V^x(k) for every irreducible k. M_k[k] and Vx_k[k] are
+ * laid out as for exchange_matrix. With desc.batched = 1 all (k, q) work runs
+ * in one persistent launch replayed from a HIP graph (re-captured when the
+ * pointers change); otherwise one launch per (k, q) pair.
+ */
+exc_status exchange_matrix_all(exc_ctx *ctx, const void *const *M_k, int32_t dtype,
+                               int32_t on_device, void *const *Vx_k, void *stream);
+
+/*
+ * exchange_energy -- E_x = 1/2 sum_k w_k Tr(rho_k V_k) over the resident V(k)
+ * of the last exchange_matrix[_all] calls (eq. "HF exchange energy" with a
+ * spin-degenerate density matrix rho = 2 P_occ).
+ *   w_k   : [n_k] host weights, NULL -> 1/n_k
+ *   rho_k : [n_k] device pointers to n_b(k)^2 complex128 column-major, or NULL
+ *           for rho_k = diag(2 for n < n_occ, 0 otherwise)
+ * Synchronises the context's stream. EXC_ESTATE if some V(k) was never computed.
+ */
+exc_status exchange_energy(exc_ctx *ctx, const double *w_k, const void *const *rho_k,
+                           double *E_out);
+
+/* Message of the last failure on ctx (never NULL; "" if none). With ctx == NULL,
+ * the message of the last failed exchange_init on this thread. */
+const char *exchange_last_error(const exc_ctx *ctx);
+
+/* Release every resource of ctx. NULL is a no-op; a second destroy of the same
+ * pointer is undefined (the memory is gone), as for free(). */
+void exchange_destroy(exc_ctx *ctx);
+
+/*
+ * exchange_query -- introspection for tests and benchmarks.
+ *   what = 0: number of work items of the batched launch
+ *   what = 1: nominal flops of the method per exchange_matrix_all (sparse-aware,
+ *             complex multiply-add = 8 flops, Hermitian upper triangle only)
+ *   what = 2: flops the chosen form executes per exchange_matrix_all (padding included)
+ *   what = 3: tile configuration id chosen by the autotuner (-1 if not tuned)
+ *   what = 4: algorithmic HBM bytes of one exchange_matrix_all
+ *             (M read once, v(q) read once, Vx written once)
+ */
+exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXCHANGE_H */

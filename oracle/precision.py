@@ -3,9 +3,11 @@
 Predicts the error a kernel running the Cholesky/HERK form in a reduced product
 precision should show against the float64 oracle, so that a GPU parity test can
 demand "within a small factor of the predicted error" instead of an arbitrary
-tolerance. The products themselves are carried out exactly (float64) on the
-rounded operands; only the rounding of the operands and of the intermediate
-Y = L^H A to the mode's storage is modelled.
+tolerance. Modelled: rounding of the operands to the mode's storage, products
+of split pieces (exact in binary32, as on the matrix cores), accumulation in
+binary32 (NumPy float32 / complex64 GEMMs; the summation order differs from the
+hardware's but the error magnitude does not), rounding of Y = L^H A to binary32,
+and the float64 diagonal and q sum.
 
 Modes
   fp32   -- operands rounded to IEEE binary32 (round to nearest even).
@@ -77,6 +79,30 @@ def _prod_bf16x3(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     return re + 1j * im
 
 
+def _pieces(x: np.ndarray, n: int):
+    return split_bf16(x) if n == 2 else split3_bf16(x)
+
+
+_PAIRS = {2: ((0, 0), (0, 1), (1, 0)), 3: ((0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0))}
+
+
+def _real_split_mm32(x: np.ndarray, y: np.ndarray, n: int) -> np.ndarray:
+    """sum over leading piece pairs of x_i @ y_j, each GEMM accumulated in float32."""
+    px = [p.astype(np.float32) for p in _pieces(x, n)]
+    py = [p.astype(np.float32) for p in _pieces(y, n)]
+    acc = np.zeros((x.shape[0], y.shape[1]), dtype=np.float32)
+    for i, j in _PAIRS[n]:
+        acc = acc + px[i] @ py[j]
+    return acc.astype(np.float64)
+
+
+def _prod_split32(a: np.ndarray, b: np.ndarray, n: int) -> np.ndarray:
+    """Complex a @ b as four real split products with float32 accumulation."""
+    re = _real_split_mm32(a.real, b.real, n) - _real_split_mm32(a.imag, b.imag, n)
+    im = _real_split_mm32(a.real, b.imag, n) + _real_split_mm32(a.imag, b.real, n)
+    return re + 1j * im
+
+
 def vx_k_emulated(m_blocks, L_list, w_q, mode: str) -> np.ndarray:
     """Emulated HERK-form V(k) for ``mode`` in {"fp64", "fp32", "bf16x3", "bf16x6"}.
 
@@ -92,14 +118,15 @@ def vx_k_emulated(m_blocks, L_list, w_q, mode: str) -> np.ndarray:
                 Y = Uh @ A
                 P = Y.conj().T @ Y
             elif mode == "fp32":
-                Y = round_fp32(round_fp32(Uh) @ round_fp32(A))
-                P = round_fp32(Y).conj().T @ round_fp32(Y)
+                Y = (Uh.astype(np.complex64) @ A.astype(np.complex64)).astype(np.complex128)
+                Y32 = Y.astype(np.complex64)
+                P = (Y32.conj().T @ Y32).astype(np.complex128)
             elif mode == "bf16x3":
-                Y = round_fp32(_prod_bf16x3(Uh, A))
-                P = _prod_bf16x3(Y.conj().T, Y)
+                Y = round_fp32(_prod_split32(Uh, A, 2))
+                P = _prod_split32(Y.conj().T, Y, 2)
             elif mode == "bf16x6":
-                Y = round_fp32(_prod_bf16x6(Uh, A))
-                P = _prod_bf16x6(Y.conj().T, Y)
+                Y = round_fp32(_prod_split32(Uh, A, 3))
+                P = _prod_split32(Y.conj().T, Y, 3)
             else:
                 raise ValueError(mode)
             d = np.sum(np.abs(Y) ** 2, axis=0)      # diagonal in float64 from the mode's Y

@@ -1,0 +1,226 @@
+"""Python binding of the MI355X nonlocal-exchange library (``libexchange.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI of ``include/exchange.h``. PyTorch provides device
+memory and streams. There is no fallback: if the shared library is missing or
+cannot be loaded, importing works but constructing :class:`Exchange` raises.
+
+Typical use::
+
+    ex = Exchange(n_bands, n_pw, ch_nrad, n_occ, E_list, D_list, C_list,
+                  precision="bf16x6", form="herk", batched=True)
+    V = ex.matrix_all([M_k0, M_k1, ...])      # list of n_b x n_b complex128 tensors
+    e = ex.energy()
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Exchange", "ExchangeError", "load_library", "LIB_PATH", "PRECISIONS", "FORMS",
+           "EXPORTED_SYMBOLS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libexchange.so")
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+FORMS = {"gemm": 0, "herk": 1}
+DTYPES = {"c128": 0, "c64": 1}
+STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
+          -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
+EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
+                    "exchange_last_error", "exchange_destroy", "exchange_query")
+
+
+class ExchangeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n_k", ctypes.c_int32), ("n_q", ctypes.c_int32), ("n_occ", ctypes.c_int32),
+                ("n_channels", ctypes.c_int32),
+                ("n_bands", ctypes.POINTER(ctypes.c_int32)), ("n_pw", ctypes.POINTER(ctypes.c_int32)),
+                ("ch_nrad", ctypes.POINTER(ctypes.c_int32)), ("w_q", ctypes.POINTER(ctypes.c_double)),
+                ("precision", ctypes.c_int32), ("form", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class _Coulomb(ctypes.Structure):
+    _fields_ = [("E", ctypes.POINTER(ctypes.c_void_p)), ("D", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libexchange.so`` and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ExchangeError(-6, f"{path} is not built; run `python -m paper_1003_0524_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.exchange_init.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Coulomb), vp, ctypes.POINTER(vp)]
+    lib.exchange_init.restype = i32
+    lib.exchange_matrix.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+    lib.exchange_matrix.restype = i32
+    lib.exchange_matrix_all.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
+    lib.exchange_matrix_all.restype = i32
+    lib.exchange_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.exchange_energy.restype = i32
+    lib.exchange_last_error.argtypes = [vp]
+    lib.exchange_last_error.restype = ctypes.c_char_p
+    lib.exchange_destroy.argtypes = [vp]
+    lib.exchange_destroy.restype = None
+    lib.exchange_query.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.exchange_query.restype = i32
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _i32(a):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Exchange:
+    """One prepared Coulomb matrix set + plans on one GPU (a ``exc_ctx``)."""
+
+    def __init__(self, n_bands: Sequence[int], n_pw: Sequence[int], ch_nrad: Sequence[int],
+                 n_occ: int, E: Sequence[np.ndarray], D: Sequence[np.ndarray], C: Sequence[np.ndarray],
+                 w_q: Optional[Sequence[float]] = None, precision: str = "fp64", form: str = "herk",
+                 batched: bool = True, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise ExchangeError(-5, "no GPU visible: the exchange library runs only on a HIP device")
+        self._torch = torch
+        self.lib = load_library()
+        self.device = device
+        self.n_k, self.n_q = len(n_bands), len(n_pw)
+        self.n_bands = [int(x) for x in n_bands]
+        self.n_occ = int(n_occ)
+        self.precision, self.form, self.batched = precision, form, bool(batched)
+        nb_arr, nb_p = _i32(n_bands)
+        pw_arr, pw_p = _i32(n_pw)
+        ch_arr, ch_p = _i32(ch_nrad if len(ch_nrad) else [0])
+        wq_arr = None
+        if w_q is not None:
+            wq_arr = np.ascontiguousarray(np.asarray(w_q, dtype=np.float64))
+        desc = _Desc(self.n_k, self.n_q, self.n_occ, len(ch_nrad), nb_p, pw_p,
+                     ch_p if len(ch_nrad) else None,
+                     wq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wq_arr is not None else None,
+                     PRECISIONS[precision], FORMS[form], 1 if batched else 0, device)
+        e_host = [np.ascontiguousarray(np.asarray(e, dtype=np.complex128).T) for e in E]  # column-major
+        e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.ctypes.data for e in e_host])
+        d_cat = np.concatenate([np.asarray(d, np.complex128).T.ravel() for d in D] + [np.zeros(0, np.complex128)])
+        c_cat = np.concatenate([np.asarray(c, np.complex128).ravel() for c in C] + [np.zeros(0, np.complex128)])
+        d_cat = np.ascontiguousarray(d_cat)
+        c_cat = np.ascontiguousarray(c_cat)
+        coul = _Coulomb(e_ptrs, d_cat.ctypes.data if d_cat.size else None,
+                        c_cat.ctypes.data if c_cat.size else None, 0)
+        torch.cuda.set_device(device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.exchange_init(ctypes.byref(desc), ctypes.byref(coul), _stream_handle(torch, device),
+                                    ctypes.byref(ctx))
+        if st != 0:
+            raise ExchangeError(st, self.lib.exchange_last_error(None).decode())
+        self.ctx = ctx
+        self._keep = (nb_arr, pw_arr, ch_arr, wq_arr)
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise ExchangeError(st, self.lib.exchange_last_error(self.ctx).decode())
+
+    def _dtype_code(self, M):
+        t = self._torch
+        if M.dtype == t.complex128:
+            return DTYPES["c128"]
+        if M.dtype == t.complex64:
+            return DTYPES["c64"]
+        raise ExchangeError(-1, f"M must be complex64 or complex128, got {M.dtype}")
+
+    def m_elems(self, k: int, n_mb: Sequence[int]) -> int:
+        return int(sum(self.n_occ * self.n_bands[k] * int(n) for n in n_mb))
+
+    # -- API ---------------------------------------------------------------
+    def matrix(self, k: int, M, out=None):
+        """V^x(k) (n_b x n_b complex128, column-major storage returned as its transpose view)."""
+        t = self._torch
+        nb = self.n_bands[k]
+        if out is None:
+            out = t.empty(nb * nb, dtype=t.complex128, device=M.device)
+        if not (M.is_cuda and M.is_contiguous() and out.is_cuda and out.is_contiguous()):
+            raise ExchangeError(-1, "M and out must be contiguous device tensors")
+        st = self.lib.exchange_matrix(self.ctx, int(k), ctypes.c_void_p(M.data_ptr()), self._dtype_code(M), 1,
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(t, self.device))
+        self._check(st)
+        return out.view(nb, nb).T      # column-major -> [n][n'] view
+
+    def matrix_all(self, Ms: Sequence, outs=None):
+        t = self._torch
+        if len(Ms) != self.n_k:
+            raise ExchangeError(-1, f"need {self.n_k} M tensors")
+        if outs is None:
+            outs = [t.empty(nb * nb, dtype=t.complex128, device=Ms[0].device) for nb in self.n_bands]
+        code = self._dtype_code(Ms[0])
+        for M in Ms:
+            if not (M.is_cuda and M.is_contiguous()) or self._dtype_code(M) != code:
+                raise ExchangeError(-1, "all M must be contiguous device tensors of one dtype")
+        mp = (ctypes.c_void_p * self.n_k)(*[M.data_ptr() for M in Ms])
+        vp = (ctypes.c_void_p * self.n_k)(*[o.data_ptr() for o in outs])
+        st = self.lib.exchange_matrix_all(self.ctx, mp, code, 1, vp, _stream_handle(t, self.device))
+        self._check(st)
+        return [o.view(nb, nb).T for o, nb in zip(outs, self.n_bands)]
+
+    def matrix_host(self, k: int, M: np.ndarray) -> np.ndarray:
+        """Host-pointer variant (copies in and out; synchronous)."""
+        nb = self.n_bands[k]
+        M = np.ascontiguousarray(M)
+        code = DTYPES["c64"] if M.dtype == np.complex64 else DTYPES["c128"]
+        if M.dtype not in (np.complex64, np.complex128):
+            raise ExchangeError(-1, "M must be complex64 or complex128")
+        out = np.empty(nb * nb, dtype=np.complex128)
+        st = self.lib.exchange_matrix(self.ctx, int(k), ctypes.c_void_p(M.ctypes.data), code, 0,
+                                      ctypes.c_void_p(out.ctypes.data), _stream_handle(self._torch, self.device))
+        self._check(st)
+        return out.reshape(nb, nb).T.copy()
+
+    def energy(self, w_k: Optional[Sequence[float]] = None, rho: Optional[Sequence] = None) -> float:
+        wk = None
+        if w_k is not None:
+            wk_arr = np.ascontiguousarray(np.asarray(w_k, dtype=np.float64))
+            wk = wk_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rp = None
+        if rho is not None:
+            rp = (ctypes.c_void_p * self.n_k)(*[r.data_ptr() for r in rho])
+        e = ctypes.c_double()
+        self._check(self.lib.exchange_energy(self.ctx, wk, rp, ctypes.byref(e)))
+        return e.value
+
+    def query(self, what: int) -> float:
+        v = ctypes.c_double()
+        self._check(self.lib.exchange_query(self.ctx, int(what), ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.exchange_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,405 @@
+// Auxiliary kernels: block-sparse rows, FP64 reduction, energy, Cholesky of
+// v(q) and preparation of the dense factor in the product mode's storage.
+#pragma once
+#include "common.hpp"
+#include "tile.hpp"
+
+namespace exc {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// ---------------------------------------------------------------------------
+// Block-sparse rows of the transformed mixed product basis (Fig. 1): each
+// multipole-free MT function couples only to the functions of its own
+// (atom, L, M) channel, i.e. to the other multipole-free functions of the
+// channel and to the channel's multipole function.
+//   HERK form: Y_c = L_c^H A_c + l_c a_{j(c)}   (rows of L^H A for v = L L^H)
+//   GEMM form: W_c = D_c A_c + C_c a_{j(c)},  X_c = C_c^H A_c (added to W row j(c))
+// One wavefront per column (k, q, n'', n): the kernel streams M once and
+// writes the sparse rows once, so it is bound by HBM bandwidth.
+// ---------------------------------------------------------------------------
+struct SparseArgs {
+  const PairInfo* pairs;
+  const void* const* mtab;
+  int32_t m_c64;
+  int32_t n_s, n_ch, n_occ, nb_max;
+  const int32_t* row_chan;   // [n_s] channel of each multipole-free row
+  const int32_t* ch_off;     // [n_ch] first multipole-free row of the channel
+  const int32_t* ch_len;     // [n_ch] nrad - 1
+  const int64_t* ch_coef;    // [n_ch] offset of the channel's square block in coef
+  const double2* coef;       // HERK: L_c (lower, col-major); GEMM: D_c (col-major)
+  const double2* cvec;       // [n_s] HERK: l_c = L_c^{-1} C_c; GEMM: C_c
+  void* ws;                  // output rows (double2 or float2)
+  double* dsp;               // HERK, reduced precision: sum_r |Y_s[r][n]|^2 per column
+};
+
+template <int FORM, int OUT64, int DIAG>
+__global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const PairInfo pi = a.pairs[blockIdx.y];
+  const int col = blockIdx.x * 4 + w;
+  if (col >= a.n_occ * pi.nb) return;       // the whole wavefront leaves together
+  const long mcol = pi.m_off + (long)col * pi.nmb;
+  const char* mb = (const char*)a.mtab[pi.k];
+  auto ldA = [&](int r) -> double2 {
+    if (a.m_c64) {
+      const float2 v = ((const float2*)mb)[mcol + r];
+      return make_double2(v.x, v.y);
+    }
+    return ((const double2*)mb)[mcol + r];
+  };
+  const long wcol = pi.ws_off + (long)col * pi.ldw;
+  double dsum = 0.0;
+  for (int r = lane; r < a.n_s; r += 64) {
+    const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
+    const double2* cf = a.coef + a.ch_coef[c];
+    double2 y = make_double2(0.0, 0.0);
+    if (FORM == 1) {
+      for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], ldA(s + j)));
+    } else {
+      for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], ldA(s + j)));
+    }
+    y = cadd(y, cmul(a.cvec[r], ldA(a.n_s + c)));
+    if (OUT64) ((double2*)a.ws)[wcol + r] = y;
+    else ((float2*)a.ws)[wcol + r] = make_float2((float)y.x, (float)y.y);
+    if (DIAG) dsum += y.x * y.x + y.y * y.y;
+  }
+  if (FORM == 0) {
+    for (int c = lane; c < a.n_ch; c += 64) {
+      const int s = a.ch_off[c], b = a.ch_len[c];
+      double2 x = make_double2(0.0, 0.0);
+      for (int j = 0; j < b; ++j) x = cadd(x, cmulc(a.cvec[s + j], ldA(s + j)));
+      ((double2*)a.ws)[wcol + a.n_s + c] = x;
+    }
+  }
+  if (DIAG) {
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
+    if (lane == 0) a.dsp[(long)blockIdx.y * a.n_occ * a.nb_max + col] = dsum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction of the item partials of each k:
+//   V(k) = - sum_{slots of k} w_q(slot) * (Gram tiles of the slot)
+// with the Hermitian mirror and Im V_nn = 0. In the reduced-precision HERK
+// modes the diagonal comes from the FP64 sums of |Y|^2.
+// ---------------------------------------------------------------------------
+struct ReduceArgs {
+  const int32_t* k_nb;         // [n_k]
+  const int32_t* slot_begin;   // [n_k + 1]
+  const double* slot_w;        // [n_slots]
+  const void* gpart;
+  int32_t gstride, acc64;
+  const double* dpart;
+  int32_t dstride, use_d64;
+  const int32_t* pair_begin;   // [n_k + 1]
+  const double* pair_w;        // [n_pairs]
+  const double* dsp;
+  int32_t dsp_stride;          // n_occ * nb_max
+  int32_t n_occ;
+  double2* vres;
+  const int64_t* v_off;        // [n_k]
+  void* const* vout;           // [n_k] device pointers or nullptr
+};
+
+// Position of G[row][col] of Gram tile tp in a partial slot written as
+// [tile][element i][lane] (see acc_row for the two accumulator layouts).
+template <int ACC64>
+__device__ __forceinline__ int gidx(int tp, int row, int col) {
+  return ACC64 ? (tp * 4 + (row >> 2)) * 64 + col + 16 * (row & 3)
+               : (tp * 4 + (row & 3)) * 64 + col + 16 * (row >> 2);
+}
+
+template <int ACC64>
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+  const int k = blockIdx.y;
+  const int nb = a.k_nb[k];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int n = e % nb, n2 = e / nb;
+  if (n2 >= nb || n > n2) return;
+  const int I = n >> 3, J = n2 >> 3, c = n & 7, c2 = n2 & 7;
+  const int tp = J * (J + 1) / 2 + I;
+  const int irr = gidx<ACC64>(tp, c, c2), iii = gidx<ACC64>(tp, c + 8, c2 + 8);
+  const int iri = gidx<ACC64>(tp, c, c2 + 8), iir = gidx<ACC64>(tp, c + 8, c2);
+  double re = 0.0, im = 0.0;
+  for (int s = a.slot_begin[k]; s < a.slot_begin[k + 1]; ++s) {
+    const double wq = a.slot_w[s];
+    double grr, gii, gri, gir;
+    if (ACC64) {
+      const double* g = (const double*)a.gpart + (long)s * a.gstride;
+      grr = g[irr]; gii = g[iii]; gri = g[iri]; gir = g[iir];
+    } else {
+      const float* g = (const float*)a.gpart + (long)s * a.gstride;
+      grr = g[irr]; gii = g[iii]; gri = g[iri]; gir = g[iir];
+    }
+    re += wq * (grr + gii);
+    im += wq * (gri - gir);
+  }
+  if (n == n2) {
+    im = 0.0;
+    if (a.use_d64) {
+      re = 0.0;
+      for (int s = a.slot_begin[k]; s < a.slot_begin[k + 1]; ++s)
+        re += a.slot_w[s] * a.dpart[(long)s * a.dstride + n];
+      for (int p = a.pair_begin[k]; p < a.pair_begin[k + 1]; ++p) {
+        double t = 0.0;
+        for (int j = 0; j < a.n_occ; ++j) t += a.dsp[(long)p * a.dsp_stride + (long)j * nb + n];
+        re += a.pair_w[p] * t;
+      }
+    }
+  }
+  const double2 v = make_double2(-re, -im);
+  double2* V = a.vres + a.v_off[k];
+  V[n + (long)n2 * nb] = v;
+  if (n != n2) V[n2 + (long)n * nb] = make_double2(-re, im);
+  if (a.vout && a.vout[k]) {
+    double2* O = (double2*)a.vout[k];
+    O[n + (long)n2 * nb] = v;
+    if (n != n2) O[n2 + (long)n * nb] = make_double2(-re, im);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Energy: per k, Tr(rho_k V_k) (or 2 sum_{n < n_occ} V_nn for rho = 2 P_occ),
+// reduced in a fixed order; the host applies 1/2 sum_k w_k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void energy_kernel(const double2* vres, const int64_t* v_off,
+                                                     const int32_t* k_nb, const void* const* rho,
+                                                     int32_t n_occ, double* out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, nb = k_nb[k];
+  const double2* V = vres + v_off[k];
+  double s = 0.0;
+  const double2* R = rho ? (const double2*)rho[k] : nullptr;
+  if (R) {
+    for (long e = threadIdx.x; e < (long)nb * nb; e += 256) {
+      const int n = (int)(e % nb), n2 = (int)(e / nb);
+      const double2 r = R[e];                      // rho[n][n2]
+      const double2 v = V[n2 + (long)n * nb];      // V[n2][n]
+      s += r.x * v.x - r.y * v.y;
+    }
+  } else {
+    for (int n = threadIdx.x; n < n_occ && n < nb; n += 256) s += 2.0 * V[n + (long)n * nb].x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Per-channel factorisation (HERK form, q independent): D_c = L_c L_c^H,
+// l_c = L_c^{-1} C_c and the Schur update ||l_c||^2 of the channel's multipole
+// diagonal entry. With one multipole function per channel the Schur
+// complement E - C^H D^{-1} C changes only those diagonal entries.
+// ---------------------------------------------------------------------------
+__global__ void chan_chol_kernel(int n_ch, const int32_t* ch_off, const int32_t* ch_len,
+                                 const int64_t* ch_coef, double2* L, double2* lvec,
+                                 double* schur, int* info) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_ch) return;
+  const int b = ch_len[c], s = ch_off[c];
+  double2* A = L + ch_coef[c];
+  for (int j = 0; j < b; ++j) {
+    double d = A[j + (long)j * b].x;
+    for (int p = 0; p < j; ++p) {
+      const double2 x = A[j + (long)p * b];
+      d -= x.x * x.x + x.y * x.y;
+    }
+    if (!(d > 0.0)) { atomicMax(info, 1); d = 1.0; }
+    d = sqrt(d);
+    A[j + (long)j * b] = make_double2(d, 0.0);
+    for (int i = j + 1; i < b; ++i) {
+      double2 t = A[i + (long)j * b];
+      for (int p = 0; p < j; ++p) {
+        const double2 u = cmul(A[i + (long)p * b], make_double2(A[j + (long)p * b].x, -A[j + (long)p * b].y));
+        t.x -= u.x; t.y -= u.y;
+      }
+      A[i + (long)j * b] = make_double2(t.x / d, t.y / d);
+    }
+    for (int i = 0; i < j; ++i) A[i + (long)j * b] = make_double2(0.0, 0.0);
+  }
+  double sc = 0.0;
+  for (int i = 0; i < b; ++i) {
+    double2 t = lvec[s + i];
+    for (int p = 0; p < i; ++p) {
+      const double2 u = cmul(A[i + (long)p * b], lvec[s + p]);
+      t.x -= u.x; t.y -= u.y;
+    }
+    const double d = A[i + (long)i * b].x;
+    t = make_double2(t.x / d, t.y / d);
+    lvec[s + i] = t;
+    sc += t.x * t.x + t.y * t.y;
+  }
+  schur[c] = sc;
+}
+
+// ---------------------------------------------------------------------------
+// Dense Cholesky of the (Schur-updated) block E(q) = L22 L22^H, FP64, one
+// workgroup per q, left-looking with 16-column panels.
+// ---------------------------------------------------------------------------
+struct CholArgs {
+  double2* A;             // per-q matrices (column-major, leading dimension lda)
+  const int64_t* a_off;
+  const int32_t* nd;
+  const int32_t* lda;
+  int32_t n_ch;
+  const double* schur;    // [n_ch] or nullptr
+  int* info;              // [n_q] first failing pivot (1-based), 0 = ok
+};
+
+__global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
+  constexpr int NB = 16, PC = 32;
+  __shared__ double2 Lp[NB][PC + 1];
+  __shared__ double2 Ld[NB][NB + 1];
+  __shared__ int s_fail;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int n = a.nd[q], lda = a.lda[q];
+  double2* A = a.A + a.a_off[q];
+  if (tid == 0) s_fail = 0;
+  if (a.schur)
+    for (int c = tid; c < a.n_ch && c < n; c += 256) A[c + (long)c * lda].x -= a.schur[c];
+  __syncthreads();
+  for (int jb = 0; jb < n; jb += NB) {
+    const int nbk = min(NB, n - jb);
+    // panel update: A[i][jb+jj] -= sum_{p<jb} A[i][p] conj(A[jb+jj][p]),  i >= jb
+    for (int i0 = jb; i0 < n; i0 += 256) {
+      const int i = i0 + tid;
+      double2 acc[NB];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) acc[jj] = make_double2(0.0, 0.0);
+      for (int p0 = 0; p0 < jb; p0 += PC) {
+        __syncthreads();
+        for (int e = tid; e < NB * PC; e += 256) {
+          const int jj = e / PC, pp = e % PC;
+          Lp[jj][pp] = (jj < nbk && p0 + pp < jb) ? A[(jb + jj) + (long)(p0 + pp) * lda] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (i < n) {
+          const int pe = min(PC, jb - p0);
+          for (int pp = 0; pp < pe; ++pp) {
+            const double2 x = A[i + (long)(p0 + pp) * lda];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+              const double2 y = Lp[jj][pp];
+              acc[jj].x += x.x * y.x + x.y * y.y;
+              acc[jj].y += x.y * y.x - x.x * y.y;
+            }
+          }
+        }
+      }
+      if (i < n) {
+        for (int jj = 0; jj < nbk; ++jj) {
+          double2* t = &A[i + (long)(jb + jj) * lda];
+          t->x -= acc[jj].x; t->y -= acc[jj].y;
+        }
+      }
+    }
+    __syncthreads();
+    // factor the diagonal block in LDS
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e % NB, cc = e / NB;
+      Ld[r][cc] = (r < nbk && cc < nbk) ? A[(jb + r) + (long)(jb + cc) * lda] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int j = 0; j < nbk; ++j) {
+        double d = Ld[j][j].x;
+        for (int p = 0; p < j; ++p) d -= Ld[j][p].x * Ld[j][p].x + Ld[j][p].y * Ld[j][p].y;
+        if (!(d > 0.0)) { if (!s_fail) s_fail = jb + j + 1; d = 1.0; }
+        d = sqrt(d);
+        Ld[j][j] = make_double2(d, 0.0);
+        for (int i = j + 1; i < nbk; ++i) {
+          double2 t = Ld[i][j];
+          for (int p = 0; p < j; ++p) {
+            t.x -= Ld[i][p].x * Ld[j][p].x + Ld[i][p].y * Ld[j][p].y;
+            t.y -= Ld[i][p].y * Ld[j][p].x - Ld[i][p].x * Ld[j][p].y;
+          }
+          Ld[i][j] = make_double2(t.x / d, t.y / d);
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nbk * nbk; e += 256) {
+      const int r = e % nbk, cc = e / nbk;
+      if (r >= cc) A[(jb + r) + (long)(jb + cc) * lda] = Ld[r][cc];
+    }
+    // rows below: x Ld^H = a  ->  x_j = (a_j - sum_{m<j} x_m conj(Ld[j][m])) / Ld[j][j]
+    for (int i = jb + nbk + tid; i < n; i += 256) {
+      double2 x[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) x[j] = j < nbk ? A[i + (long)(jb + j) * lda] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nbk) {
+          double2 t = x[j];
+#pragma unroll
+          for (int m = 0; m < NB; ++m) {
+            if (m < j) {
+              t.x -= x[m].x * Ld[j][m].x + x[m].y * Ld[j][m].y;
+              t.y -= x[m].y * Ld[j][m].x - x[m].x * Ld[j][m].y;
+            }
+          }
+          const double d = Ld[j][j].x;
+          x[j] = make_double2(t.x / d, t.y / d);
+        }
+      }
+      for (int j = 0; j < nbk; ++j) A[i + (long)(jb + j) * lda] = x[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) a.info[q] = s_fail;
+}
+
+// ---------------------------------------------------------------------------
+// Write the dense factor of q into the tile kernel's planes:
+//   HERK: B[r][c] = conj(L22[c][r]) for c >= r (upper triangular L22^H)
+//   GEMM: B[r][c] = E[r][c]
+// planes [re pieces..., im pieces...], each ldu x ldu row-major, zero padded.
+// ---------------------------------------------------------------------------
+template <int MODE, int FORM>
+__global__ __launch_bounds__(256) void prep_factor_kernel(const double2* src, const int64_t* s_off,
+                                                          const int32_t* nd, const int32_t* lds,
+                                                          void* dst, const int64_t* d_off,
+                                                          const int32_t* ldu) {
+  using lds_t = typename Traits<MODE>::lds_t;
+  constexpr int NP = Traits<MODE>::NPIECE;
+  const int q = blockIdx.y;
+  const int n = nd[q], ld = ldu[q], ls = lds[q];
+  const long plane = (long)ld * ld;
+  lds_t* D = (lds_t*)dst + d_off[q];
+  const double2* S = src + s_off[q];
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < plane; e += (long)gridDim.x * 256) {
+    const int r = (int)(e / ld), c = (int)(e % ld);
+    double re = 0.0, im = 0.0;
+    if (r < n && c < n) {
+      if (FORM == 1) {
+        if (c >= r) {
+          const double2 v = S[c + (long)r * ls];
+          re = v.x; im = -v.y;
+        }
+      } else {
+        const double2 v = S[r + (long)c * ls];
+        re = v.x; im = v.y;
+      }
+    }
+    put_real<MODE>(D + e, plane, re);
+    put_real<MODE>(D + NP * plane + e, plane, im);
+  }
+}
+
+__global__ void zero_int_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace exc

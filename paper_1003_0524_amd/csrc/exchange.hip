@@ -1,0 +1,817 @@
+// C ABI and host runtime of the MI355X nonlocal-exchange library.
+//
+// Computes V^x_{nn'}(k) = - sum_q w_q sum_{n''} A^H v(q) A (the vector-matrix-
+// vector form of Sec. II.C) on one gfx950 GPU. See include/exchange.h for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/exchange.h"
+#include "aux.hpp"
+#include "tile.hpp"
+
+using namespace exc;
+
+namespace {
+
+constexpr uint32_t kAlive = 0x45584331u;   // "EXC1"
+thread_local std::string g_init_err;
+
+struct KernelCfg {
+  int mode, form, BM, KC, NCT, NB8M;
+  void (*fn)(TileArgs);
+  size_t lds;
+  int id;
+};
+
+#define CFG(MODE, FORM, BM, KC, NCT, NB8M, ID)                                              \
+  KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, tile_kernel<MODE, FORM, BM, KC, NCT, NB8M>,         \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M>::LDS_B, ID}
+
+// The GEMM form stages two FP64 operands per n'' value and therefore stops at
+// n_b <= 64 (band-tile count 8) within the 160 KB of LDS.
+// Tile shapes: BM rows of the factor per step, KC complex k per LDS stage, NCT
+// 8-column band tiles per pass (n_b rounded to 8, times the n'' chunk), NB8M
+// the largest band-tile count per n'' value the instance contracts.
+const KernelCfg kCfgs[] = {
+    CFG(M_F64, 0, 64, 16, 6, 3, 0),    CFG(M_F64, 0, 64, 16, 8, 8, 1),
+    CFG(M_F64, 1, 64, 16, 12, 3, 10),  CFG(M_F64, 1, 64, 16, 8, 8, 11),
+    CFG(M_F64, 1, 64, 16, 16, 16, 12),
+    CFG(M_F32, 1, 128, 16, 12, 3, 20), CFG(M_F32, 1, 128, 16, 16, 8, 21),
+    CFG(M_F32, 1, 64, 16, 16, 16, 22),
+    CFG(M_BF16X3, 1, 128, 32, 12, 3, 30), CFG(M_BF16X3, 1, 128, 32, 16, 8, 31),
+    CFG(M_BF16X3, 1, 64, 32, 16, 16, 32),
+    CFG(M_BF16X6, 1, 128, 32, 12, 3, 40), CFG(M_BF16X6, 1, 128, 32, 16, 8, 41),
+    CFG(M_BF16X6, 1, 64, 32, 16, 16, 42),
+};
+
+struct Plan {
+  std::vector<WorkItem> items;      // generation order: pair-major, slot = index
+  std::vector<int> pair_item;       // [n_pairs + 1] item range per pair
+  std::vector<int> k_item;          // [n_k + 1] item range per k
+  std::vector<int> slot_begin;      // [n_k + 1]
+  std::vector<double> slot_w;
+  WorkItem* d_items = nullptr;      // generation order
+  WorkItem* d_items_lpt = nullptr;  // longest-processing-time order
+  int32_t* d_slot_begin = nullptr;
+  double* d_slot_w = nullptr;
+  int n_slots = 0;
+};
+
+}  // namespace
+
+struct exc_ctx {
+  uint32_t magic = kAlive;
+  std::string err;
+  int n_k = 0, n_q = 0, n_occ = 0, n_ch = 0, precision = 0, form = 0, batched = 0, device = 0;
+  std::vector<int> nb, npw, nrad, nd, nmb;
+  std::vector<double> wq;
+  int n_s = 0, nb_max = 0, nbt_max = 0;
+  std::vector<int> ch_off, ch_len;
+  std::vector<int64_t> ch_coef;
+  int64_t coef_total = 0;
+  // device-resident Coulomb data
+  double2* d_coef = nullptr;
+  double2* d_cvec = nullptr;
+  double* d_schur = nullptr;
+  void* d_U = nullptr;
+  std::vector<int64_t> u_off;
+  std::vector<int> ldu;
+  int32_t *d_row_chan = nullptr, *d_ch_off = nullptr, *d_ch_len = nullptr;
+  int64_t* d_ch_coef = nullptr;
+  // pairs, plans, buffers
+  std::vector<PairInfo> pairs;
+  PairInfo* d_pairs = nullptr;
+  std::vector<int> k_pair;            // [n_k + 1]
+  std::vector<double> pair_w;
+  double* d_pair_w = nullptr;
+  int32_t* d_pair_begin = nullptr;
+  Plan plain, bat;
+  const KernelCfg* cfg = nullptr;
+  void* d_ws = nullptr;
+  double* d_dsp = nullptr;
+  void* d_gpart = nullptr;
+  double* d_dpart = nullptr;
+  int gstride = 0, dstride = 0;
+  double2* d_vres = nullptr;
+  std::vector<int64_t> v_off;
+  int64_t* d_voff = nullptr;
+  int32_t* d_knb = nullptr;
+  std::vector<char> v_valid;
+  // pointer tables (device) and their host mirrors
+  void** d_mtab = nullptr;
+  void** d_vtab = nullptr;
+  std::vector<void*> h_mtab, h_vtab;
+  int32_t* d_counter = nullptr;
+  int persist_grid = 0;
+  // graph of the batched path
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t own = nullptr;          // capturable stream of the batched path
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int g_dtype = -1;
+  // staging for host-pointer calls
+  void* d_mstage = nullptr;
+  size_t mstage_bytes = 0;
+  double* d_eout = nullptr;
+  hipStream_t last_stream = nullptr;
+  // accounting
+  double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
+};
+
+namespace {
+
+exc_status fail(exc_ctx* c, exc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_init_err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                                       \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(ctx, EXC_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                    \
+  } while (0)
+
+template <class T>
+exc_status dalloc(exc_ctx* c, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return fail(c, EXC_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
+  }
+  return EXC_OK;
+}
+#define TRY(x)                      \
+  do {                              \
+    exc_status s_ = (x);            \
+    if (s_ != EXC_OK) return s_;    \
+  } while (0)
+
+template <class T>
+exc_status upload(exc_ctx* c, T** d, const std::vector<T>& h) {
+  TRY(dalloc(c, d, h.size()));
+  if (!h.empty()) HIPCHK(c, hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return EXC_OK;
+}
+
+size_t lds_elem_size(int mode) { return mode == M_F64 ? 8 : (mode == M_F32 ? 4 : 2); }
+int npieces(int mode) { return mode == M_BF16X3 ? 2 : (mode == M_BF16X6 ? 3 : 1); }
+
+void free_plan(Plan& p) {
+  hipFree(p.d_items); hipFree(p.d_items_lpt); hipFree(p.d_slot_begin); hipFree(p.d_slot_w);
+  p.d_items = p.d_items_lpt = nullptr; p.d_slot_begin = nullptr; p.d_slot_w = nullptr;
+}
+
+void release(exc_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  if (c->ev_in) hipEventDestroy(c->ev_in);
+  if (c->ev_out) hipEventDestroy(c->ev_out);
+  if (c->own) hipStreamDestroy(c->own);
+  c->ev_in = c->ev_out = nullptr;
+  c->own = nullptr;
+  void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
+                  c->d_ch_len, c->d_ch_coef, c->d_pairs, c->d_pair_w, c->d_pair_begin,
+                  c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
+                  c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout};
+  for (void* p : ptrs) if (p) hipFree(p);
+  free_plan(c->plain);
+  free_plan(c->bat);
+}
+
+// Relative cost of one row block (for balancing and LPT order).
+double block_cost(const exc_ctx* c, const PairInfo& p, int rb, int ncols) {
+  const int BM = c->cfg->BM;
+  const double contract = (double)BM * p.nb8 * p.nb8;      // Gram tiles
+  if (rb < p.nsb) return contract + (double)BM * ncols;
+  const int d0 = (rb - p.nsb) * BM;
+  const double k = c->form == EXC_FORM_CHOL_HERK ? (double)(p.nd - d0) + c->cfg->KC : (double)p.nd;
+  return contract + 2.0 * BM * ncols * k;
+}
+
+// Build work items. split_rows: 0 = one item covers all row blocks of the pair
+// (n'' chunks looped inside), 1 = one item per (n'' chunk, row block).
+exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
+  P.items.clear();
+  P.pair_item.assign(1, 0);
+  P.k_item.assign(1, 0);
+  P.slot_begin.assign(1, 0);
+  P.slot_w.clear();
+  const int nct = c->cfg->NCT;
+  std::vector<double> cost;
+  for (int k = 0; k < c->n_k; ++k) {
+    for (int pidx = c->k_pair[k]; pidx < c->k_pair[k + 1]; ++pidx) {
+      const PairInfo& p = c->pairs[pidx];
+      const int nbt = p.nb8 / 8;
+      const int ngc = std::max(1, std::min(c->n_occ, nct / nbt));
+      const int nrb = p.nsb + p.ndb;
+      auto push = [&](int g0, int g1, int rb0, int rb1) {
+        WorkItem w{};
+        w.pair = pidx; w.g0 = g0; w.g1 = g1; w.ngc = ngc; w.rb0 = rb0; w.rb1 = rb1;
+        w.slot = (int)P.items.size();
+        double cs = 0;
+        for (int g = g0; g < g1; g += ngc)
+          for (int rb = rb0; rb < rb1; ++rb) cs += block_cost(c, p, rb, std::min(ngc, g1 - g) * p.nb8);
+        P.items.push_back(w);
+        P.slot_w.push_back(c->wq[p.q]);
+        cost.push_back(cs);
+      };
+      if (!split_rows) {
+        push(0, c->n_occ, 0, nrb);
+      } else {
+        for (int g = 0; g < c->n_occ; g += ngc)
+          for (int rb = 0; rb < nrb; ++rb) push(g, std::min(c->n_occ, g + ngc), rb, rb + 1);
+      }
+      P.pair_item.push_back((int)P.items.size());
+    }
+    P.k_item.push_back((int)P.items.size());
+    P.slot_begin.push_back((int)P.items.size());
+  }
+  P.n_slots = (int)P.items.size();
+  std::vector<WorkItem> lpt(P.items);
+  std::vector<int> order(P.items.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (size_t i = 0; i < order.size(); ++i) lpt[i] = P.items[order[i]];
+  TRY(upload(c, &P.d_items, P.items));
+  TRY(upload(c, &P.d_items_lpt, lpt));
+  std::vector<int32_t> sb(P.slot_begin.begin(), P.slot_begin.end());
+  TRY(upload(c, &P.d_slot_begin, sb));
+  TRY(upload(c, &P.d_slot_w, P.slot_w));
+  return EXC_OK;
+}
+
+const KernelCfg* pick_cfg(int mode, int form, int nbt_max) {
+  const KernelCfg* best = nullptr;
+  for (const auto& k : kCfgs) {
+    if (k.mode != mode || k.form != form || k.NB8M < nbt_max || k.NCT < nbt_max) continue;
+    if (!best || k.NB8M < best->NB8M) best = &k;
+  }
+  return best;
+}
+
+exc_status set_tables(exc_ctx* c, int k0, int nk, const void* const* M, void* const* V,
+                      hipStream_t st) {
+  bool changed = false;
+  for (int i = 0; i < nk; ++i) {
+    if (c->h_mtab[k0 + i] != M[i] || c->h_vtab[k0 + i] != V[i]) changed = true;
+    c->h_mtab[k0 + i] = const_cast<void*>(M[i]);
+    c->h_vtab[k0 + i] = V[i];
+  }
+  if (changed) {
+    HIPCHK(c, hipMemcpyAsync(c->d_mtab + k0, c->h_mtab.data() + k0, nk * sizeof(void*),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->d_vtab + k0, c->h_vtab.data() + k0, nk * sizeof(void*),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));   // the host mirrors may change on the next call
+  }
+  return EXC_OK;
+}
+
+TileArgs tile_args(exc_ctx* c, int dtype) {
+  TileArgs a{};
+  a.pairs = c->d_pairs;
+  a.mtab = (const void* const*)c->d_mtab;
+  a.m_c64 = dtype == EXC_C64;
+  a.n_s = c->n_s;
+  a.n_ch = c->n_ch;
+  a.U = c->d_U;
+  a.ws = c->d_ws;
+  a.gpart = c->d_gpart;
+  a.dpart = c->d_dpart;
+  a.gstride = c->gstride;
+  a.dstride = c->dstride;
+  return a;
+}
+
+SparseArgs sparse_args(exc_ctx* c, int dtype) {
+  SparseArgs s{};
+  s.pairs = c->d_pairs;
+  s.mtab = (const void* const*)c->d_mtab;
+  s.m_c64 = dtype == EXC_C64;
+  s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max;
+  s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
+  s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
+  s.ws = c->d_ws; s.dsp = c->d_dsp;
+  return s;
+}
+
+void launch_sparse(exc_ctx* c, int dtype, int pair0, int npairs, hipStream_t st) {
+  if (c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return;
+  SparseArgs s = sparse_args(c, dtype);
+  s.pairs = c->d_pairs + pair0;
+  // dsp is indexed by blockIdx.y: offset it to the first pair
+  s.dsp = c->d_dsp ? c->d_dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
+  dim3 grid((c->n_occ * c->nb_max + 3) / 4, npairs);
+  const bool herk = c->form == EXC_FORM_CHOL_HERK;
+  const bool f64 = c->precision == EXC_FP64;
+  if (!herk) hipLaunchKernelGGL((sparse_kernel<0, 1, 0>), grid, dim3(256), 0, st, s);
+  else if (f64) hipLaunchKernelGGL((sparse_kernel<1, 1, 0>), grid, dim3(256), 0, st, s);
+  else hipLaunchKernelGGL((sparse_kernel<1, 0, 1>), grid, dim3(256), 0, st, s);
+}
+
+void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
+  ReduceArgs r{};
+  r.k_nb = c->d_knb + k0;
+  r.slot_begin = P.d_slot_begin + k0;
+  r.slot_w = P.d_slot_w;
+  r.gpart = c->d_gpart;
+  r.gstride = c->gstride;
+  r.acc64 = c->precision == EXC_FP64;
+  r.dpart = c->d_dpart;
+  r.dstride = c->dstride;
+  r.use_d64 = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
+  r.pair_begin = c->d_pair_begin + k0;
+  r.pair_w = c->d_pair_w;
+  r.dsp = c->d_dsp;
+  r.dsp_stride = c->n_occ * c->nb_max;
+  r.n_occ = c->n_occ;
+  r.vres = c->d_vres;
+  r.v_off = c->d_voff + k0;
+  r.vout = c->d_vtab + k0;
+  dim3 grid((c->nb_max * c->nb_max + 255) / 256, nk);
+  if (r.acc64) hipLaunchKernelGGL((reduce_kernel<1>), grid, dim3(256), 0, st, r);
+  else hipLaunchKernelGGL((reduce_kernel<0>), grid, dim3(256), 0, st, r);
+}
+
+void launch_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  TileArgs a = tile_args(c, dtype);
+  a.items = items;
+  a.n_items = n;
+  a.counter = persistent ? c->d_counter : nullptr;
+  const int grid = persistent ? std::min(n, c->persist_grid) : n;
+  if (persistent) hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, st, c->d_counter, 1);
+  hipLaunchKernelGGL(c->cfg->fn, dim3(grid), dim3(256), 0, st, a);
+}
+
+// One k, batched over its q: sparse rows of all pairs of k, one tile launch, reduce.
+void run_k_batched(exc_ctx* c, int k, int dtype, hipStream_t st) {
+  const int p0 = c->k_pair[k], p1 = c->k_pair[k + 1];
+  launch_sparse(c, dtype, p0, p1 - p0, st);
+  const Plan& P = c->bat;
+  launch_tile(c, dtype, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], false, st);
+  launch_reduce(c, P, k, 1, st);
+}
+
+// One k, plain form: one launch of each kernel per (k, q) pair.
+void run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
+  const Plan& P = c->plain;
+  for (int p = c->k_pair[k]; p < c->k_pair[k + 1]; ++p) {
+    launch_sparse(c, dtype, p, 1, st);
+    launch_tile(c, dtype, P.d_items + P.pair_item[p], P.pair_item[p + 1] - P.pair_item[p], false, st);
+  }
+  launch_reduce(c, P, k, 1, st);
+}
+
+void run_all_batched_body(exc_ctx* c, int dtype, hipStream_t st) {
+  launch_sparse(c, dtype, 0, (int)c->pairs.size(), st);
+  launch_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, st);
+  launch_reduce(c, c->bat, 0, c->n_k, st);
+}
+
+exc_status check_ctx(const exc_ctx* c) {
+  if (!c) return EXC_EINVAL;
+  if (c->magic != kAlive) return EXC_ESTATE;
+  return EXC_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream, exc_ctx** out) {
+  if (!out) return fail(nullptr, EXC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d || !cv) return fail(nullptr, EXC_EINVAL, "desc or coulomb is NULL");
+  if (d->n_k < 1 || d->n_q < 1 || d->n_occ < 1 || d->n_channels < 0)
+    return fail(nullptr, EXC_EINVAL, "n_k, n_q, n_occ must be >= 1 and n_channels >= 0");
+  if (!d->n_bands || !d->n_pw || (d->n_channels > 0 && !d->ch_nrad))
+    return fail(nullptr, EXC_EINVAL, "n_bands, n_pw or ch_nrad is NULL");
+  if (d->precision < EXC_FP64 || d->precision > EXC_BF16X6)
+    return fail(nullptr, EXC_EINVAL, "bad precision %d", d->precision);
+  if (d->form != EXC_FORM_GEMM && d->form != EXC_FORM_CHOL_HERK)
+    return fail(nullptr, EXC_EINVAL, "bad form %d", d->form);
+  if (d->form == EXC_FORM_GEMM && d->precision != EXC_FP64)
+    return fail(nullptr, EXC_EUNSUPPORTED, "the GEMM form runs in FP64 only");
+  if (!cv->E) return fail(nullptr, EXC_EINVAL, "coulomb.E is NULL");
+  for (int k = 0; k < d->n_k; ++k)
+    if (d->n_bands[k] < 1 || d->n_bands[k] > 128)
+      return fail(nullptr, d->n_bands[k] < 1 ? EXC_EINVAL : EXC_EUNSUPPORTED,
+                  "n_bands[%d] = %d outside [1, 128]", k, d->n_bands[k]);
+  for (int q = 0; q < d->n_q; ++q)
+    if (d->n_pw[q] < 0) return fail(nullptr, EXC_EINVAL, "n_pw[%d] < 0", q);
+  for (int c = 0; c < d->n_channels; ++c)
+    if (d->ch_nrad[c] < 1) return fail(nullptr, EXC_EINVAL, "ch_nrad[%d] < 1", c);
+  if (d->w_q)
+    for (int q = 0; q < d->n_q; ++q)
+      if (!std::isfinite(d->w_q[q])) return fail(nullptr, EXC_EINVAL, "w_q[%d] not finite", q);
+
+  exc_ctx* c = new (std::nothrow) exc_ctx();
+  if (!c) return fail(nullptr, EXC_ENOMEM, "host allocation failed");
+  auto bail = [&](exc_status st) {
+    g_init_err = c->err;
+    release(c);
+    c->magic = 0;
+    delete c;
+    return st;
+  };
+#define ITRY(x)                       \
+  do {                                \
+    exc_status s_ = (x);              \
+    if (s_ != EXC_OK) return bail(s_); \
+  } while (0)
+#define IHIP(call)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      fail(c, EXC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                     \
+      return bail(EXC_EHIP);                                                                \
+    }                                                                                       \
+  } while (0)
+
+  c->n_k = d->n_k; c->n_q = d->n_q; c->n_occ = d->n_occ; c->n_ch = d->n_channels;
+  c->precision = d->precision; c->form = d->form; c->batched = d->batched; c->device = d->device;
+  c->nb.assign(d->n_bands, d->n_bands + d->n_k);
+  c->npw.assign(d->n_pw, d->n_pw + d->n_q);
+  if (c->n_ch) c->nrad.assign(d->ch_nrad, d->ch_nrad + c->n_ch);
+  c->wq.resize(c->n_q);
+  for (int q = 0; q < c->n_q; ++q) c->wq[q] = d->w_q ? d->w_q[q] : 1.0 / c->n_q;
+
+  IHIP(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+
+  // ---- channel layout (sparse rows) ----
+  c->ch_off.resize(c->n_ch); c->ch_len.resize(c->n_ch); c->ch_coef.resize(c->n_ch);
+  std::vector<int32_t> row_chan;
+  for (int ch = 0; ch < c->n_ch; ++ch) {
+    c->ch_off[ch] = c->n_s;
+    c->ch_len[ch] = c->nrad[ch] - 1;
+    c->ch_coef[ch] = c->coef_total;
+    c->coef_total += (int64_t)c->ch_len[ch] * c->ch_len[ch];
+    for (int i = 0; i < c->ch_len[ch]; ++i) row_chan.push_back(ch);
+    c->n_s += c->ch_len[ch];
+  }
+  c->nb_max = *std::max_element(c->nb.begin(), c->nb.end());
+  c->nbt_max = (c->nb_max + 7) / 8;
+  c->cfg = pick_cfg(c->precision, c->form, c->nbt_max);
+  if (!c->cfg) { fail(c, EXC_EUNSUPPORTED, "no tile configuration for n_b = %d", c->nb_max); return bail(EXC_EUNSUPPORTED); }
+  const int BM = c->cfg->BM;
+
+  c->nd.resize(c->n_q); c->nmb.resize(c->n_q); c->ldu.resize(c->n_q); c->u_off.resize(c->n_q);
+  const int npl = 2 * npieces(c->precision);
+  int64_t u_total = 0;
+  for (int q = 0; q < c->n_q; ++q) {
+    c->nd[q] = c->n_ch + c->npw[q];
+    c->nmb[q] = c->n_s + c->nd[q];
+    c->ldu[q] = std::max(128, (c->nd[q] + 127) / 128 * 128);
+    c->u_off[q] = u_total;
+    u_total += (int64_t)npl * c->ldu[q] * c->ldu[q];
+  }
+
+  // ---- Coulomb blocks to the device ----
+  {
+    const hipMemcpyKind kind = cv->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    ITRY(dalloc(c, &c->d_coef, (size_t)c->coef_total));
+    ITRY(dalloc(c, &c->d_cvec, (size_t)c->n_s));
+    if (c->coef_total) {
+      if (!cv->D) { fail(c, EXC_EINVAL, "coulomb.D is NULL"); return bail(EXC_EINVAL); }
+      IHIP(hipMemcpy(c->d_coef, cv->D, c->coef_total * 16, kind));
+    }
+    if (c->n_s) {
+      if (!cv->C) { fail(c, EXC_EINVAL, "coulomb.C is NULL"); return bail(EXC_EINVAL); }
+      IHIP(hipMemcpy(c->d_cvec, cv->C, (size_t)c->n_s * 16, kind));
+    }
+    ITRY(upload(c, &c->d_row_chan, row_chan));
+    ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));
+    ITRY(upload(c, &c->d_ch_len, std::vector<int32_t>(c->ch_len.begin(), c->ch_len.end())));
+    ITRY(upload(c, &c->d_ch_coef, c->ch_coef));
+    ITRY(dalloc(c, &c->d_schur, (size_t)std::max(1, c->n_ch)));
+
+    // dense blocks: a column-major workspace per q (factored in place for HERK)
+    std::vector<int64_t> e_off(c->n_q);
+    std::vector<int32_t> e_ld(c->n_q), nd32(c->nd.begin(), c->nd.end()), ldu32(c->ldu.begin(), c->ldu.end());
+    int64_t e_total = 0;
+    for (int q = 0; q < c->n_q; ++q) { e_off[q] = e_total; e_ld[q] = std::max(1, c->nd[q]); e_total += (int64_t)c->nd[q] * c->nd[q]; }
+    double2* d_E = nullptr;
+    int64_t *d_eoff = nullptr, *d_uoff = nullptr;
+    int32_t *d_nd = nullptr, *d_eld = nullptr, *d_ldu = nullptr;
+    int* d_info = nullptr;
+    auto cleanup = [&]() { hipFree(d_E); hipFree(d_eoff); hipFree(d_uoff); hipFree(d_nd); hipFree(d_eld); hipFree(d_ldu); hipFree(d_info); };
+    exc_status s = dalloc(c, &d_E, (size_t)e_total);
+    if (s != EXC_OK) { cleanup(); return bail(s); }
+    for (int q = 0; q < c->n_q; ++q) {
+      if (!cv->E[q] && c->nd[q] > 0) { cleanup(); fail(c, EXC_EINVAL, "coulomb.E[%d] is NULL", q); return bail(EXC_EINVAL); }
+      if (c->nd[q] > 0) {
+        hipError_t e = hipMemcpy(d_E + e_off[q], cv->E[q], (size_t)c->nd[q] * c->nd[q] * 16, kind);
+        if (e != hipSuccess) { cleanup(); fail(c, EXC_EHIP, "copy of E[%d]: %s", q, hipGetErrorString(e)); return bail(EXC_EHIP); }
+      }
+    }
+    if ((s = upload(c, &d_eoff, e_off)) != EXC_OK || (s = upload(c, &d_uoff, c->u_off)) != EXC_OK ||
+        (s = upload(c, &d_nd, nd32)) != EXC_OK || (s = upload(c, &d_eld, e_ld)) != EXC_OK ||
+        (s = upload(c, &d_ldu, ldu32)) != EXC_OK || (s = dalloc(c, &d_info, (size_t)c->n_q + 1)) != EXC_OK) {
+      cleanup(); return bail(s);
+    }
+    hipMemsetAsync(d_info, 0, (c->n_q + 1) * sizeof(int), st);
+    const size_t usz = lds_elem_size(c->precision);
+    s = dalloc(c, (char**)&c->d_U, (size_t)u_total * usz);
+    if (s != EXC_OK) { cleanup(); return bail(s); }
+    if (c->form == EXC_FORM_CHOL_HERK) {
+      if (c->n_ch)
+        hipLaunchKernelGGL(chan_chol_kernel, dim3((c->n_ch + 63) / 64), dim3(64), 0, st, c->n_ch,
+                           c->d_ch_off, c->d_ch_len, c->d_ch_coef, c->d_coef, c->d_cvec,
+                           c->d_schur, d_info + c->n_q);
+      CholArgs ca{d_E, d_eoff, d_nd, d_eld, c->n_ch, c->n_ch ? c->d_schur : nullptr, d_info};
+      hipLaunchKernelGGL(dense_chol_kernel, dim3(c->n_q), dim3(256), 0, st, ca);
+    }
+    dim3 pg(64, c->n_q);
+    const int f = c->form;
+    switch (c->precision) {
+      case EXC_FP64:
+        if (f == 1) hipLaunchKernelGGL((prep_factor_kernel<M_F64, 1>), pg, dim3(256), 0, st, d_E, d_eoff, d_nd, d_eld, c->d_U, d_uoff, d_ldu);
+        else hipLaunchKernelGGL((prep_factor_kernel<M_F64, 0>), pg, dim3(256), 0, st, d_E, d_eoff, d_nd, d_eld, c->d_U, d_uoff, d_ldu);
+        break;
+      case EXC_FP32:
+        hipLaunchKernelGGL((prep_factor_kernel<M_F32, 1>), pg, dim3(256), 0, st, d_E, d_eoff, d_nd, d_eld, c->d_U, d_uoff, d_ldu);
+        break;
+      case EXC_BF16X3:
+        hipLaunchKernelGGL((prep_factor_kernel<M_BF16X3, 1>), pg, dim3(256), 0, st, d_E, d_eoff, d_nd, d_eld, c->d_U, d_uoff, d_ldu);
+        break;
+      default:
+        hipLaunchKernelGGL((prep_factor_kernel<M_BF16X6, 1>), pg, dim3(256), 0, st, d_E, d_eoff, d_nd, d_eld, c->d_U, d_uoff, d_ldu);
+        break;
+    }
+    std::vector<int> info(c->n_q + 1, 0);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipError_t e3 = hipMemcpy(info.data(), d_info, info.size() * sizeof(int), hipMemcpyDeviceToHost);
+    cleanup();
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      fail(c, EXC_EHIP, "factor preparation failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
+      return bail(EXC_EHIP);
+    }
+    if (info[c->n_q]) { fail(c, EXC_ENOTPD, "a multipole-free channel block D_c is not positive definite"); return bail(EXC_ENOTPD); }
+    for (int q = 0; q < c->n_q; ++q)
+      if (info[q]) { fail(c, EXC_ENOTPD, "v(q) is not positive definite at q = %d (pivot %d)", q, info[q]); return bail(EXC_ENOTPD); }
+  }
+
+  // ---- pairs (k-major), workspace, plans ----
+  const int ldw = c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch;
+  int64_t ws_total = 0, m_max = 0;
+  c->k_pair.assign(1, 0);
+  for (int k = 0; k < c->n_k; ++k) {
+    int64_t moff = 0;
+    for (int q = 0; q < c->n_q; ++q) {
+      PairInfo p{};
+      p.k = k; p.q = q; p.nb = c->nb[k]; p.nmb = c->nmb[q]; p.nd = c->nd[q];
+      p.nsb = (c->n_s + BM - 1) / BM; p.ndb = (c->nd[q] + BM - 1) / BM;
+      p.nb8 = (p.nb + 7) / 8 * 8;
+      p.m_off = moff; p.ws_off = ws_total; p.u_off = c->u_off[q]; p.ldu = c->ldu[q]; p.ldw = std::max(1, ldw);
+      moff += (int64_t)c->n_occ * p.nb * p.nmb;
+      ws_total += (int64_t)c->n_occ * p.nb * ldw;
+      c->pairs.push_back(p);
+      c->pair_w.push_back(c->wq[q]);
+      // accounting (nominal: sparse-aware method, Hermitian upper triangle)
+      const double R = (double)c->n_occ * p.nb;
+      double sp = 0;
+      for (int ch = 0; ch < c->n_ch; ++ch) sp += 8.0 * c->ch_len[ch] * c->ch_len[ch] * R;
+      c->flops_nominal += 8.0 * p.nd * (double)p.nd * R + sp + 16.0 * c->n_s * R +
+                          4.0 * p.nb * (p.nb + 1.0) * p.nmb * c->n_occ;
+      if (c->form == EXC_FORM_CHOL_HERK)
+        c->flops_exec += 4.0 * p.nd * (double)p.nd * R + 4.0 * p.nb * (p.nb + 1.0) * p.nmb * c->n_occ;
+      else
+        c->flops_exec += 8.0 * p.nd * (double)p.nd * R + 4.0 * p.nb * (p.nb + 1.0) * p.nmb * c->n_occ;
+    }
+    m_max = std::max(m_max, moff);
+    c->k_pair.push_back((int)c->pairs.size());
+  }
+  {
+    double mb = 0, vb = 0, ub = 0;
+    for (int k = 0; k < c->n_k; ++k) {
+      int64_t e = 0;
+      for (int q = 0; q < c->n_q; ++q) e += (int64_t)c->n_occ * c->nb[k] * c->nmb[q];
+      mb += (double)e;
+      vb += (double)c->nb[k] * c->nb[k] * 16.0;
+    }
+    for (int q = 0; q < c->n_q; ++q) ub += (double)c->nd[q] * c->nd[q] * 16.0;   // v(q) dense block once
+    c->bytes_alg = mb * 16.0 + ub + vb;   // per complex128 M; the binding rescales for complex64
+  }
+  c->mstage_bytes = (size_t)m_max * 16;
+  ITRY(upload(c, &c->d_pairs, c->pairs));
+  ITRY(upload(c, &c->d_pair_w, c->pair_w));
+  ITRY(upload(c, &c->d_pair_begin, std::vector<int32_t>(c->k_pair.begin(), c->k_pair.end())));
+  const size_t wsz = c->precision == EXC_FP64 ? 16 : 8;
+  ITRY(dalloc(c, (char**)&c->d_ws, (size_t)std::max<int64_t>(1, ws_total) * wsz));
+  if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
+    ITRY(dalloc(c, &c->d_dsp, c->pairs.size() * (size_t)c->n_occ * c->nb_max));
+    IHIP(hipMemset(c->d_dsp, 0, c->pairs.size() * (size_t)c->n_occ * c->nb_max * sizeof(double)));
+  }
+
+  ITRY(build_plan(c, c->plain, 1));
+  ITRY(build_plan(c, c->bat, 0));
+  const int nbt = c->nbt_max;
+  c->gstride = nbt * (nbt + 1) / 2 * 256;
+  c->dstride = nbt * 8;
+  const size_t nslot = std::max(c->plain.n_slots, c->bat.n_slots);
+  const size_t asz = c->precision == EXC_FP64 ? 8 : 4;
+  ITRY(dalloc(c, (char**)&c->d_gpart, nslot * c->gstride * asz));
+  ITRY(dalloc(c, &c->d_dpart, nslot * (size_t)c->dstride));
+  IHIP(hipMemsetAsync(c->d_gpart, 0, nslot * c->gstride * asz, st));
+  IHIP(hipMemsetAsync(c->d_dpart, 0, nslot * (size_t)c->dstride * 8, st));
+
+  int64_t vtot = 0;
+  for (int k = 0; k < c->n_k; ++k) { c->v_off.push_back(vtot); vtot += (int64_t)c->nb[k] * c->nb[k]; }
+  ITRY(dalloc(c, &c->d_vres, (size_t)vtot));
+  ITRY(upload(c, &c->d_voff, c->v_off));
+  ITRY(upload(c, &c->d_knb, std::vector<int32_t>(c->nb.begin(), c->nb.end())));
+  c->v_valid.assign(c->n_k, 0);
+  ITRY(dalloc(c, &c->d_mtab, (size_t)c->n_k));
+  ITRY(dalloc(c, &c->d_vtab, (size_t)c->n_k));
+  c->h_mtab.assign(c->n_k, nullptr);
+  c->h_vtab.assign(c->n_k, nullptr);
+  IHIP(hipMemset(c->d_mtab, 0, c->n_k * sizeof(void*)));
+  IHIP(hipMemset(c->d_vtab, 0, c->n_k * sizeof(void*)));
+  ITRY(dalloc(c, &c->d_counter, 1));
+  ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
+
+  int n_cu = 0, occ = 0;
+  IHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 256, 0));
+  c->persist_grid = std::max(1, n_cu * std::max(1, occ));
+  IHIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+  IHIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  IHIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  IHIP(hipStreamSynchronize(st));
+#undef ITRY
+#undef IHIP
+  *out = c;
+  return EXC_OK;
+}
+
+static exc_status ensure_stage(exc_ctx* c) {
+  if (!c->d_mstage) TRY(dalloc(c, (char**)&c->d_mstage, c->mstage_bytes));
+  return EXC_OK;
+}
+
+exc_status exchange_matrix(exc_ctx* c, int32_t k, const void* M, int32_t dtype, int32_t on_device,
+                           void* Vx, void* stream) {
+  TRY(check_ctx(c));
+  if (k < 0 || k >= c->n_k) return fail(c, EXC_EINVAL, "k = %d outside [0, %d)", k, c->n_k);
+  if (!M || !Vx) return fail(c, EXC_EINVAL, "M or Vx is NULL");
+  if (dtype != EXC_C128 && dtype != EXC_C64) return fail(c, EXC_EINVAL, "bad dtype %d", dtype);
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t esz = dtype == EXC_C64 ? 8 : 16;
+  const size_t mbytes = (size_t)(c->pairs[c->k_pair[k + 1] - 1].m_off +
+                                 (int64_t)c->n_occ * c->nb[k] * c->nmb[c->n_q - 1]) * esz;
+  const void* Md = M;
+  void* Vd = Vx;
+  if (!on_device) {
+    TRY(ensure_stage(c));
+    HIPCHK(c, hipMemcpyAsync(c->d_mstage, M, mbytes, hipMemcpyHostToDevice, st));
+    Md = c->d_mstage;
+    Vd = nullptr;
+  }
+  const void* mp[1] = {Md};
+  void* vp[1] = {Vd};
+  TRY(set_tables(c, k, 1, mp, vp, st));
+  if (c->batched) run_k_batched(c, k, dtype, st);
+  else run_k_plain(c, k, dtype, st);
+  HIPCHK(c, hipGetLastError());
+  if (!on_device) {
+    HIPCHK(c, hipMemcpyAsync(Vx, c->d_vres + c->v_off[k], (size_t)c->nb[k] * c->nb[k] * 16,
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+  }
+  c->v_valid[k] = 1;
+  return EXC_OK;
+}
+
+exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype, int32_t on_device,
+                               void* const* Vx_k, void* stream) {
+  TRY(check_ctx(c));
+  if (!M_k || !Vx_k) return fail(c, EXC_EINVAL, "M_k or Vx_k is NULL");
+  for (int k = 0; k < c->n_k; ++k)
+    if (!M_k[k] || !Vx_k[k]) return fail(c, EXC_EINVAL, "M_k[%d] or Vx_k[%d] is NULL", k, k);
+  if (dtype != EXC_C128 && dtype != EXC_C64) return fail(c, EXC_EINVAL, "bad dtype %d", dtype);
+  if (!on_device) {
+    for (int k = 0; k < c->n_k; ++k) TRY(exchange_matrix(c, k, M_k[k], dtype, 0, Vx_k[k], stream));
+    return EXC_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!c->batched) {
+    TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
+    for (int k = 0; k < c->n_k; ++k) run_k_plain(c, k, dtype, st);
+    HIPCHK(c, hipGetLastError());
+  } else {
+    bool same = c->gexec && c->g_dtype == dtype;
+    for (int k = 0; k < c->n_k && same; ++k)
+      if (c->h_mtab[k] != M_k[k] || c->h_vtab[k] != Vx_k[k]) same = false;
+    TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
+    if (!same) {
+      if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+      run_all_batched_body(c, dtype, c->own);
+      hipError_t le = hipGetLastError();
+      hipError_t ce = hipStreamEndCapture(c->own, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(c, EXC_EHIP, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+      }
+      hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ie != hipSuccess) { c->gexec = nullptr; return fail(c, EXC_EHIP, "graph instantiate: %s", hipGetErrorString(ie)); }
+      c->g_dtype = dtype;
+    }
+    // order: caller's stream -> graph on the internal stream -> caller's stream
+    HIPCHK(c, hipEventRecord(c->ev_in, st));
+    HIPCHK(c, hipStreamWaitEvent(c->own, c->ev_in, 0));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
+    HIPCHK(c, hipEventRecord(c->ev_out, c->own));
+    HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
+  }
+  for (int k = 0; k < c->n_k; ++k) c->v_valid[k] = 1;
+  return EXC_OK;
+}
+
+exc_status exchange_energy(exc_ctx* c, const double* w_k, const void* const* rho_k, double* E_out) {
+  TRY(check_ctx(c));
+  if (!E_out) return fail(c, EXC_EINVAL, "E_out is NULL");
+  for (int k = 0; k < c->n_k; ++k)
+    if (!c->v_valid[k]) return fail(c, EXC_ESTATE, "V(k=%d) has not been computed", k);
+  hipStream_t st = c->last_stream;
+  void** d_rho = nullptr;
+  if (rho_k) {
+    TRY(dalloc(c, &d_rho, (size_t)c->n_k));
+    if (hipMemcpy(d_rho, rho_k, c->n_k * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(d_rho);
+      return fail(c, EXC_EHIP, "copy of rho pointers failed");
+    }
+  }
+  hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
+                     (const void* const*)d_rho, c->n_occ, c->d_eout);
+  std::vector<double> e(c->n_k);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  hipError_t e3 = hipMemcpy(e.data(), c->d_eout, c->n_k * sizeof(double), hipMemcpyDeviceToHost);
+  if (d_rho) hipFree(d_rho);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(c, EXC_EHIP, "energy kernel failed");
+  double s = 0.0;
+  for (int k = 0; k < c->n_k; ++k) s += (w_k ? w_k[k] : 1.0 / c->n_k) * e[k];
+  *E_out = 0.5 * s;
+  return EXC_OK;
+}
+
+const char* exchange_last_error(const exc_ctx* c) {
+  if (!c) return g_init_err.c_str();
+  if (c->magic != kAlive) return "context is not alive";
+  return c->err.c_str();
+}
+
+void exchange_destroy(exc_ctx* c) {
+  if (!c || c->magic != kAlive) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  release(c);
+  c->magic = 0;
+  delete c;
+}
+
+exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
+  TRY(check_ctx(c));
+  if (!value) return EXC_EINVAL;
+  switch (what) {
+    case 0: *value = c->bat.n_slots; return EXC_OK;
+    case 1: *value = c->flops_nominal; return EXC_OK;
+    case 2: *value = c->flops_exec; return EXC_OK;
+    case 3: *value = c->cfg ? c->cfg->id : -1; return EXC_OK;
+    case 4: *value = c->bytes_alg; return EXC_OK;
+    default: return EXC_EINVAL;
+  }
+}
+
+}  // extern "C"
