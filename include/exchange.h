@@ -168,8 +168,20 @@ void exchange_destroy(exc_ctx *ctx);
  *   what = 3: tile configuration id chosen by the autotuner (-1 if not tuned)
  *   what = 4: algorithmic HBM bytes of one exchange_matrix_all
  *             (M read once, v(q) read once, Vx written once)
+ *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
+
+/*
+ * exchange_timing -- live kernel timing of the batched exchange_matrix_all
+ * path for benchmarks. n_slots > 0: the next captured graph carries event-
+ * record nodes around the block-sparse kernel and the tile kernel, and each
+ * replay records into its own slot of a pool of n_slots event triples (the
+ * last n_slots replays are kept). n_slots = 0 switches timing off. Both
+ * synchronise the device and drop the current graph. Read the means with
+ * exchange_query: what = 5 tile kernel ms, 7 sparse kernel ms, 6 replays timed.
+ */
+exc_status exchange_timing(exc_ctx *ctx, int32_t n_slots);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,7 @@ DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
-                    "exchange_last_error", "exchange_destroy", "exchange_query")
+                    "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing")
 
 
 class ExchangeError(RuntimeError):
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_destroy.restype = None
     lib.exchange_query.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     lib.exchange_query.restype = i32
+    lib.exchange_timing.argtypes = [vp, i32]
+    lib.exchange_timing.restype = i32
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -213,6 +215,14 @@ class Exchange:
         v = ctypes.c_double()
         self._check(self.lib.exchange_query(self.ctx, int(what), ctypes.byref(v)))
         return v.value
+
+    def timing(self, n_slots: int) -> None:
+        """Enable (n_slots > 0) or disable (0) live kernel timing of the batched path."""
+        self._check(self.lib.exchange_timing(self.ctx, int(n_slots)))
+
+    def kernel_ms(self):
+        """(mean tile-kernel ms, mean sparse-kernel ms, replays timed)."""
+        return self.query(5), self.query(7), int(self.query(6))
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -117,6 +117,12 @@ struct exc_ctx {
   hipStream_t own = nullptr;          // capturable stream of the batched path
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int g_dtype = -1;
+  // live kernel timing of the batched path: event-record nodes around the
+  // sparse and tile kernels; one pool entry (3 events) per graph replay
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t tnode[3] = {nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> tpool;      // 3 per slot
+  int t_slots = 0, t_next = 0, t_count = 0;
   // staging for host-pointer calls
   void* d_mstage = nullptr;
   size_t mstage_bytes = 0;
@@ -177,9 +183,18 @@ void free_plan(Plan& p) {
   p.d_items = p.d_items_lpt = nullptr; p.d_slot_begin = nullptr; p.d_slot_w = nullptr;
 }
 
+void release_timing(exc_ctx* c) {
+  for (hipEvent_t e : c->tpool) hipEventDestroy(e);
+  c->tpool.clear();
+  c->t_slots = c->t_next = c->t_count = 0;
+}
+
 void release(exc_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph = nullptr;
+  release_timing(c);
   if (c->ev_in) hipEventDestroy(c->ev_in);
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own) hipStreamDestroy(c->own);
@@ -311,22 +326,48 @@ SparseArgs sparse_args(exc_ctx* c, int dtype) {
   return s;
 }
 
-void launch_sparse(exc_ctx* c, int dtype, int pair0, int npairs, hipStream_t st) {
-  if (c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return;
-  SparseArgs s = sparse_args(c, dtype);
+// A configured kernel launch: enqueued directly or added to a graph as a node.
+struct KLaunch {
+  const void* fn = nullptr;
+  dim3 grid, block{256, 1, 1};
+  void* arg = nullptr;          // points at the single by-value argument struct
+};
+
+hipError_t enqueue(const KLaunch& L, hipStream_t st) {
+  void* args[1] = {L.arg};
+  return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st);
+}
+
+hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGraphNode_t* out) {
+  void* args[1] = {L.arg};
+  hipKernelNodeParams p{};
+  p.func = const_cast<void*>(L.fn);
+  p.gridDim = L.grid;
+  p.blockDim = L.block;
+  p.kernelParams = args;
+  p.sharedMemBytes = 0;
+  p.extra = nullptr;
+  return hipGraphAddKernelNode(out, g, dep, dep ? 1 : 0, &p);
+}
+
+// Block-sparse rows of pairs [pair0, pair0 + npairs). Returns false when there is nothing to do.
+bool cfg_sparse(exc_ctx* c, int dtype, int pair0, int npairs, SparseArgs& s, KLaunch& L) {
+  if (c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return false;
+  s = sparse_args(c, dtype);
   s.pairs = c->d_pairs + pair0;
   // dsp is indexed by blockIdx.y: offset it to the first pair
   s.dsp = c->d_dsp ? c->d_dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
-  dim3 grid((c->n_occ * c->nb_max + 3) / 4, npairs);
+  L.grid = dim3((c->n_occ * c->nb_max + 3) / 4, npairs);
   const bool herk = c->form == EXC_FORM_CHOL_HERK;
   const bool f64 = c->precision == EXC_FP64;
-  if (!herk) hipLaunchKernelGGL((sparse_kernel<0, 1, 0>), grid, dim3(256), 0, st, s);
-  else if (f64) hipLaunchKernelGGL((sparse_kernel<1, 1, 0>), grid, dim3(256), 0, st, s);
-  else hipLaunchKernelGGL((sparse_kernel<1, 0, 1>), grid, dim3(256), 0, st, s);
+  L.fn = !herk ? (const void*)sparse_kernel<0, 1, 0>
+               : (f64 ? (const void*)sparse_kernel<1, 1, 0> : (const void*)sparse_kernel<1, 0, 1>);
+  L.arg = &s;
+  return true;
 }
 
-void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
-  ReduceArgs r{};
+void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunch& L) {
+  r = ReduceArgs{};
   r.k_nb = c->d_knb + k0;
   r.slot_begin = P.d_slot_begin + k0;
   r.slot_w = P.d_slot_w;
@@ -344,21 +385,41 @@ void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
   r.vres = c->d_vres;
   r.v_off = c->d_voff + k0;
   r.vout = c->d_vtab + k0;
-  dim3 grid((c->nb_max * c->nb_max + 255) / 256, nk);
-  if (r.acc64) hipLaunchKernelGGL((reduce_kernel<1>), grid, dim3(256), 0, st, r);
-  else hipLaunchKernelGGL((reduce_kernel<0>), grid, dim3(256), 0, st, r);
+  L.grid = dim3((c->nb_max * c->nb_max + 255) / 256, nk);
+  L.fn = r.acc64 ? (const void*)reduce_kernel<1> : (const void*)reduce_kernel<0>;
+  L.arg = &r;
 }
 
-void launch_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent,
-                 hipStream_t st) {
-  if (n <= 0) return;
-  TileArgs a = tile_args(c, dtype);
+void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent, TileArgs& a,
+              KLaunch& L) {
+  a = tile_args(c, dtype);
   a.items = items;
   a.n_items = n;
   a.counter = persistent ? c->d_counter : nullptr;
-  const int grid = persistent ? std::min(n, c->persist_grid) : n;
-  if (persistent) hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, st, c->d_counter, 1);
-  hipLaunchKernelGGL(c->cfg->fn, dim3(grid), dim3(256), 0, st, a);
+  L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
+  L.fn = (const void*)c->cfg->fn;
+  L.arg = &a;
+}
+
+void launch_sparse(exc_ctx* c, int dtype, int pair0, int npairs, hipStream_t st) {
+  SparseArgs s;
+  KLaunch L;
+  if (cfg_sparse(c, dtype, pair0, npairs, s, L)) (void)enqueue(L, st);
+}
+
+void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
+  ReduceArgs r;
+  KLaunch L;
+  cfg_reduce(c, P, k0, nk, r, L);
+  (void)enqueue(L, st);
+}
+
+void launch_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, hipStream_t st) {
+  if (n <= 0) return;
+  TileArgs a;
+  KLaunch L;
+  cfg_tile(c, dtype, items, n, false, a, L);
+  (void)enqueue(L, st);
 }
 
 // One k, batched over its q: sparse rows of all pairs of k, one tile launch, reduce.
@@ -366,7 +427,7 @@ void run_k_batched(exc_ctx* c, int k, int dtype, hipStream_t st) {
   const int p0 = c->k_pair[k], p1 = c->k_pair[k + 1];
   launch_sparse(c, dtype, p0, p1 - p0, st);
   const Plan& P = c->bat;
-  launch_tile(c, dtype, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], false, st);
+  launch_tile(c, dtype, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], st);
   launch_reduce(c, P, k, 1, st);
 }
 
@@ -375,15 +436,69 @@ void run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
   const Plan& P = c->plain;
   for (int p = c->k_pair[k]; p < c->k_pair[k + 1]; ++p) {
     launch_sparse(c, dtype, p, 1, st);
-    launch_tile(c, dtype, P.d_items + P.pair_item[p], P.pair_item[p + 1] - P.pair_item[p], false, st);
+    launch_tile(c, dtype, P.d_items + P.pair_item[p], P.pair_item[p + 1] - P.pair_item[p], st);
   }
   launch_reduce(c, P, k, 1, st);
 }
 
-void run_all_batched_body(exc_ctx* c, int dtype, hipStream_t st) {
-  launch_sparse(c, dtype, 0, (int)c->pairs.size(), st);
-  launch_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, st);
-  launch_reduce(c, c->bat, 0, c->n_k, st);
+// The batched path as an explicit graph:
+//   zero work counter -> [ev0] -> block-sparse rows -> [ev1] -> persistent tile
+//   kernel -> [ev2] -> FP64 reduction.
+// The event-record nodes exist only while kernel timing is on; their events are
+// swapped per replay (hipGraphExecEventRecordNodeSetEvent).
+exc_status build_batched_graph(exc_ctx* c, int dtype) {
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipGraphCreate(&g, 0));
+  const bool timed = c->t_slots > 0;
+  for (auto& t : c->tnode) t = nullptr;
+  int32_t one = 1;
+  int32_t* ctr = c->d_counter;
+  void* zargs[2] = {&ctr, &one};
+  hipKernelNodeParams zp{};
+  zp.func = (void*)zero_int_kernel;
+  zp.gridDim = dim3(1);
+  zp.blockDim = dim3(64);
+  zp.kernelParams = zargs;
+  hipGraphNode_t last = nullptr, node = nullptr;
+  hipError_t e = hipGraphAddKernelNode(&node, g, nullptr, 0, &zp);
+  last = node;
+  auto add_ev = [&](int i) -> hipError_t {
+    if (!timed || e != hipSuccess) return e;
+    hipGraphNode_t n2 = nullptr;
+    hipError_t r = hipGraphAddEventRecordNode(&n2, g, &last, 1, c->tpool[i]);
+    if (r == hipSuccess) { c->tnode[i] = n2; last = n2; }
+    return r;
+  };
+  e = add_ev(0);
+  SparseArgs sa;
+  KLaunch L;
+  if (e == hipSuccess && cfg_sparse(c, dtype, 0, (int)c->pairs.size(), sa, L)) {
+    e = add_node(g, L, &last, &node);
+    last = node;
+  }
+  e = add_ev(1);
+  TileArgs ta;
+  if (e == hipSuccess) {
+    cfg_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
+    e = add_node(g, L, &last, &node);
+    last = node;
+  }
+  e = add_ev(2);
+  ReduceArgs ra;
+  if (e == hipSuccess) {
+    cfg_reduce(c, c->bat, 0, c->n_k, ra, L);
+    e = add_node(g, L, &last, &node);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    c->gexec = nullptr;
+    return fail(c, EXC_EHIP, "building the batched graph failed: %s", hipGetErrorString(e));
+  }
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph = g;
+  c->g_dtype = dtype;
+  return EXC_OK;
 }
 
 exc_status check_ctx(const exc_ctx* c) {
@@ -733,19 +848,15 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
     TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
     if (!same) {
       if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
-      hipGraph_t g = nullptr;
-      HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
-      run_all_batched_body(c, dtype, c->own);
-      hipError_t le = hipGetLastError();
-      hipError_t ce = hipStreamEndCapture(c->own, &g);
-      if (le != hipSuccess || ce != hipSuccess) {
-        if (g) hipGraphDestroy(g);
-        return fail(c, EXC_EHIP, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ce));
-      }
-      hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
-      if (ie != hipSuccess) { c->gexec = nullptr; return fail(c, EXC_EHIP, "graph instantiate: %s", hipGetErrorString(ie)); }
-      c->g_dtype = dtype;
+      TRY(build_batched_graph(c, dtype));
+    }
+    if (c->t_slots > 0 && c->tnode[0] && c->tnode[1] && c->tnode[2]) {
+      // rotate the event triple of this replay
+      const int s = c->t_next;
+      for (int i = 0; i < 3; ++i)
+        HIPCHK(c, hipGraphExecEventRecordNodeSetEvent(c->gexec, c->tnode[i], c->tpool[3 * s + i]));
+      c->t_next = (c->t_next + 1) % c->t_slots;
+      c->t_count = std::min(c->t_count + 1, c->t_slots);
     }
     // order: caller's stream -> graph on the internal stream -> caller's stream
     HIPCHK(c, hipEventRecord(c->ev_in, st));
@@ -810,8 +921,38 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 2: *value = c->flops_exec; return EXC_OK;
     case 3: *value = c->cfg ? c->cfg->id : -1; return EXC_OK;
     case 4: *value = c->bytes_alg; return EXC_OK;
+    case 5:
+    case 7: {
+      // mean duration (ms) of the tile (5) or sparse (7) kernel over the timed replays
+      if (c->t_count == 0) { *value = 0.0; return EXC_OK; }
+      double sum = 0.0;
+      for (int s = 0; s < c->t_count; ++s) {
+        hipEvent_t* e = const_cast<hipEvent_t*>(&c->tpool[3 * s]);
+        if (hipEventSynchronize(e[2]) != hipSuccess) return EXC_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, what == 5 ? e[1] : e[0], what == 5 ? e[2] : e[1]) != hipSuccess) return EXC_EHIP;
+        sum += ms;
+      }
+      *value = sum / c->t_count;
+      return EXC_OK;
+    }
+    case 6: *value = c->t_count; return EXC_OK;
     default: return EXC_EINVAL;
   }
+}
+
+exc_status exchange_timing(exc_ctx* c, int32_t n_slots) {
+  TRY(check_ctx(c));
+  if (n_slots < 0) return fail(c, EXC_EINVAL, "n_slots < 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  release_timing(c);
+  if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }   // re-capture with / without event nodes
+  if (n_slots == 0) return EXC_OK;
+  c->tpool.resize(3 * (size_t)n_slots, nullptr);
+  for (auto& e : c->tpool) HIPCHK(c, hipEventCreate(&e));
+  c->t_slots = n_slots;
+  return EXC_OK;
 }
 
 }  // extern "C"
