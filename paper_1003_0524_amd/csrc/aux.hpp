@@ -21,8 +21,11 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 // channel and to the channel's multipole function.
 //   HERK form: Y_c = L_c^H A_c + l_c a_{j(c)}   (rows of L^H A for v = L L^H)
 //   GEMM form: W_c = D_c A_c + C_c a_{j(c)},  X_c = C_c^H A_c (added to W row j(c))
-// One wavefront per column (k, q, n'', n): the kernel streams M once and
-// writes the sparse rows once, so it is bound by HBM bandwidth.
+// One wavefront per column (k, q, n'', n): the column's MT and multipole rows
+// are staged in LDS with coalesced 16-byte loads, every row is computed in FP64
+// and written once, so the kernel is bound by HBM bandwidth. Output: double2
+// rows (FP64 mode) or the tile kernel's split planes [plane][row] with the row
+// pitch padded to 8 and zero filled (reduced-precision modes).
 // ---------------------------------------------------------------------------
 struct SparseArgs {
   const PairInfo* pairs;
@@ -35,50 +38,72 @@ struct SparseArgs {
   const int64_t* ch_coef;    // [n_ch] offset of the channel's square block in coef
   const double2* coef;       // HERK: L_c (lower, col-major); GEMM: D_c (col-major)
   const double2* cvec;       // [n_s] HERK: l_c = L_c^{-1} C_c; GEMM: C_c
-  void* ws;                  // output rows (double2 or float2)
+  void* ws;                  // output rows
   double* dsp;               // HERK, reduced precision: sum_r |Y_s[r][n]|^2 per column
 };
 
-template <int FORM, int OUT64, int DIAG>
+template <int FORM, int MODE>
 __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
+  extern __shared__ double2 scol[];          // [4 waves][n_s + n_ch]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const PairInfo pi = a.pairs[blockIdx.y];
   const int col = blockIdx.x * 4 + w;
-  if (col >= a.n_occ * pi.nb) return;       // the whole wavefront leaves together
-  const long mcol = pi.m_off + (long)col * pi.nmb;
-  const char* mb = (const char*)a.mtab[pi.k];
-  auto ldA = [&](int r) -> double2 {
-    if (a.m_c64) {
-      const float2 v = ((const float2*)mb)[mcol + r];
-      return make_double2(v.x, v.y);
+  const bool active = col < a.n_occ * pi.nb;
+  const int nrow = a.n_s + a.n_ch;
+  double2* S = scol + (long)w * nrow;
+  if (active) {
+    const long mcol = pi.m_off + (long)col * pi.nmb;
+    const char* mb = (const char*)a.mtab[pi.k];
+    for (int r = lane; r < nrow; r += 64) {
+      if (a.m_c64) {
+        const float2 v = ((const float2*)mb)[mcol + r];
+        S[r] = make_double2(v.x, v.y);
+      } else {
+        S[r] = ((const double2*)mb)[mcol + r];
+      }
     }
-    return ((const double2*)mb)[mcol + r];
-  };
-  const long wcol = pi.ws_off + (long)col * pi.ldw;
+  }
+  __syncthreads();
+  if (!active) return;                       // whole wavefronts leave; no barrier follows
   double dsum = 0.0;
-  for (int r = lane; r < a.n_s; r += 64) {
-    const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-    const double2* cf = a.coef + a.ch_coef[c];
-    double2 y = make_double2(0.0, 0.0);
-    if (FORM == 1) {
-      for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], ldA(s + j)));
-    } else {
-      for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], ldA(s + j)));
+  if constexpr (MODE == M_F64) {
+    const long wcol = pi.ws_off + (long)col * pi.ldw;
+    double2* out = (double2*)a.ws;
+    for (int r = lane; r < a.n_s; r += 64) {
+      const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
+      const double2* cf = a.coef + a.ch_coef[c];
+      double2 y = make_double2(0.0, 0.0);
+      if (FORM == 1) {
+        for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
+      } else {
+        for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], S[s + j]));
+      }
+      out[wcol + r] = cadd(y, cmul(a.cvec[r], S[a.n_s + c]));
     }
-    y = cadd(y, cmul(a.cvec[r], ldA(a.n_s + c)));
-    if (OUT64) ((double2*)a.ws)[wcol + r] = y;
-    else ((float2*)a.ws)[wcol + r] = make_float2((float)y.x, (float)y.y);
-    if (DIAG) dsum += y.x * y.x + y.y * y.y;
-  }
-  if (FORM == 0) {
-    for (int c = lane; c < a.n_ch; c += 64) {
-      const int s = a.ch_off[c], b = a.ch_len[c];
-      double2 x = make_double2(0.0, 0.0);
-      for (int j = 0; j < b; ++j) x = cadd(x, cmulc(a.cvec[s + j], ldA(s + j)));
-      ((double2*)a.ws)[wcol + a.n_s + c] = x;
+    if (FORM == 0) {
+      for (int c = lane; c < a.n_ch; c += 64) {
+        const int s = a.ch_off[c], b = a.ch_len[c];
+        double2 x = make_double2(0.0, 0.0);
+        for (int j = 0; j < b; ++j) x = cadd(x, cmulc(a.cvec[s + j], S[s + j]));
+        out[wcol + a.n_s + c] = x;
+      }
     }
-  }
-  if (DIAG) {
+  } else {
+    using lds_t = typename Traits<MODE>::lds_t;
+    constexpr int NP = Traits<MODE>::NPIECE;
+    lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
+    for (int r = lane; r < pi.ldw; r += 64) {
+      double2 y = make_double2(0.0, 0.0);
+      if (r < a.n_s) {
+        const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
+        const double2* cf = a.coef + a.ch_coef[c];
+        for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
+        y = cadd(y, cmul(a.cvec[r], S[a.n_s + c]));
+        dsum += y.x * y.x + y.y * y.y;
+      }
+      put_real<MODE>(out + r, pi.ldw, y.x);
+      put_real<MODE>(out + (long)NP * pi.ldw + r, pi.ldw, y.y);
+    }
     for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
     if (lane == 0) a.dsp[(long)blockIdx.y * a.n_occ * a.nb_max + col] = dsum;
   }
@@ -87,8 +112,10 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 reduction of the item partials of each k:
 //   V(k) = - sum_{slots of k} w_q(slot) * (Gram tiles of the slot)
-// with the Hermitian mirror and Im V_nn = 0. In the reduced-precision HERK
-// modes the diagonal comes from the FP64 sums of |Y|^2.
+// with the Hermitian mirror and Im V_nn = 0. One workgroup per (Gram tile, k):
+// 64 entries of the 8x8 band block times 4 interleaved slot subsets, combined
+// in a fixed order. In the reduced-precision HERK modes the diagonal comes from
+// the FP64 sums of |Y|^2.
 // ---------------------------------------------------------------------------
 struct ReduceArgs {
   const int32_t* k_nb;         // [n_k]
@@ -98,11 +125,6 @@ struct ReduceArgs {
   int32_t gstride, acc64;
   const double* dpart;
   int32_t dstride, use_d64;
-  const int32_t* pair_begin;   // [n_k + 1]
-  const double* pair_w;        // [n_pairs]
-  const double* dsp;
-  int32_t dsp_stride;          // n_occ * nb_max
-  int32_t n_occ;
   double2* vres;
   const int64_t* v_off;        // [n_k]
   void* const* vout;           // [n_k] device pointers or nullptr
@@ -118,17 +140,22 @@ __device__ __forceinline__ int gidx(int tp, int row, int col) {
 
 template <int ACC64>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+  __shared__ double red[4][64][3];
   const int k = blockIdx.y;
   const int nb = a.k_nb[k];
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int n = e % nb, n2 = e / nb;
-  if (n2 >= nb || n > n2) return;
-  const int I = n >> 3, J = n2 >> 3, c = n & 7, c2 = n2 & 7;
-  const int tp = J * (J + 1) / 2 + I;
+  const int nbt = (nb + 7) >> 3;
+  const int tp = blockIdx.x;
+  if (tp >= nbt * (nbt + 1) / 2) return;     // uniform over the workgroup
+  int I, J;
+  tp_to_ij(tp, I, J);
+  const int e = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int c = e & 7, c2 = e >> 3;
+  const int n = I * 8 + c, n2 = J * 8 + c2;
   const int irr = gidx<ACC64>(tp, c, c2), iii = gidx<ACC64>(tp, c + 8, c2 + 8);
   const int iri = gidx<ACC64>(tp, c, c2 + 8), iir = gidx<ACC64>(tp, c + 8, c2);
-  double re = 0.0, im = 0.0;
-  for (int s = a.slot_begin[k]; s < a.slot_begin[k + 1]; ++s) {
+  double re = 0.0, im = 0.0, dg = 0.0;
+  const bool diag = (n == n2) && n < nb;
+  for (int s = a.slot_begin[k] + sg; s < a.slot_begin[k + 1]; s += 4) {
     const double wq = a.slot_w[s];
     double grr, gii, gri, gir;
     if (ACC64) {
@@ -140,19 +167,18 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     }
     re += wq * (grr + gii);
     im += wq * (gri - gir);
+    if (diag && a.use_d64) dg += wq * a.dpart[(long)s * a.dstride + n];
   }
+  red[sg][e][0] = re;
+  red[sg][e][1] = im;
+  red[sg][e][2] = dg;
+  __syncthreads();
+  if (sg != 0 || n >= nb || n2 >= nb || n > n2) return;
+  re = ((red[0][e][0] + red[1][e][0]) + red[2][e][0]) + red[3][e][0];
+  im = ((red[0][e][1] + red[1][e][1]) + red[2][e][1]) + red[3][e][1];
   if (n == n2) {
     im = 0.0;
-    if (a.use_d64) {
-      re = 0.0;
-      for (int s = a.slot_begin[k]; s < a.slot_begin[k + 1]; ++s)
-        re += a.slot_w[s] * a.dpart[(long)s * a.dstride + n];
-      for (int p = a.pair_begin[k]; p < a.pair_begin[k + 1]; ++p) {
-        double t = 0.0;
-        for (int j = 0; j < a.n_occ; ++j) t += a.dsp[(long)p * a.dsp_stride + (long)j * nb + n];
-        re += a.pair_w[p] * t;
-      }
-    }
+    if (a.use_d64) re = ((red[0][e][2] + red[1][e][2]) + red[2][e][2]) + red[3][e][2];
   }
   const double2 v = make_double2(-re, -im);
   double2* V = a.vres + a.v_off[k];

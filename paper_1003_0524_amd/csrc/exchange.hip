@@ -26,31 +26,31 @@ constexpr uint32_t kAlive = 0x45584331u;   // "EXC1"
 thread_local std::string g_init_err;
 
 struct KernelCfg {
-  int mode, form, BM, KC, NCT, NB8M;
+  int mode, form, BM, KC, NCT, NB8M, NW, NBUF;
   void (*fn)(TileArgs);
   size_t lds;
   int id;
 };
 
-#define CFG(MODE, FORM, BM, KC, NCT, NB8M, ID)                                              \
-  KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, tile_kernel<MODE, FORM, BM, KC, NCT, NB8M>,         \
-            TileCfg<MODE, FORM, BM, KC, NCT, NB8M>::LDS_B, ID}
+#define CFG(MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF, ID)                                          \
+  KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF, tile_kernel<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>, \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>::LDS_B, ID}
 
-// The GEMM form stages two FP64 operands per n'' value and therefore stops at
-// n_b <= 64 (band-tile count 8) within the 160 KB of LDS.
-// Tile shapes: BM rows of the factor per step, KC complex k per LDS stage, NCT
-// 8-column band tiles per pass (n_b rounded to 8, times the n'' chunk), NB8M
-// the largest band-tile count per n'' value the instance contracts.
+// Tile shapes: BM rows of the factor per step (split over NW wavefronts), KC
+// complex k per LDS stage, NCT 8-column band tiles per pass (n_b rounded to 8,
+// times the n'' chunk), NB8M the largest band-tile count per n'' value the
+// instance contracts, NBUF K-loop buffers. The GEMM form stages two FP64
+// operands per n'' value and therefore stops at n_b <= 64.
 const KernelCfg kCfgs[] = {
-    CFG(M_F64, 0, 64, 16, 6, 3, 0),    CFG(M_F64, 0, 64, 16, 8, 8, 1),
-    CFG(M_F64, 1, 64, 16, 12, 3, 10),  CFG(M_F64, 1, 64, 16, 8, 8, 11),
-    CFG(M_F64, 1, 64, 16, 16, 16, 12),
-    CFG(M_F32, 1, 128, 16, 12, 3, 20), CFG(M_F32, 1, 128, 16, 16, 8, 21),
-    CFG(M_F32, 1, 64, 16, 16, 16, 22),
-    CFG(M_BF16X3, 1, 128, 32, 12, 3, 30), CFG(M_BF16X3, 1, 128, 32, 16, 8, 31),
-    CFG(M_BF16X3, 1, 64, 32, 16, 16, 32),
-    CFG(M_BF16X6, 1, 128, 32, 12, 3, 40), CFG(M_BF16X6, 1, 128, 32, 16, 8, 41),
-    CFG(M_BF16X6, 1, 64, 32, 16, 16, 42),
+    CFG(M_F64, 0, 64, 16, 6, 3, 4, 2, 0),      CFG(M_F64, 0, 64, 16, 8, 8, 4, 2, 1),
+    CFG(M_F64, 1, 64, 16, 12, 3, 4, 2, 10),    CFG(M_F64, 1, 64, 16, 8, 8, 4, 2, 11),
+    CFG(M_F64, 1, 64, 16, 13, 13, 4, 2, 13),   CFG(M_F64, 1, 64, 16, 16, 16, 4, 2, 12),
+    CFG(M_F32, 1, 128, 16, 12, 3, 8, 2, 20),   CFG(M_F32, 1, 128, 16, 8, 8, 8, 2, 21),
+    CFG(M_F32, 1, 128, 16, 13, 13, 8, 2, 23),  CFG(M_F32, 1, 128, 16, 16, 16, 8, 2, 22),
+    CFG(M_BF16X3, 1, 128, 32, 12, 3, 8, 2, 30), CFG(M_BF16X3, 1, 128, 32, 8, 8, 8, 2, 31),
+    CFG(M_BF16X3, 1, 128, 32, 13, 13, 8, 2, 33), CFG(M_BF16X3, 1, 64, 32, 16, 16, 4, 2, 32),
+    CFG(M_BF16X6, 1, 64, 32, 12, 3, 4, 2, 40),  CFG(M_BF16X6, 1, 64, 32, 8, 8, 4, 2, 41),
+    CFG(M_BF16X6, 1, 64, 32, 13, 13, 4, 1, 43), CFG(M_BF16X6, 1, 64, 32, 16, 16, 4, 1, 42),
 };
 
 struct Plan {
@@ -233,7 +233,11 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
     for (int pidx = c->k_pair[k]; pidx < c->k_pair[k + 1]; ++pidx) {
       const PairInfo& p = c->pairs[pidx];
       const int nbt = p.nb8 / 8;
-      const int ngc = std::max(1, std::min(c->n_occ, nct / nbt));
+      // n'' values per K-loop pass: as many as the column tiles allow, balanced
+      // so that the passes of a pair are equally full
+      const int ngmax = std::max(1, std::min(c->n_occ, nct / nbt));
+      const int npass = (c->n_occ + ngmax - 1) / ngmax;
+      const int ngc = (c->n_occ + npass - 1) / npass;
       const int nrb = p.nsb + p.ndb;
       auto push = [&](int g0, int g1, int rb0, int rb1) {
         WorkItem w{};
@@ -307,6 +311,8 @@ TileArgs tile_args(exc_ctx* c, int dtype) {
   a.n_ch = c->n_ch;
   a.U = c->d_U;
   a.ws = c->d_ws;
+  a.dsp = c->d_dsp;
+  a.dsp_stride = c->n_occ * c->nb_max;
   a.gpart = c->d_gpart;
   a.dpart = c->d_dpart;
   a.gstride = c->gstride;
@@ -330,12 +336,13 @@ SparseArgs sparse_args(exc_ctx* c, int dtype) {
 struct KLaunch {
   const void* fn = nullptr;
   dim3 grid, block{256, 1, 1};
+  size_t shmem = 0;
   void* arg = nullptr;          // points at the single by-value argument struct
 };
 
 hipError_t enqueue(const KLaunch& L, hipStream_t st) {
   void* args[1] = {L.arg};
-  return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st);
+  return hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, st);
 }
 
 hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGraphNode_t* out) {
@@ -345,9 +352,21 @@ hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGrap
   p.gridDim = L.grid;
   p.blockDim = L.block;
   p.kernelParams = args;
-  p.sharedMemBytes = 0;
+  p.sharedMemBytes = (unsigned)L.shmem;
   p.extra = nullptr;
   return hipGraphAddKernelNode(out, g, dep, dep ? 1 : 0, &p);
+}
+
+size_t sparse_lds_bytes(const exc_ctx* c) { return (size_t)4 * (c->n_s + c->n_ch) * sizeof(double2); }
+
+const void* sparse_fn(const exc_ctx* c) {
+  if (c->form != EXC_FORM_CHOL_HERK) return (const void*)sparse_kernel<0, M_F64>;
+  switch (c->precision) {
+    case EXC_FP64: return (const void*)sparse_kernel<1, M_F64>;
+    case EXC_FP32: return (const void*)sparse_kernel<1, M_F32>;
+    case EXC_BF16X3: return (const void*)sparse_kernel<1, M_BF16X3>;
+    default: return (const void*)sparse_kernel<1, M_BF16X6>;
+  }
 }
 
 // Block-sparse rows of pairs [pair0, pair0 + npairs). Returns false when there is nothing to do.
@@ -358,10 +377,9 @@ bool cfg_sparse(exc_ctx* c, int dtype, int pair0, int npairs, SparseArgs& s, KLa
   // dsp is indexed by blockIdx.y: offset it to the first pair
   s.dsp = c->d_dsp ? c->d_dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
   L.grid = dim3((c->n_occ * c->nb_max + 3) / 4, npairs);
-  const bool herk = c->form == EXC_FORM_CHOL_HERK;
-  const bool f64 = c->precision == EXC_FP64;
-  L.fn = !herk ? (const void*)sparse_kernel<0, 1, 0>
-               : (f64 ? (const void*)sparse_kernel<1, 1, 0> : (const void*)sparse_kernel<1, 0, 1>);
+  L.block = dim3(256);
+  L.shmem = sparse_lds_bytes(c);
+  L.fn = sparse_fn(c);
   L.arg = &s;
   return true;
 }
@@ -377,15 +395,12 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   r.dpart = c->d_dpart;
   r.dstride = c->dstride;
   r.use_d64 = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
-  r.pair_begin = c->d_pair_begin + k0;
-  r.pair_w = c->d_pair_w;
-  r.dsp = c->d_dsp;
-  r.dsp_stride = c->n_occ * c->nb_max;
-  r.n_occ = c->n_occ;
   r.vres = c->d_vres;
   r.v_off = c->d_voff + k0;
   r.vout = c->d_vtab + k0;
-  L.grid = dim3((c->nb_max * c->nb_max + 255) / 256, nk);
+  L.grid = dim3(c->nbt_max * (c->nbt_max + 1) / 2, nk);
+  L.block = dim3(256);
+  L.shmem = 0;
   L.fn = r.acc64 ? (const void*)reduce_kernel<1> : (const void*)reduce_kernel<0>;
   L.arg = &r;
 }
@@ -397,6 +412,8 @@ void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persiste
   a.n_items = n;
   a.counter = persistent ? c->d_counter : nullptr;
   L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
+  L.block = dim3(64 * c->cfg->NW);
+  L.shmem = 0;
   L.fn = (const void*)c->cfg->fn;
   L.arg = &a;
 }
@@ -489,11 +506,12 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
     cfg_reduce(c, c->bat, 0, c->n_k, ra, L);
     e = add_node(g, L, &last, &node);
   }
+  const char* where = e == hipSuccess ? "instantiate" : "add node";
   if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     hipGraphDestroy(g);
     c->gexec = nullptr;
-    return fail(c, EXC_EHIP, "building the batched graph failed: %s", hipGetErrorString(e));
+    return fail(c, EXC_EHIP, "building the batched graph failed (%s): %s", where, hipGetErrorString(e));
   }
   if (c->graph) hipGraphDestroy(c->graph);
   c->graph = g;
@@ -691,7 +709,12 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   }
 
   // ---- pairs (k-major), workspace, plans ----
-  const int ldw = c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch;
+  // sparse-row workspace: FP64 -> double2 rows (pitch n_s, or n_s + n_ch with the
+  // GEMM form's multipole corrections); reduced precision -> split planes
+  // [plane][row] per column with the row pitch padded to 8 (elements of lds_t)
+  const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
+  const int ldw = split_ws ? (c->n_s + 7) / 8 * 8 : (c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch);
+  const int ws_cols = split_ws ? 2 * npieces(c->precision) : 1;   // planes per column
   int64_t ws_total = 0, m_max = 0;
   c->k_pair.assign(1, 0);
   for (int k = 0; k < c->n_k; ++k) {
@@ -703,7 +726,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       p.nb8 = (p.nb + 7) / 8 * 8;
       p.m_off = moff; p.ws_off = ws_total; p.u_off = c->u_off[q]; p.ldu = c->ldu[q]; p.ldw = std::max(1, ldw);
       moff += (int64_t)c->n_occ * p.nb * p.nmb;
-      ws_total += (int64_t)c->n_occ * p.nb * ldw;
+      ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
       c->pairs.push_back(p);
       c->pair_w.push_back(c->wq[q]);
       // accounting (nominal: sparse-aware method, Hermitian upper triangle)
@@ -735,7 +758,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(upload(c, &c->d_pairs, c->pairs));
   ITRY(upload(c, &c->d_pair_w, c->pair_w));
   ITRY(upload(c, &c->d_pair_begin, std::vector<int32_t>(c->k_pair.begin(), c->k_pair.end())));
-  const size_t wsz = c->precision == EXC_FP64 ? 16 : 8;
+  const size_t wsz = split_ws ? lds_elem_size(c->precision) : 16;
   ITRY(dalloc(c, (char**)&c->d_ws, (size_t)std::max<int64_t>(1, ws_total) * wsz));
   if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
     ITRY(dalloc(c, &c->d_dsp, c->pairs.size() * (size_t)c->n_occ * c->nb_max));
@@ -769,9 +792,20 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(dalloc(c, &c->d_counter, 1));
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
 
+  {
+    hipFuncAttributes fa{};
+    IHIP(hipFuncGetAttributes(&fa, (const void*)c->cfg->fn));
+    if (fa.maxThreadsPerBlock < 64 * c->cfg->NW) {
+      fail(c, EXC_EUNSUPPORTED, "tile kernel %d allows %d threads per block, needs %d", c->cfg->id,
+           fa.maxThreadsPerBlock, 64 * c->cfg->NW);
+      return bail(EXC_EUNSUPPORTED);
+    }
+  }
   int n_cu = 0, occ = 0;
   IHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 256, 0));
+  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 64 * c->cfg->NW, 0));
+  if (sparse_lds_bytes(c) > 65536)
+    IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   c->persist_grid = std::max(1, n_cu * std::max(1, occ));
   IHIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   IHIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));

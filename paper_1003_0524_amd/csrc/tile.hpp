@@ -16,24 +16,29 @@
 // so a complex multiply-add costs 4 real multiply-adds and odd band counts
 // waste at most 7 columns.
 //
-// Partials: each work item (pair (k,q), a group of n'' values, a range of row
-// blocks) accumulates 16x16 real Gram tiles G(I,J), I <= J over 8-column band
-// tiles, and writes them (plus, in the reduced-precision modes, an FP64 sum of
-// |Y|^2 per band) to its own slot. A separate kernel sums the slots of each k
-// in a fixed order in FP64 (deterministic).
+// Work decomposition: NW wavefronts split the BM rows of a row block; the K
+// loop stages row panels of B and column panels of A through NBUF LDS buffers
+// (with two: one barrier per chunk; global loads for chunk i+1 are in flight
+// while chunk i runs on MFMA). The contraction stages one n'' group of Y at a time in LDS and
+// each wavefront owns a subset of the 16x16 Gram tiles G(I,J), I <= J.
+//
+// Partials: each work item (pair (k,q), a range of n'' values, a range of row
+// blocks) writes its Gram tiles (plus, in the reduced-precision modes, an FP64
+// sum of |Y|^2 per band) to its own slot; a separate kernel sums the slots of
+// each k in a fixed order in FP64 (deterministic).
 #pragma once
 #include "common.hpp"
 
 namespace exc {
 
 struct PairInfo {
-  int32_t k, q, nb, nmb;   // k, q, bands n_b(k), N_MB(q)
+  int32_t k, q, nb, nmb;     // k, q, bands n_b(k), N_MB(q)
   int32_t nd, nsb, nb8, ndb; // N_d(q), sparse row blocks, n_b rounded to 8, dense row blocks
-  int64_t m_off;           // complex elements of block (k,q) inside M_k[k]
-  int64_t ws_off;          // complex elements of the pair's sparse block inside the workspace
-  int64_t u_off;           // lds_t elements of plane 0 of q inside the prepared factor
-  int32_t ldu;             // padded order of the factor of q (multiple of 128)
-  int32_t ldw;             // column length of the sparse workspace block
+  int64_t m_off;             // complex elements of block (k,q) inside M_k[k]
+  int64_t ws_off;            // elements (see ldw) of the pair's sparse block inside the workspace
+  int64_t u_off;             // lds_t elements of plane 0 of q inside the prepared factor
+  int32_t ldu;               // padded order of the factor of q (multiple of 128)
+  int32_t ldw;               // row pitch of one column (one plane) of the sparse workspace
 };
 // One work item: pair (k,q); n'' values [g0, g1) processed ngc at a time (each
 // chunk is one pass of the K loop over ngc * n_b columns); row blocks [rb0, rb1)
@@ -47,9 +52,11 @@ struct TileArgs {
   int32_t* counter;              // non-null: persistent mode (atomic work counter)
   const void* const* mtab;       // [n_k] device pointers to M_k
   int32_t m_c64;                 // 1: M holds complex64
-  int32_t n_s, n_ch;
+  int32_t n_s, n_ch, n_occ;
   const void* U;                 // prepared factor planes
-  const void* ws;                // sparse workspace (complex, double2 or float2)
+  const void* ws;                // sparse workspace: double2 (FP64) or split planes (others)
+  const double* dsp;             // reduced precision: FP64 sum_r |Y_s|^2 per (pair, n'', n)
+  int32_t dsp_stride;            // n_occ * nb_max
   void* gpart;                   // Gram-tile partials, acc_t
   double* dpart;                 // FP64 diagonal partials
   int32_t gstride, dstride;      // elements per slot
@@ -63,37 +70,48 @@ __device__ __forceinline__ void tp_to_ij(int tp, int& I, int& J) {
   I = tp - j * (j + 1) / 2;
 }
 
-template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M>
+template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NW, int NBUF>
 struct TileCfg {
   using T = Traits<MODE>;
   using acc_t = typename T::acc_t;
   using lds_t = typename T::lds_t;
   using accv_t = typename T::accv_t;
-  static constexpr int NP = T::NPIECE, KS = T::KS, KPL = KS / 4;   // k values each of the 4 lane groups supplies
-  static constexpr int BMW = BM / 4, RT = BMW / 16;
+  static constexpr int NT = 64 * NW;                    // threads
+  static constexpr int NP = T::NPIECE, KS = T::KS;
+  static constexpr int KPL = KS / 4;                    // k values each of the 4 lane groups supplies
+  static constexpr int BMW = BM / NW, RT = BMW / 16;
+  static_assert(RT >= 1 && BMW % 16 == 0, "each wavefront owns whole 16-row tiles");
   static constexpr int NCC = NCT * 8;
   static constexpr int PADE = 16 / (int)sizeof(lds_t);
   static constexpr int LDK = KC + PADE;
   static constexpr int LDR = BM + PADE;
-  static constexpr int US_SZ = 2 * NP * BM * LDK;
-  static constexpr int AS_SZ = 2 * NP * NCC * LDK;
-  static constexpr int YPL = NB8M * 8 * LDR;              // one plane of the group stage
-  static constexpr int YS_SZ = 2 * NP * YPL;
-  static constexpr int LPL = NB8M * 8 * (BM + 2);         // GEMM left operand (double)
+  static constexpr int NPL = 2 * NP;                    // planes: re pieces, im pieces
+  static constexpr int UPL = BM * LDK;                  // one plane of the B stage
+  static constexpr int APL = NCC * LDK;                 // one plane of the A stage
+  static constexpr int STAGE = NPL * (UPL + APL);       // lds_t elements of one K-loop buffer
+  static constexpr int YPL = NB8M * 8 * LDR;            // one plane of the group stage
+  static constexpr int YS_SZ = NPL * YPL;
+  static constexpr int LPL = NB8M * 8 * (BM + 2);       // GEMM left operand (double)
   static constexpr int LS_SZ = (FORM == 0) ? 2 * LPL : 0;
   static constexpr int NPT = NB8M * (NB8M + 1) / 2;
-  static constexpr int NPW = (NPT + 3) / 4;
-  static constexpr size_t KLOOP_B = (size_t)(US_SZ + AS_SZ) * sizeof(lds_t);
+  static constexpr int NPW = (NPT + NW - 1) / NW;
+  // Many Gram tiles per wave (large n_b) do not fit in registers next to the Y
+  // accumulators: then each tile is accumulated for one row block at a time and
+  // added into the item's private partial slot in global memory.
+  static constexpr bool GSTREAM = NPW * 4 * (int)sizeof(acc_t) / 4 > 32;
+  static constexpr size_t KLOOP_B = (size_t)NBUF * STAGE * sizeof(lds_t);
   static constexpr size_t STAGE_B = ((size_t)YS_SZ * sizeof(lds_t) + 15) / 16 * 16 + (size_t)LS_SZ * 8;
-  static constexpr size_t DIAG_B = (size_t)4 * NCC * sizeof(double);
-  static constexpr size_t LDS_B = KLOOP_B > STAGE_B ? (KLOOP_B > DIAG_B ? KLOOP_B : DIAG_B)
-                                                    : (STAGE_B > DIAG_B ? STAGE_B : DIAG_B);
-  // per-thread prefetch counts (16-byte units for U; k-pairs for A)
+  static constexpr size_t MAIN_B = KLOOP_B > STAGE_B ? KLOOP_B : STAGE_B;
+  static constexpr size_t DACC_B = (MODE != M_F64 && FORM == 1) ? (size_t)NW * NCC * 2 * sizeof(double) : 0;
+  static constexpr size_t LDS_B = MAIN_B + DACC_B;
+  static_assert(LDS_B + 16 <= 163840, "tile configuration exceeds the 160 KB of LDS");
+  static_assert(NBUF == 1 || NBUF == 2, "one or two K-loop buffers");
+  // per-thread prefetch counts (16-byte units for B; k-pairs for A)
   static constexpr int UV_PER_PLANE = BM * KC * (int)sizeof(lds_t) / 16;
-  static constexpr int UV_TOTAL = 2 * NP * UV_PER_PLANE;
-  static constexpr int UV_PT = (UV_TOTAL + 255) / 256;
+  static constexpr int UV_TOTAL = NPL * UV_PER_PLANE;
+  static constexpr int UV_PT = (UV_TOTAL + NT - 1) / NT;
   static constexpr int AV_TOTAL = NCC * KC / 2;
-  static constexpr int AV_PT = (AV_TOTAL + 255) / 256;
+  static constexpr int AV_PT = (AV_TOTAL + NT - 1) / NT;
 };
 
 // Load the operand a lane supplies for one MFMA from an LDS row (k contiguous).
@@ -106,24 +124,23 @@ __device__ __forceinline__ auto lds_operand(const typename Traits<MODE>::lds_t* 
   }
 }
 
-template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M>
-__global__ __launch_bounds__(256, 1) void tile_kernel(TileArgs a) {
-  using C = TileCfg<MODE, FORM, BM, KC, NCT, NB8M>;
+template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NW, int NBUF>
+__global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
+  using C = TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>;
   using acc_t = typename C::acc_t;
   using lds_t = typename C::lds_t;
   using accv_t = typename C::accv_t;
-  constexpr int NP = C::NP, KS = C::KS, KPL = C::KPL, RT = C::RT, BMW = C::BMW;
-  constexpr int LDK = C::LDK, LDR = C::LDR, YPL = C::YPL;
+  constexpr int NT = C::NT, NP = C::NP, KS = C::KS, KPL = C::KPL, RT = C::RT, BMW = C::BMW;
+  constexpr int LDK = C::LDK, LDR = C::LDR, YPL = C::YPL, UPL = C::UPL, APL = C::APL;
   constexpr bool HERK = (FORM == 1);
   constexpr bool DIAG64 = HERK && (MODE != M_F64);
+  constexpr int ESZ = (int)sizeof(lds_t);
 
   __shared__ __align__(16) unsigned char smem[C::LDS_B];
   __shared__ int s_item;
-  lds_t* Us = (lds_t*)smem;
-  lds_t* As = Us + C::US_SZ;
   lds_t* Ys = (lds_t*)smem;
   double* Ls = (double*)(smem + ((size_t)C::YS_SZ * sizeof(lds_t) + 15) / 16 * 16);
-  double* Dsum = (double*)smem;
+  double* Dacc = (double*)(smem + C::MAIN_B);   // [NW][NCC][2] per-wave diagonal sums (re, im parts)
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;       // MFMA row/col within tile, k group
@@ -134,7 +151,9 @@ __global__ __launch_bounds__(256, 1) void tile_kernel(TileArgs a) {
     if (a.counter) {
       if (tid == 0) s_item = atomicAdd(a.counter, 1);
       __syncthreads();
-      idx = s_item;
+      // uniform across the workgroup: keep the item and everything derived from it
+      // in scalar registers
+      idx = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
     } else {
       if (iter > 0) break;
@@ -150,149 +169,159 @@ __global__ __launch_bounds__(256, 1) void tile_kernel(TileArgs a) {
     const int esz = a.m_c64 ? 8 : 16;
     const char* mbase = (const char*)a.mtab[pi.k] + pi.m_off * esz;
 
-    accv_t gacc[C::NPW];
+    constexpr int NPWR = C::GSTREAM ? 1 : C::NPW;   // Gram tiles held in registers
+    accv_t gacc[NPWR];
 #pragma unroll
-    for (int s = 0; s < C::NPW; ++s) gacc[s] = accv_t{0, 0, 0, 0};
-    double dacc[NCT];
-#pragma unroll
-    for (int t = 0; t < NCT; ++t) dacc[t] = 0.0;
+    for (int s = 0; s < NPWR; ++s) gacc[s] = accv_t{0, 0, 0, 0};
+    acc_t* gp = (acc_t*)a.gpart + (long)wi.slot * a.gstride;
+    if constexpr (C::GSTREAM) {
+      for (int s = 0; s < C::NPW; ++s) {
+        const int tp = w + NW * s;
+        if (tp < npt)
+          for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] = (acc_t)0;
+      }
+    }
+    if constexpr (DIAG64) {
+      for (int e = tid; e < NW * C::NCC * 2; e += NT) Dacc[e] = 0.0;
+    }
 
     for (int gbase = wi.g0; gbase < wi.g1; gbase += wi.ngc) {
-    const int ng = min(wi.ngc, wi.g1 - gbase);
-    const int nct = ng * nbt;
-    const int ncols = ng * nb8;
-    for (int rb = wi.rb0; rb < wi.rb1; ++rb) {
-      const bool sparse = rb < pi.nsb;
-      const int r0 = sparse ? rb * BM : (rb - pi.nsb) * BM;  // first row (sparse or dense coords)
+      const int ng = min(wi.ngc, wi.g1 - gbase);
+      const int nct = ng * nbt;
+      const int ncols = ng * nb8;
+      for (int rb = wi.rb0; rb < wi.rb1; ++rb) {
+        const bool sparse = rb < pi.nsb;
+        const int r0 = sparse ? rb * BM : (rb - pi.nsb) * BM;  // first row (sparse or dense coords)
 
-      accv_t yacc[RT][NCT];
-      if (!sparse) {
-        // ---------------- dense rows: K loop on MFMA ----------------
+        accv_t yacc[RT][NCT];
+        if (!sparse) {
+          // ---------------- dense rows: K loop on MFMA ----------------
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+          for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) yacc[rt][ct] = accv_t{0, 0, 0, 0};
-        const int kc0 = HERK ? (r0 / KC) * KC : 0;
-        const int kc1 = (nd + KC - 1) / KC * KC;
-        const lds_t* Ug = (const lds_t*)a.U + pi.u_off;
-        const long plane = (long)pi.ldu * pi.ldu;
+            for (int ct = 0; ct < NCT; ++ct) yacc[rt][ct] = accv_t{0, 0, 0, 0};
+          const int kc0 = HERK ? (r0 / KC) * KC : 0;
+          const int kc1 = (nd + KC - 1) / KC * KC;
+          const int nch = (kc1 - kc0) / KC;
+          const lds_t* Ug = (const lds_t*)a.U + pi.u_off;
+          const long plane = (long)pi.ldu * pi.ldu;
 
-        u4_t ureg[C::UV_PT];
-        u4_t areg[C::AV_PT][2];
-        auto prefetch = [&](int kc) {
+          u4_t ureg[C::UV_PT];
+          u4_t areg0[C::AV_PT], areg1[C::AV_PT];   // complex k, k+1 (complex128) or both (complex64)
+          auto prefetch = [&](int kc) {
 #pragma unroll
-          for (int j = 0; j < C::UV_PT; ++j) {
-            const int v = tid + 256 * j;
-            if (v < C::UV_TOTAL) {
-              const int pl = v / C::UV_PER_PLANE, rem = v % C::UV_PER_PLANE;
-              constexpr int VPR = KC * (int)sizeof(lds_t) / 16;   // 16-byte vectors per row
-              const int row = rem / VPR, kv = rem % VPR;
-              const lds_t* src = Ug + pl * plane + (long)(r0 + row) * pi.ldu + kc + kv * (16 / (int)sizeof(lds_t));
-              ureg[j] = *(const u4_t*)src;
+            for (int j = 0; j < C::UV_PT; ++j) {
+              const int v = tid + NT * j;
+              if (v < C::UV_TOTAL) {
+                const int pl = v / C::UV_PER_PLANE, rem = v % C::UV_PER_PLANE;
+                constexpr int VPR = KC * ESZ / 16;   // 16-byte vectors per row
+                const int row = rem / VPR, kv = rem % VPR;
+                const lds_t* src = Ug + pl * plane + (long)(r0 + row) * pi.ldu + kc + kv * (16 / ESZ);
+                ureg[j] = *(const u4_t*)src;
+              }
             }
-          }
 #pragma unroll
-          for (int j = 0; j < C::AV_PT; ++j) {
-            const int v = tid + 256 * j;
-            areg[j][0] = u4_t{0, 0, 0, 0};
-            areg[j][1] = u4_t{0, 0, 0, 0};
-            if (v < C::AV_TOTAL) {
+            for (int j = 0; j < C::AV_PT; ++j) {
+              const int v = tid + NT * j;
+              u4_t x0 = u4_t{0, 0, 0, 0}, x1 = u4_t{0, 0, 0, 0};
               const int c = v / (KC / 2), kp = v % (KC / 2);
               const int g = c / nb8, n = c - g * nb8;
               const int kk = kc + 2 * kp;
-              if (c < ncols && n < nb && kk < nd) {
+              if (v < C::AV_TOTAL && c < ncols && n < nb && kk < nd) {
                 const long e = ((long)(gbase + g) * nb + n) * pi.nmb + a.n_s + kk;
                 if (a.m_c64) {
                   const float* p = (const float*)mbase + 2 * e;
-                  const float2 x0 = *(const float2*)p;
-                  float2 x1 = make_float2(0.f, 0.f);
-                  if (kk + 1 < nd) x1 = *(const float2*)(p + 2);
-                  areg[j][0] = u4_t{__float_as_uint(x0.x), __float_as_uint(x0.y),
-                                    __float_as_uint(x1.x), __float_as_uint(x1.y)};
+                  const float2 f0 = *(const float2*)p;
+                  const float2 f1 = (kk + 1 < nd) ? *(const float2*)(p + 2) : make_float2(0.f, 0.f);
+                  x0 = u4_t{__float_as_uint(f0.x), __float_as_uint(f0.y), __float_as_uint(f1.x), __float_as_uint(f1.y)};
                 } else {
                   const u4_t* p = (const u4_t*)(mbase + 16 * e);
-                  areg[j][0] = p[0];
-                  if (kk + 1 < nd) areg[j][1] = p[1];
+                  x0 = p[0];
+                  if (kk + 1 < nd) x1 = p[1];
+                }
+              }
+              areg0[j] = x0;
+              areg1[j] = x1;
+            }
+          };
+          auto stage = [&](lds_t* Us, lds_t* As) {
+#pragma unroll
+            for (int j = 0; j < C::UV_PT; ++j) {
+              const int v = tid + NT * j;
+              if (v < C::UV_TOTAL) {
+                const int pl = v / C::UV_PER_PLANE, rem = v % C::UV_PER_PLANE;
+                constexpr int VPR = KC * ESZ / 16;
+                const int row = rem / VPR, kv = rem % VPR;
+                *(u4_t*)(Us + pl * UPL + row * LDK + kv * (16 / ESZ)) = ureg[j];
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < C::AV_PT; ++j) {
+              const int v = tid + NT * j;
+              if (v < C::AV_TOTAL) {
+                const int c = v / (KC / 2), kp = v % (KC / 2);
+                double re0, im0, re1, im1;
+                const u4_t x0 = areg0[j], x1 = areg1[j];
+                if (a.m_c64) {
+                  re0 = __uint_as_float(x0.x); im0 = __uint_as_float(x0.y);
+                  re1 = __uint_as_float(x0.z); im1 = __uint_as_float(x0.w);
+                } else {
+                  re0 = __hiloint2double(x0.y, x0.x);
+                  im0 = __hiloint2double(x0.w, x0.z);
+                  re1 = __hiloint2double(x1.y, x1.x);
+                  im1 = __hiloint2double(x1.w, x1.z);
+                }
+                lds_t* d = As + c * LDK + 2 * kp;
+                if constexpr (MODE == M_F64) {
+                  *(double2*)(d) = make_double2(re0, re1);
+                  *(double2*)(d + NP * APL) = make_double2(im0, im1);
+                } else if constexpr (MODE == M_F32) {
+                  *(float2*)(d) = make_float2((float)re0, (float)re1);
+                  *(float2*)(d + NP * APL) = make_float2((float)im0, (float)im1);
+                } else {
+                  uint16_t h0[NP], h1[NP], g0[NP], g1[NP];
+                  split_d<NP>(re0, h0); split_d<NP>(re1, h1);
+                  split_d<NP>(im0, g0); split_d<NP>(im1, g1);
+#pragma unroll
+                  for (int p = 0; p < NP; ++p) {
+                    *(uint32_t*)(d + p * APL) = (uint32_t)h0[p] | ((uint32_t)h1[p] << 16);
+                    *(uint32_t*)(d + (NP + p) * APL) = (uint32_t)g0[p] | ((uint32_t)g1[p] << 16);
+                  }
                 }
               }
             }
-          }
-        };
-        auto stage = [&]() {
-#pragma unroll
-          for (int j = 0; j < C::UV_PT; ++j) {
-            const int v = tid + 256 * j;
-            if (v < C::UV_TOTAL) {
-              const int pl = v / C::UV_PER_PLANE, rem = v % C::UV_PER_PLANE;
-              constexpr int VPR = KC * (int)sizeof(lds_t) / 16;
-              const int row = rem / VPR, kv = rem % VPR;
-              *(u4_t*)(Us + pl * (BM * LDK) + row * LDK + kv * (16 / (int)sizeof(lds_t))) = ureg[j];
-            }
-          }
-          constexpr int APL = C::NCC * LDK;   // one plane of As
-#pragma unroll
-          for (int j = 0; j < C::AV_PT; ++j) {
-            const int v = tid + 256 * j;
-            if (v < C::AV_TOTAL) {
-              const int c = v / (KC / 2), kp = v % (KC / 2);
-              double re0, im0, re1, im1;
-              if (a.m_c64) {
-                re0 = __uint_as_float(areg[j][0].x); im0 = __uint_as_float(areg[j][0].y);
-                re1 = __uint_as_float(areg[j][0].z); im1 = __uint_as_float(areg[j][0].w);
-              } else {
-                re0 = __hiloint2double(areg[j][0].y, areg[j][0].x);
-                im0 = __hiloint2double(areg[j][0].w, areg[j][0].z);
-                re1 = __hiloint2double(areg[j][1].y, areg[j][1].x);
-                im1 = __hiloint2double(areg[j][1].w, areg[j][1].z);
-              }
-              lds_t* d = As + c * LDK + 2 * kp;
-              if constexpr (MODE == M_F64) {
-                *(double2*)(d) = make_double2(re0, re1);
-                *(double2*)(d + NP * APL) = make_double2(im0, im1);
-              } else if constexpr (MODE == M_F32) {
-                *(float2*)(d) = make_float2((float)re0, (float)re1);
-                *(float2*)(d + NP * APL) = make_float2((float)im0, (float)im1);
-              } else {
-                uint16_t h0[NP], h1[NP], g0[NP], g1[NP];
-                split_d<NP>(re0, h0); split_d<NP>(re1, h1);
-                split_d<NP>(im0, g0); split_d<NP>(im1, g1);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                  *(uint32_t*)(d + p * APL) = (uint32_t)h0[p] | ((uint32_t)h1[p] << 16);
-                  *(uint32_t*)(d + (NP + p) * APL) = (uint32_t)g0[p] | ((uint32_t)g1[p] << 16);
-                }
-              }
-            }
-          }
-        };
+          };
 
-        prefetch(kc0);
-        for (int kc = kc0; kc < kc1; kc += KC) {
+          lds_t* buf0 = (lds_t*)smem;
+          lds_t* buf1 = buf0 + (NBUF == 2 ? C::STAGE : 0);
+          __syncthreads();                      // previous users of the LDS are done
+          prefetch(kc0);
+          stage(buf0, buf0 + C::NPL * UPL);
           __syncthreads();
-          stage();
-          __syncthreads();
-          if (kc + KC < kc1) prefetch(kc + KC);
+          for (int i = 0; i < nch; ++i) {
+            lds_t* Us = (i & 1) ? buf1 : buf0;
+            lds_t* As = Us + C::NPL * UPL;
+            if (i + 1 < nch) prefetch(kc0 + (i + 1) * KC);
 #pragma unroll
-          for (int ks = 0; ks < KC / KS; ++ks) {
-            const int kofs = ks * KS + KPL * lq;
+            for (int ks = 0; ks < KC / KS; ++ks) {
+              const int kofs = ks * KS + KPL * lq;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              decltype(lds_operand<MODE>(Us)) aop[RT][NP];
+              for (int h = 0; h < 2; ++h) {
+                decltype(lds_operand<MODE>(Us)) aop[RT][NP];
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt)
+                for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int p = 0; p < NP; ++p)
-                  aop[rt][p] = lds_operand<MODE>(Us + (h * NP + p) * (BM * LDK) +
-                                                 (w * BMW + rt * 16 + l16) * LDK + kofs);
-              const int bpart = part ^ h;
-              const bool neg = (h == 1) && (part == 0);
+                  for (int p = 0; p < NP; ++p)
+                    aop[rt][p] = lds_operand<MODE>(Us + (h * NP + p) * UPL + (w * BMW + rt * 16 + l16) * LDK + kofs);
+                const int bpart = part ^ h;
+                const bool neg = (h == 1) && (part == 0);
+                // all NCT column tiles: columns beyond the item are zero in LDS
 #pragma unroll
-              for (int ct = 0; ct < NCT; ++ct) {
-                if (ct < nct) {
+                for (int ct = 0; ct < NCT; ++ct) {
                   decltype(lds_operand<MODE>(As)) bop[NP];
 #pragma unroll
                   for (int p = 0; p < NP; ++p) {
-                    bop[p] = lds_operand<MODE>(As + (bpart * NP + p) * (C::NCC * LDK) + (ct * 8 + c8) * LDK + kofs);
+                    bop[p] = lds_operand<MODE>(As + (bpart * NP + p) * APL + (ct * 8 + c8) * LDK + kofs);
                     if (neg) bop[p] = negate(bop[p]);
                   }
 #pragma unroll
@@ -308,119 +337,131 @@ __global__ __launch_bounds__(256, 1) void tile_kernel(TileArgs a) {
                 }
               }
             }
+            if (i + 1 < nch) {
+              if constexpr (NBUF == 1) __syncthreads();   // every wave is done with the only buffer
+              stage((i & 1) ? buf0 : buf1, ((i & 1) ? buf0 : buf1) + C::NPL * UPL);
+            }
+            __syncthreads();
           }
-        }
-        if constexpr (DIAG64) {
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const double y = (double)yacc[rt][ct][i];
-                dacc[ct] += y * y;
-              }
-        }
-        if constexpr (!HERK) {
-          // W rows of the multipole functions receive C_c^H A_c from the sparse kernel
-          if (r0 < a.n_ch) {
-            const double* X = (const double*)a.ws + 2 * pi.ws_off;
+          if constexpr (DIAG64) {
+            // FP64 sums of |Y|^2 per real column; the four lanes of one column are
+            // reduced first so that each wave owns its Dacc row (no races, fixed order)
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct) {
-              if (ct < nct) {
-                const int c = ct * 8 + c8, g = c / nb8, n = c - g * nb8;
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    const int d = r0 + w * BMW + rt * 16 + acc_row<MODE>(lq, i);
-                    if (d < a.n_ch && n < nb)
-                      yacc[rt][ct][i] += X[2 * (((long)(gbase + g) * nb + n) * pi.ldw + a.n_s + d) + part];
-                  }
-              }
-            }
-          }
-        }
-      }
-
-      // ---------------- per n'' group: stage rows, contract ----------------
-      for (int g = 0; g < ng; ++g) {
-        __syncthreads();
-        if (!sparse) {
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) {
-            if (ct >= g * nbt && ct < (g + 1) * nbt) {
-              const int cl = (ct - g * nbt) * 8 + c8;
+              double d = 0.0;
 #pragma unroll
               for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  const int row = w * BMW + rt * 16 + acc_row<MODE>(lq, i);
-                  if constexpr (MODE == M_F64)
-                    Ys[(part * NP) * YPL + cl * LDR + row] = yacc[rt][ct][i];
-                  else
-                    put_realf<MODE>(Ys + (part * NP) * YPL + cl * LDR + row, YPL, (float)yacc[rt][ct][i]);
+                  const double y = (double)yacc[rt][ct][i];
+                  d += y * y;
                 }
+              d += __shfl_xor(d, 16);
+              d += __shfl_xor(d, 32);
+              if (lq == 0) Dacc[(w * C::NCC + ct * 8 + c8) * 2 + part] += d;
             }
           }
           if constexpr (!HERK) {
-            // left operand: A_d rows [r0, r0+BM) of group g, FP64
-            for (int e = tid; e < nb8 * BM; e += 256) {
-              const int cl = e / BM, row = e - cl * BM;
-              const int d = r0 + row;
-              double re = 0.0, im = 0.0;
-              if (cl < nb && d < nd) {
-                const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + a.n_s + d));
-                re = p[0]; im = p[1];
+            // W rows of the multipole functions receive C_c^H A_c from the sparse kernel
+            if (r0 < a.n_ch) {
+              const double* X = (const double*)a.ws + 2 * pi.ws_off;
+#pragma unroll
+              for (int ct = 0; ct < NCT; ++ct) {
+                if (ct < nct) {
+                  const int c = ct * 8 + c8, g = c / nb8, n = c - g * nb8;
+#pragma unroll
+                  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                      const int d = r0 + w * BMW + rt * 16 + acc_row<MODE>(lq, i);
+                      if (d < a.n_ch && n < nb)
+                        yacc[rt][ct][i] += X[2 * (((long)(gbase + g) * nb + n) * pi.ldw + a.n_s + d) + part];
+                    }
+                }
               }
-              Ls[cl * (BM + 2) + row] = re;
-              Ls[C::LPL + cl * (BM + 2) + row] = im;
-            }
-          }
-        } else {
-          // sparse rows: Y_s (HERK) or W_s (GEMM) from the workspace, A_s for GEMM
-          for (int e = tid; e < nb8 * BM; e += 256) {
-            const int cl = e / BM, row = e - cl * BM;
-            const int r = r0 + row;
-            double re = 0.0, im = 0.0;
-            if (cl < nb && r < a.n_s) {
-              const long wo = pi.ws_off + ((long)(gbase + g) * nb + cl) * pi.ldw + r;
-              if constexpr (MODE == M_F64) {
-                const double2 v = ((const double2*)a.ws)[wo];
-                re = v.x; im = v.y;
-              } else {
-                const float2 v = ((const float2*)a.ws)[wo];
-                re = v.x; im = v.y;
-              }
-            }
-            lds_t* d = Ys + cl * LDR + row;
-            if constexpr (MODE == M_F64) {
-              d[0] = re; d[NP * YPL] = im;
-            } else {
-              put_realf<MODE>(d, YPL, (float)re);
-              put_realf<MODE>(d + NP * YPL, YPL, (float)im);
-            }
-            if constexpr (!HERK) {
-              double lre = 0.0, lim = 0.0;
-              if (cl < nb && r < a.n_s) {
-                const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + r));
-                lre = p[0]; lim = p[1];
-              }
-              Ls[cl * (BM + 2) + row] = lre;
-              Ls[C::LPL + cl * (BM + 2) + row] = lim;
             }
           }
         }
-        __syncthreads();
-        // contraction: this wave's Gram tiles, K = BM rows
+
+        // ---------------- per n'' group: stage rows, contract ----------------
+        for (int g = 0; g < ng; ++g) {
+          __syncthreads();
+          if (!sparse) {
 #pragma unroll
-        for (int s = 0; s < C::NPW; ++s) {
-          const int tp = w + 4 * s;
-          if (tp < npt) {
+            for (int ct = 0; ct < NCT; ++ct) {
+              if (ct >= g * nbt && ct < (g + 1) * nbt) {
+                const int cl = (ct - g * nbt) * 8 + c8;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    const int row = w * BMW + rt * 16 + acc_row<MODE>(lq, i);
+                    if constexpr (MODE == M_F64)
+                      Ys[(part * NP) * YPL + cl * LDR + row] = yacc[rt][ct][i];
+                    else
+                      put_realf<MODE>(Ys + (part * NP) * YPL + cl * LDR + row, YPL, (float)yacc[rt][ct][i]);
+                  }
+              }
+            }
+            if constexpr (!HERK) {
+              // left operand: A_d rows [r0, r0+BM) of group g, FP64
+              for (int e = tid; e < nb8 * BM; e += NT) {
+                const int cl = e / BM, row = e - cl * BM;
+                const int d = r0 + row;
+                double re = 0.0, im = 0.0;
+                if (cl < nb && d < nd) {
+                  const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + a.n_s + d));
+                  re = p[0]; im = p[1];
+                }
+                Ls[cl * (BM + 2) + row] = re;
+                Ls[C::LPL + cl * (BM + 2) + row] = im;
+              }
+            }
+          } else if constexpr (MODE == M_F64) {
+            // sparse rows: Y_s (HERK) or W_s (GEMM) as double2 from the workspace, A_s for GEMM
+            for (int e = tid; e < nb8 * BM; e += NT) {
+              const int cl = e / BM, row = e - cl * BM;
+              const int r = r0 + row;
+              double re = 0.0, im = 0.0;
+              if (cl < nb && r < a.n_s) {
+                const double2 v = ((const double2*)a.ws)[pi.ws_off + ((long)(gbase + g) * nb + cl) * pi.ldw + r];
+                re = v.x; im = v.y;
+              }
+              Ys[cl * LDR + row] = re;
+              Ys[YPL + cl * LDR + row] = im;
+              if constexpr (!HERK) {
+                double lre = 0.0, lim = 0.0;
+                if (cl < nb && r < a.n_s) {
+                  const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + r));
+                  lre = p[0]; lim = p[1];
+                }
+                Ls[cl * (BM + 2) + row] = lre;
+                Ls[C::LPL + cl * (BM + 2) + row] = lim;
+              }
+            }
+          } else {
+            // sparse rows, reduced precision: the block-sparse kernel wrote Y_s already split
+            // into planes [n''][n][plane][row] (pitch ldw, zero padded to 8 rows): 16-byte copies
+            constexpr int EPV = 16 / ESZ;                       // elements per 16-byte vector
+            constexpr int VPC = BM / EPV;                       // vectors per column and plane
+            const lds_t* src = (const lds_t*)a.ws + pi.ws_off;
+            for (int v = tid; v < C::NPL * nb8 * VPC; v += NT) {
+              const int pl = v / (nb8 * VPC), rem = v - pl * (nb8 * VPC);
+              const int cl = rem / VPC, rv = rem - cl * VPC;
+              const int r = r0 + rv * EPV;
+              u4_t x = u4_t{0, 0, 0, 0};
+              if (cl < nb && r < pi.ldw)
+                x = *(const u4_t*)(src + (((long)(gbase + g) * nb + cl) * C::NPL + pl) * pi.ldw + r);
+              *(u4_t*)(Ys + pl * YPL + cl * LDR + rv * EPV) = x;
+            }
+          }
+          __syncthreads();
+          // contraction: this wave's Gram tiles, K = BM rows
+          auto contract = [&](int tp, accv_t acc) -> accv_t {
             int I, J;
             tp_to_ij(tp, I, J);
             const int cA = I * 8 + c8, cB = J * 8 + c8;
-#pragma unroll
+#pragma unroll 2
             for (int ks = 0; ks < BM / KS; ++ks) {
               const int kofs = ks * KS + KPL * lq;
               if constexpr (HERK) {
@@ -431,50 +472,60 @@ __global__ __launch_bounds__(256, 1) void tile_kernel(TileArgs a) {
                   bo[p] = lds_operand<MODE>(Ys + (part * NP + p) * YPL + cB * LDR + kofs);
                 }
                 if constexpr (NP == 1) {
-                  gacc[s] = mfma(ao[0], bo[0], gacc[s]);
+                  acc = mfma(ao[0], bo[0], acc);
                 } else {
 #pragma unroll
                   for (int pr = 0; pr < C::T::NPROD; ++pr)
-                    gacc[s] = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], gacc[s]);
+                    acc = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], acc);
                 }
               } else {
                 const double ao = Ls[part * C::LPL + cA * (BM + 2) + kofs];
                 const double bo = Ys[part * YPL + cB * LDR + kofs];
-                gacc[s] = mfma(ao, bo, gacc[s]);
+                acc = mfma(ao, bo, acc);
               }
+            }
+            return acc;
+          };
+          if constexpr (C::GSTREAM) {
+            for (int s = 0; s < C::NPW; ++s) {
+              const int tp = w + NW * s;
+              if (tp >= npt) break;
+              const accv_t acc = contract(tp, accv_t{0, 0, 0, 0});
+#pragma unroll
+              for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] += acc[i];
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < NPWR; ++s) {
+              const int tp = w + NW * s;
+              if (tp < npt) gacc[s] = contract(tp, gacc[s]);
             }
           }
         }
       }
-    }
-
     }  // n'' chunks
 
     // ---------------- write the item's partials ----------------
-    acc_t* gp = (acc_t*)a.gpart + (long)wi.slot * a.gstride;
+    if constexpr (!C::GSTREAM) {
 #pragma unroll
-    for (int s = 0; s < C::NPW; ++s) {
-      const int tp = w + 4 * s;
-      if (tp < npt) {
+      for (int s = 0; s < NPWR; ++s) {
+        const int tp = w + NW * s;
+        if (tp < npt) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] = gacc[s][i];
+          for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] = gacc[s][i];
+        }
       }
     }
     if constexpr (DIAG64) {
       __syncthreads();
-#pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) {
-        double d = dacc[ct];
-        d += __shfl_xor(d, 16);
-        d += __shfl_xor(d, 32);
-        d += __shfl_xor(d, 8);
-        if (lane < 8) Dsum[w * C::NCC + ct * 8 + lane] = d;
-      }
-      __syncthreads();
-      for (int n = tid; n < nb8; n += 256) {
+      for (int n = tid; n < nb8; n += NT) {
         double s = 0.0;
         for (int c = n; c < C::NCC; c += nb8)   // same band in every group position
-          for (int ww = 0; ww < 4; ++ww) s += Dsum[ww * C::NCC + c];
+          for (int ww = 0; ww < NW; ++ww) s += Dacc[(ww * C::NCC + c) * 2] + Dacc[(ww * C::NCC + c) * 2 + 1];
+        // multipole-free rows: FP64 sums from the block-sparse kernel, added once per
+        // (pair, n'') by the item that holds the pair's first row block
+        if (wi.rb0 == 0 && n < nb)
+          for (int j = wi.g0; j < wi.g1; ++j) s += a.dsp[(long)wi.pair * a.dsp_stride + (long)j * nb + n];
         a.dpart[(long)wi.slot * a.dstride + n] = s;
       }
     }
