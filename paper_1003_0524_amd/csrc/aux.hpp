@@ -24,14 +24,17 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 // One wavefront per column (k, q, n'', n): the column's MT and multipole rows
 // are staged in LDS with coalesced 16-byte loads, every row is computed in FP64
 // and written once, so the kernel is bound by HBM bandwidth. Output: double2
-// rows (FP64 mode) or the tile kernel's split planes [plane][row] with the row
-// pitch padded to 8 and zero filled (reduced-precision modes).
+// rows (FP64 mode), or (reduced-precision modes) the whole column packed into
+// the tile kernel's split planes [plane][row]: the sparse rows Y_s followed by
+// the dense rows of M, each part zero padded (this is also the conversion of M
+// to the product mode's storage, done once per column).
 // ---------------------------------------------------------------------------
 struct SparseArgs {
   const PairInfo* pairs;
   const void* const* mtab;
   int32_t m_c64;
   int32_t n_s, n_ch, n_occ, nb_max;
+  int32_t ns_pad;            // n_s rounded up to 8: start of the dense rows in a packed column
   const int32_t* row_chan;   // [n_s] channel of each multipole-free row
   const int32_t* ch_off;     // [n_ch] first multipole-free row of the channel
   const int32_t* ch_len;     // [n_ch] nrad - 1
@@ -89,10 +92,13 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
       }
     }
   } else {
+    // pack the whole column into the tile kernel's split planes [plane][row]:
+    // rows [0, ns_pad) = Y_s (zero beyond n_s), rows [ns_pad, ldw) = the dense
+    // rows A_d of M (zero beyond N_d)
     using lds_t = typename Traits<MODE>::lds_t;
     constexpr int NP = Traits<MODE>::NPIECE;
     lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
-    for (int r = lane; r < pi.ldw; r += 64) {
+    for (int r = lane; r < a.ns_pad; r += 64) {
       double2 y = make_double2(0.0, 0.0);
       if (r < a.n_s) {
         const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
@@ -103,6 +109,21 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
       }
       put_real<MODE>(out + r, pi.ldw, y.x);
       put_real<MODE>(out + (long)NP * pi.ldw + r, pi.ldw, y.y);
+    }
+    const long mcol = pi.m_off + (long)col * pi.nmb + a.n_s;
+    const char* mb = (const char*)a.mtab[pi.k];
+    for (int d = lane; d < pi.ldw - a.ns_pad; d += 64) {
+      double2 x = make_double2(0.0, 0.0);
+      if (d < pi.nd) {
+        if (a.m_c64) {
+          const float2 v = ((const float2*)mb)[mcol + d];
+          x = make_double2(v.x, v.y);
+        } else {
+          x = ((const double2*)mb)[mcol + d];
+        }
+      }
+      put_real<MODE>(out + a.ns_pad + d, pi.ldw, x.x);
+      put_real<MODE>(out + (long)NP * pi.ldw + a.ns_pad + d, pi.ldw, x.y);
     }
     for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
     if (lane == 0) a.dsp[(long)blockIdx.y * a.n_occ * a.nb_max + col] = dsum;

@@ -26,31 +26,33 @@ constexpr uint32_t kAlive = 0x45584331u;   // "EXC1"
 thread_local std::string g_init_err;
 
 struct KernelCfg {
-  int mode, form, BM, KC, NCT, NB8M, NW, NBUF;
+  int mode, form, BM, KC, NCT, NB8M, NWR, NWC, NBUF;
   void (*fn)(TileArgs);
   size_t lds;
   int id;
+  int NW() const { return NWR * NWC; }
 };
 
-#define CFG(MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF, ID)                                          \
-  KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF, tile_kernel<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>, \
-            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>::LDS_B, ID}
+#define CFG(MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF, ID)                                    \
+  KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF,                                         \
+            tile_kernel<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>,                            \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::LDS_B, ID}
 
-// Tile shapes: BM rows of the factor per step (split over NW wavefronts), KC
-// complex k per LDS stage, NCT 8-column band tiles per pass (n_b rounded to 8,
-// times the n'' chunk), NB8M the largest band-tile count per n'' value the
-// instance contracts, NBUF K-loop buffers. The GEMM form stages two FP64
-// operands per n'' value and therefore stops at n_b <= 64.
+// Tile shapes: BM rows of the factor per step, split over NWR wavefronts; NCT
+// 8-column band tiles per pass (n_b rounded to 8, times the n'' chunk), split
+// over NWC wavefronts; KC complex k per LDS stage; NB8M the largest band-tile
+// count per n'' value the instance contracts; NBUF K-loop buffers. The GEMM
+// form stages two FP64 operands per row block and therefore stops at n_b <= 64.
 const KernelCfg kCfgs[] = {
-    CFG(M_F64, 0, 64, 16, 6, 3, 4, 2, 0),      CFG(M_F64, 0, 64, 16, 8, 8, 4, 2, 1),
-    CFG(M_F64, 1, 64, 16, 12, 3, 4, 2, 10),    CFG(M_F64, 1, 64, 16, 8, 8, 4, 2, 11),
-    CFG(M_F64, 1, 64, 16, 13, 13, 4, 2, 13),   CFG(M_F64, 1, 64, 16, 16, 16, 4, 2, 12),
-    CFG(M_F32, 1, 128, 16, 12, 3, 8, 2, 20),   CFG(M_F32, 1, 128, 16, 8, 8, 8, 2, 21),
-    CFG(M_F32, 1, 128, 16, 13, 13, 8, 2, 23),  CFG(M_F32, 1, 128, 16, 16, 16, 8, 2, 22),
-    CFG(M_BF16X3, 1, 128, 32, 12, 3, 8, 2, 30), CFG(M_BF16X3, 1, 128, 32, 8, 8, 8, 2, 31),
-    CFG(M_BF16X3, 1, 128, 32, 13, 13, 8, 2, 33), CFG(M_BF16X3, 1, 64, 32, 16, 16, 4, 2, 32),
-    CFG(M_BF16X6, 1, 64, 32, 12, 3, 4, 2, 40),  CFG(M_BF16X6, 1, 64, 32, 8, 8, 4, 2, 41),
-    CFG(M_BF16X6, 1, 64, 32, 13, 13, 4, 1, 43), CFG(M_BF16X6, 1, 64, 32, 16, 16, 4, 1, 42),
+    CFG(M_F64, 0, 64, 16, 6, 3, 4, 1, 2, 0),       CFG(M_F64, 0, 64, 16, 8, 8, 4, 1, 2, 1),
+    CFG(M_F64, 1, 64, 16, 12, 3, 4, 1, 2, 10),     CFG(M_F64, 1, 64, 16, 8, 8, 4, 1, 2, 11),
+    CFG(M_F64, 1, 64, 16, 13, 13, 4, 1, 2, 13),    CFG(M_F64, 1, 64, 16, 16, 16, 4, 1, 2, 12),
+    CFG(M_F32, 1, 128, 16, 12, 3, 4, 2, 2, 20),    CFG(M_F32, 1, 128, 16, 8, 8, 4, 2, 2, 21),
+    CFG(M_F32, 1, 64, 16, 13, 13, 4, 1, 2, 23),   CFG(M_F32, 1, 128, 16, 16, 16, 4, 2, 2, 22),
+    CFG(M_BF16X3, 1, 128, 32, 12, 3, 4, 2, 2, 30), CFG(M_BF16X3, 1, 128, 32, 8, 8, 4, 2, 2, 31),
+    CFG(M_BF16X3, 1, 64, 32, 13, 13, 4, 1, 2, 33), CFG(M_BF16X3, 1, 64, 32, 16, 16, 4, 1, 2, 32),
+    CFG(M_BF16X6, 1, 64, 32, 12, 3, 2, 2, 2, 40),  CFG(M_BF16X6, 1, 64, 32, 8, 8, 2, 2, 2, 41),
+    CFG(M_BF16X6, 1, 64, 32, 13, 13, 4, 1, 1, 43), CFG(M_BF16X6, 1, 64, 32, 16, 16, 4, 1, 1, 42),
 };
 
 struct Plan {
@@ -74,7 +76,7 @@ struct exc_ctx {
   int n_k = 0, n_q = 0, n_occ = 0, n_ch = 0, precision = 0, form = 0, batched = 0, device = 0;
   std::vector<int> nb, npw, nrad, nd, nmb;
   std::vector<double> wq;
-  int n_s = 0, nb_max = 0, nbt_max = 0;
+  int n_s = 0, nb_max = 0, nbt_max = 0, ns_pad = 0;
   std::vector<int> ch_off, ch_len;
   std::vector<int64_t> ch_coef;
   int64_t coef_total = 0;
@@ -309,6 +311,7 @@ TileArgs tile_args(exc_ctx* c, int dtype) {
   a.m_c64 = dtype == EXC_C64;
   a.n_s = c->n_s;
   a.n_ch = c->n_ch;
+  a.ns_pad = c->ns_pad;
   a.U = c->d_U;
   a.ws = c->d_ws;
   a.dsp = c->d_dsp;
@@ -325,7 +328,7 @@ SparseArgs sparse_args(exc_ctx* c, int dtype) {
   s.pairs = c->d_pairs;
   s.mtab = (const void* const*)c->d_mtab;
   s.m_c64 = dtype == EXC_C64;
-  s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max;
+  s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max; s.ns_pad = c->ns_pad;
   s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
   s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
   s.ws = c->d_ws; s.dsp = c->d_dsp;
@@ -371,7 +374,8 @@ const void* sparse_fn(const exc_ctx* c) {
 
 // Block-sparse rows of pairs [pair0, pair0 + npairs). Returns false when there is nothing to do.
 bool cfg_sparse(exc_ctx* c, int dtype, int pair0, int npairs, SparseArgs& s, KLaunch& L) {
-  if (c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return false;
+  const bool packs = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;   // packs the dense rows too
+  if (!packs && c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return false;
   s = sparse_args(c, dtype);
   s.pairs = c->d_pairs + pair0;
   // dsp is indexed by blockIdx.y: offset it to the first pair
@@ -412,7 +416,7 @@ void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persiste
   a.n_items = n;
   a.counter = persistent ? c->d_counter : nullptr;
   L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
-  L.block = dim3(64 * c->cfg->NW);
+  L.block = dim3(64 * c->cfg->NW());
   L.shmem = 0;
   L.fn = (const void*)c->cfg->fn;
   L.arg = &a;
@@ -712,8 +716,12 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   // sparse-row workspace: FP64 -> double2 rows (pitch n_s, or n_s + n_ch with the
   // GEMM form's multipole corrections); reduced precision -> split planes
   // [plane][row] per column with the row pitch padded to 8 (elements of lds_t)
+  // FP64: double2 sparse rows (pitch n_s, or n_s + n_ch with the GEMM form's
+  // multipole corrections). Reduced precision: each column packed into split
+  // planes [plane][row], rows = sparse rows padded to 8 then dense rows padded
+  // to 32 (elements of the mode's storage type).
   const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
-  const int ldw = split_ws ? (c->n_s + 7) / 8 * 8 : (c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch);
+  c->ns_pad = (c->n_s + 7) / 8 * 8;
   const int ws_cols = split_ws ? 2 * npieces(c->precision) : 1;   // planes per column
   int64_t ws_total = 0, m_max = 0;
   c->k_pair.assign(1, 0);
@@ -724,6 +732,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       p.k = k; p.q = q; p.nb = c->nb[k]; p.nmb = c->nmb[q]; p.nd = c->nd[q];
       p.nsb = (c->n_s + BM - 1) / BM; p.ndb = (c->nd[q] + BM - 1) / BM;
       p.nb8 = (p.nb + 7) / 8 * 8;
+      const int ldw = split_ws ? c->ns_pad + (c->nd[q] + 31) / 32 * 32
+                               : (c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch);
       p.m_off = moff; p.ws_off = ws_total; p.u_off = c->u_off[q]; p.ldu = c->ldu[q]; p.ldw = std::max(1, ldw);
       moff += (int64_t)c->n_occ * p.nb * p.nmb;
       ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
@@ -795,15 +805,15 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   {
     hipFuncAttributes fa{};
     IHIP(hipFuncGetAttributes(&fa, (const void*)c->cfg->fn));
-    if (fa.maxThreadsPerBlock < 64 * c->cfg->NW) {
+    if (fa.maxThreadsPerBlock < 64 * c->cfg->NW()) {
       fail(c, EXC_EUNSUPPORTED, "tile kernel %d allows %d threads per block, needs %d", c->cfg->id,
-           fa.maxThreadsPerBlock, 64 * c->cfg->NW);
+           fa.maxThreadsPerBlock, 64 * c->cfg->NW());
       return bail(EXC_EUNSUPPORTED);
     }
   }
   int n_cu = 0, occ = 0;
   IHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 64 * c->cfg->NW, 0));
+  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 64 * c->cfg->NW(), 0));
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   c->persist_grid = std::max(1, n_cu * std::max(1, occ));

@@ -16,11 +16,14 @@
 // so a complex multiply-add costs 4 real multiply-adds and odd band counts
 // waste at most 7 columns.
 //
-// Work decomposition: NW wavefronts split the BM rows of a row block; the K
+// Work decomposition: the K
 // loop stages row panels of B and column panels of A through NBUF LDS buffers
 // (with two: one barrier per chunk; global loads for chunk i+1 are in flight
-// while chunk i runs on MFMA). The contraction stages one n'' group of Y at a time in LDS and
-// each wavefront owns a subset of the 16x16 Gram tiles G(I,J), I <= J.
+// while chunk i runs on MFMA). Wavefronts form an NWR x NWC grid over the rows
+// and column tiles of a row block, so one B-operand load feeds RT row tiles.
+// After the K loop the whole row block (every n'' group of the pass) is staged
+// in LDS once and each wavefront contracts its own 16x16 Gram tiles G(I,J),
+// I <= J, over all rows and groups.
 //
 // Partials: each work item (pair (k,q), a range of n'' values, a range of row
 // blocks) writes its Gram tiles (plus, in the reduced-precision modes, an FP64
@@ -53,6 +56,7 @@ struct TileArgs {
   const void* const* mtab;       // [n_k] device pointers to M_k
   int32_t m_c64;                 // 1: M holds complex64
   int32_t n_s, n_ch, n_occ;
+  int32_t ns_pad;                // reduced precision: first dense row of a packed column
   const void* U;                 // prepared factor planes
   const void* ws;                // sparse workspace: double2 (FP64) or split planes (others)
   const double* dsp;             // reduced precision: FP64 sum_r |Y_s|^2 per (pair, n'', n)
@@ -70,17 +74,20 @@ __device__ __forceinline__ void tp_to_ij(int tp, int& I, int& J) {
   I = tp - j * (j + 1) / 2;
 }
 
-template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NW, int NBUF>
+template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NWR, int NWC, int NBUF>
 struct TileCfg {
   using T = Traits<MODE>;
   using acc_t = typename T::acc_t;
   using lds_t = typename T::lds_t;
   using accv_t = typename T::accv_t;
+  static constexpr int NW = NWR * NWC;                  // wavefronts: NWR along rows x NWC along columns
   static constexpr int NT = 64 * NW;                    // threads
   static constexpr int NP = T::NPIECE, KS = T::KS;
   static constexpr int KPL = KS / 4;                    // k values each of the 4 lane groups supplies
-  static constexpr int BMW = BM / NW, RT = BMW / 16;
+  static constexpr int BMW = BM / NWR, RT = BMW / 16;
   static_assert(RT >= 1 && BMW % 16 == 0, "each wavefront owns whole 16-row tiles");
+  static constexpr int CTW = NCT / NWC;                 // column tiles per wavefront
+  static_assert(CTW * NWC == NCT, "column tiles split evenly over the wavefronts");
   static constexpr int NCC = NCT * 8;
   static constexpr int PADE = 16 / (int)sizeof(lds_t);
   static constexpr int LDK = KC + PADE;
@@ -89,9 +96,9 @@ struct TileCfg {
   static constexpr int UPL = BM * LDK;                  // one plane of the B stage
   static constexpr int APL = NCC * LDK;                 // one plane of the A stage
   static constexpr int STAGE = NPL * (UPL + APL);       // lds_t elements of one K-loop buffer
-  static constexpr int YPL = NB8M * 8 * LDR;            // one plane of the group stage
+  static constexpr int YPL = NCC * LDR;                 // one plane of the row-block stage (all n'' groups)
   static constexpr int YS_SZ = NPL * YPL;
-  static constexpr int LPL = NB8M * 8 * (BM + 2);       // GEMM left operand (double)
+  static constexpr int LPL = NCC * (BM + 2);            // GEMM left operand (double)
   static constexpr int LS_SZ = (FORM == 0) ? 2 * LPL : 0;
   static constexpr int NPT = NB8M * (NB8M + 1) / 2;
   static constexpr int NPW = (NPT + NW - 1) / NW;
@@ -112,6 +119,11 @@ struct TileCfg {
   static constexpr int UV_PT = (UV_TOTAL + NT - 1) / NT;
   static constexpr int AV_TOTAL = NCC * KC / 2;
   static constexpr int AV_PT = (AV_TOTAL + NT - 1) / NT;
+  // reduced precision: A comes pre-split; 16-byte vectors of k per (plane, column)
+  static constexpr int EPV = 16 / (int)sizeof(lds_t);
+  static constexpr int PV_PER_PLANE = NCC * KC / EPV;
+  static constexpr int PV_TOTAL = NPL * PV_PER_PLANE;
+  static constexpr int PV_PT = (PV_TOTAL + NT - 1) / NT;
 };
 
 // Load the operand a lane supplies for one MFMA from an LDS row (k contiguous).
@@ -124,9 +136,10 @@ __device__ __forceinline__ auto lds_operand(const typename Traits<MODE>::lds_t* 
   }
 }
 
-template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NW, int NBUF>
-__global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
-  using C = TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NW, NBUF>;
+template <int MODE, int FORM, int BM, int KC, int NCT, int NB8M, int NWR, int NWC, int NBUF>
+__global__ __launch_bounds__(64 * NWR * NWC, 1) void tile_kernel(TileArgs a) {
+  using C = TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>;
+  constexpr int NW = C::NW, CTW = C::CTW;
   using acc_t = typename C::acc_t;
   using lds_t = typename C::lds_t;
   using accv_t = typename C::accv_t;
@@ -143,6 +156,7 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
   double* Dacc = (double*)(smem + C::MAIN_B);   // [NW][NCC][2] per-wave diagonal sums (re, im parts)
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w % NWR, wc = w / NWR;            // wavefront's row band and column-tile band
   const int l16 = lane & 15, lq = lane >> 4;       // MFMA row/col within tile, k group
   const int c8 = l16 & 7, part = l16 >> 3;         // complex column within tile, re/im
 
@@ -193,13 +207,13 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
         const bool sparse = rb < pi.nsb;
         const int r0 = sparse ? rb * BM : (rb - pi.nsb) * BM;  // first row (sparse or dense coords)
 
-        accv_t yacc[RT][NCT];
+        accv_t yacc[RT][CTW];
         if (!sparse) {
           // ---------------- dense rows: K loop on MFMA ----------------
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) yacc[rt][ct] = accv_t{0, 0, 0, 0};
+            for (int j = 0; j < CTW; ++j) yacc[rt][j] = accv_t{0, 0, 0, 0};
           const int kc0 = HERK ? (r0 / KC) * KC : 0;
           const int kc1 = (nd + KC - 1) / KC * KC;
           const int nch = (kc1 - kc0) / KC;
@@ -207,7 +221,9 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
           const long plane = (long)pi.ldu * pi.ldu;
 
           u4_t ureg[C::UV_PT];
-          u4_t areg0[C::AV_PT], areg1[C::AV_PT];   // complex k, k+1 (complex128) or both (complex64)
+          constexpr int AR = (MODE == M_F64) ? C::AV_PT : C::PV_PT;
+          u4_t areg0[AR], areg1[(MODE == M_F64) ? C::AV_PT : 1];
+          const lds_t* Pg = (const lds_t*)a.ws + pi.ws_off;   // packed columns (reduced precision)
           auto prefetch = [&](int kc) {
 #pragma unroll
             for (int j = 0; j < C::UV_PT; ++j) {
@@ -220,28 +236,43 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
                 ureg[j] = *(const u4_t*)src;
               }
             }
+            if constexpr (MODE == M_F64) {
 #pragma unroll
-            for (int j = 0; j < C::AV_PT; ++j) {
-              const int v = tid + NT * j;
-              u4_t x0 = u4_t{0, 0, 0, 0}, x1 = u4_t{0, 0, 0, 0};
-              const int c = v / (KC / 2), kp = v % (KC / 2);
-              const int g = c / nb8, n = c - g * nb8;
-              const int kk = kc + 2 * kp;
-              if (v < C::AV_TOTAL && c < ncols && n < nb && kk < nd) {
-                const long e = ((long)(gbase + g) * nb + n) * pi.nmb + a.n_s + kk;
-                if (a.m_c64) {
-                  const float* p = (const float*)mbase + 2 * e;
-                  const float2 f0 = *(const float2*)p;
-                  const float2 f1 = (kk + 1 < nd) ? *(const float2*)(p + 2) : make_float2(0.f, 0.f);
-                  x0 = u4_t{__float_as_uint(f0.x), __float_as_uint(f0.y), __float_as_uint(f1.x), __float_as_uint(f1.y)};
-                } else {
-                  const u4_t* p = (const u4_t*)(mbase + 16 * e);
-                  x0 = p[0];
-                  if (kk + 1 < nd) x1 = p[1];
+              for (int j = 0; j < C::AV_PT; ++j) {
+                const int v = tid + NT * j;
+                u4_t x0 = u4_t{0, 0, 0, 0}, x1 = u4_t{0, 0, 0, 0};
+                const int c = v / (KC / 2), kp = v % (KC / 2);
+                const int g = c / nb8, n = c - g * nb8;
+                const int kk = kc + 2 * kp;
+                if (v < C::AV_TOTAL && c < ncols && n < nb && kk < nd) {
+                  const long e = ((long)(gbase + g) * nb + n) * pi.nmb + a.n_s + kk;
+                  if (a.m_c64) {
+                    const float* p = (const float*)mbase + 2 * e;
+                    const float2 f0 = *(const float2*)p;
+                    const float2 f1 = (kk + 1 < nd) ? *(const float2*)(p + 2) : make_float2(0.f, 0.f);
+                    x0 = u4_t{__float_as_uint(f0.x), __float_as_uint(f0.y), __float_as_uint(f1.x), __float_as_uint(f1.y)};
+                  } else {
+                    const u4_t* p = (const u4_t*)(mbase + 16 * e);
+                    x0 = p[0];
+                    if (kk + 1 < nd) x1 = p[1];
+                  }
                 }
+                areg0[j] = x0;
+                areg1[j] = x1;
               }
-              areg0[j] = x0;
-              areg1[j] = x1;
+            } else {
+#pragma unroll
+              for (int j = 0; j < C::PV_PT; ++j) {
+                const int v = tid + NT * j;
+                u4_t x = u4_t{0, 0, 0, 0};
+                constexpr int VPK = KC / C::EPV;      // vectors per column and plane
+                const int pl = v / C::PV_PER_PLANE, rem = v % C::PV_PER_PLANE;
+                const int c = rem / VPK, kv = rem % VPK;
+                const int g = c / nb8, n = c - g * nb8;
+                if (v < C::PV_TOTAL && c < ncols && n < nb)
+                  x = *(const u4_t*)(Pg + (((long)(gbase + g) * nb + n) * C::NPL + pl) * pi.ldw + a.ns_pad + kc + kv * C::EPV);
+                areg0[j] = x;
+              }
             }
           };
           auto stage = [&](lds_t* Us, lds_t* As) {
@@ -255,38 +286,37 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
                 *(u4_t*)(Us + pl * UPL + row * LDK + kv * (16 / ESZ)) = ureg[j];
               }
             }
+            if constexpr (MODE == M_F64) {
 #pragma unroll
-            for (int j = 0; j < C::AV_PT; ++j) {
-              const int v = tid + NT * j;
-              if (v < C::AV_TOTAL) {
-                const int c = v / (KC / 2), kp = v % (KC / 2);
-                double re0, im0, re1, im1;
-                const u4_t x0 = areg0[j], x1 = areg1[j];
-                if (a.m_c64) {
-                  re0 = __uint_as_float(x0.x); im0 = __uint_as_float(x0.y);
-                  re1 = __uint_as_float(x0.z); im1 = __uint_as_float(x0.w);
-                } else {
-                  re0 = __hiloint2double(x0.y, x0.x);
-                  im0 = __hiloint2double(x0.w, x0.z);
-                  re1 = __hiloint2double(x1.y, x1.x);
-                  im1 = __hiloint2double(x1.w, x1.z);
-                }
-                lds_t* d = As + c * LDK + 2 * kp;
-                if constexpr (MODE == M_F64) {
+              for (int j = 0; j < C::AV_PT; ++j) {
+                const int v = tid + NT * j;
+                if (v < C::AV_TOTAL) {
+                  const int c = v / (KC / 2), kp = v % (KC / 2);
+                  const u4_t x0 = areg0[j], x1 = areg1[j];
+                  double re0, im0, re1, im1;
+                  if (a.m_c64) {
+                    re0 = __uint_as_float(x0.x); im0 = __uint_as_float(x0.y);
+                    re1 = __uint_as_float(x0.z); im1 = __uint_as_float(x0.w);
+                  } else {
+                    re0 = __hiloint2double(x0.y, x0.x);
+                    im0 = __hiloint2double(x0.w, x0.z);
+                    re1 = __hiloint2double(x1.y, x1.x);
+                    im1 = __hiloint2double(x1.w, x1.z);
+                  }
+                  lds_t* d = As + c * LDK + 2 * kp;
                   *(double2*)(d) = make_double2(re0, re1);
                   *(double2*)(d + NP * APL) = make_double2(im0, im1);
-                } else if constexpr (MODE == M_F32) {
-                  *(float2*)(d) = make_float2((float)re0, (float)re1);
-                  *(float2*)(d + NP * APL) = make_float2((float)im0, (float)im1);
-                } else {
-                  uint16_t h0[NP], h1[NP], g0[NP], g1[NP];
-                  split_d<NP>(re0, h0); split_d<NP>(re1, h1);
-                  split_d<NP>(im0, g0); split_d<NP>(im1, g1);
+                }
+              }
+            } else {
 #pragma unroll
-                  for (int p = 0; p < NP; ++p) {
-                    *(uint32_t*)(d + p * APL) = (uint32_t)h0[p] | ((uint32_t)h1[p] << 16);
-                    *(uint32_t*)(d + (NP + p) * APL) = (uint32_t)g0[p] | ((uint32_t)g1[p] << 16);
-                  }
+              for (int j = 0; j < C::PV_PT; ++j) {
+                const int v = tid + NT * j;
+                if (v < C::PV_TOTAL) {
+                  constexpr int VPK = KC / C::EPV;
+                  const int pl = v / C::PV_PER_PLANE, rem = v % C::PV_PER_PLANE;
+                  const int c = rem / VPK, kv = rem % VPK;
+                  *(u4_t*)(As + pl * APL + c * LDK + kv * C::EPV) = areg0[j];
                 }
               }
             }
@@ -312,12 +342,13 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                   for (int p = 0; p < NP; ++p)
-                    aop[rt][p] = lds_operand<MODE>(Us + (h * NP + p) * UPL + (w * BMW + rt * 16 + l16) * LDK + kofs);
+                    aop[rt][p] = lds_operand<MODE>(Us + (h * NP + p) * UPL + (wr * BMW + rt * 16 + l16) * LDK + kofs);
                 const int bpart = part ^ h;
                 const bool neg = (h == 1) && (part == 0);
-                // all NCT column tiles: columns beyond the item are zero in LDS
+                // this wave's CTW column tiles: columns beyond the item are zero in LDS
 #pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) {
+                for (int j = 0; j < CTW; ++j) {
+                  const int ct = wc * CTW + j;
                   decltype(lds_operand<MODE>(As)) bop[NP];
 #pragma unroll
                   for (int p = 0; p < NP; ++p) {
@@ -327,11 +358,11 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
 #pragma unroll
                   for (int rt = 0; rt < RT; ++rt) {
                     if constexpr (NP == 1) {
-                      yacc[rt][ct] = mfma(aop[rt][0], bop[0], yacc[rt][ct]);
+                      yacc[rt][j] = mfma(aop[rt][0], bop[0], yacc[rt][j]);
                     } else {
 #pragma unroll
                       for (int pr = 0; pr < C::T::NPROD; ++pr)
-                        yacc[rt][ct] = mfma(aop[rt][prod_a(NP, pr)], bop[prod_b(NP, pr)], yacc[rt][ct]);
+                        yacc[rt][j] = mfma(aop[rt][prod_a(NP, pr)], bop[prod_b(NP, pr)], yacc[rt][j]);
                     }
                   }
                 }
@@ -347,13 +378,14 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
             // FP64 sums of |Y|^2 per real column; the four lanes of one column are
             // reduced first so that each wave owns its Dacc row (no races, fixed order)
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
+            for (int j = 0; j < CTW; ++j) {
+              const int ct = wc * CTW + j;
               double d = 0.0;
 #pragma unroll
               for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  const double y = (double)yacc[rt][ct][i];
+                  const double y = (double)yacc[rt][j][i];
                   d += y * y;
                 }
               d += __shfl_xor(d, 16);
@@ -366,16 +398,17 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
             if (r0 < a.n_ch) {
               const double* X = (const double*)a.ws + 2 * pi.ws_off;
 #pragma unroll
-              for (int ct = 0; ct < NCT; ++ct) {
+              for (int j = 0; j < CTW; ++j) {
+                const int ct = wc * CTW + j;
                 if (ct < nct) {
                   const int c = ct * 8 + c8, g = c / nb8, n = c - g * nb8;
 #pragma unroll
                   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                      const int d = r0 + w * BMW + rt * 16 + acc_row<MODE>(lq, i);
+                      const int d = r0 + wr * BMW + rt * 16 + acc_row<MODE>(lq, i);
                       if (d < a.n_ch && n < nb)
-                        yacc[rt][ct][i] += X[2 * (((long)(gbase + g) * nb + n) * pi.ldw + a.n_s + d) + part];
+                        yacc[rt][j][i] += X[2 * (((long)(gbase + g) * nb + n) * pi.ldw + a.n_s + d) + part];
                     }
                 }
               }
@@ -383,123 +416,124 @@ __global__ __launch_bounds__(64 * NW, 1) void tile_kernel(TileArgs a) {
           }
         }
 
-        // ---------------- per n'' group: stage rows, contract ----------------
-        for (int g = 0; g < ng; ++g) {
-          __syncthreads();
-          if (!sparse) {
+        // ---------------- stage the row block (all n'' groups), contract ----------------
+        __syncthreads();
+        if (!sparse) {
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-              if (ct >= g * nbt && ct < (g + 1) * nbt) {
-                const int cl = (ct - g * nbt) * 8 + c8;
+          for (int j = 0; j < CTW; ++j) {
+            const int cl = (wc * CTW + j) * 8 + c8;   // column within the pass (group-major)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    const int row = w * BMW + rt * 16 + acc_row<MODE>(lq, i);
-                    if constexpr (MODE == M_F64)
-                      Ys[(part * NP) * YPL + cl * LDR + row] = yacc[rt][ct][i];
-                    else
-                      put_realf<MODE>(Ys + (part * NP) * YPL + cl * LDR + row, YPL, (float)yacc[rt][ct][i]);
-                  }
+              for (int i = 0; i < 4; ++i) {
+                const int row = wr * BMW + rt * 16 + acc_row<MODE>(lq, i);
+                if constexpr (MODE == M_F64)
+                  Ys[(part * NP) * YPL + cl * LDR + row] = yacc[rt][j][i];
+                else
+                  put_realf<MODE>(Ys + (part * NP) * YPL + cl * LDR + row, YPL, (float)yacc[rt][j][i]);
               }
-            }
-            if constexpr (!HERK) {
-              // left operand: A_d rows [r0, r0+BM) of group g, FP64
-              for (int e = tid; e < nb8 * BM; e += NT) {
-                const int cl = e / BM, row = e - cl * BM;
-                const int d = r0 + row;
-                double re = 0.0, im = 0.0;
-                if (cl < nb && d < nd) {
-                  const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + a.n_s + d));
-                  re = p[0]; im = p[1];
-                }
-                Ls[cl * (BM + 2) + row] = re;
-                Ls[C::LPL + cl * (BM + 2) + row] = im;
-              }
-            }
-          } else if constexpr (MODE == M_F64) {
-            // sparse rows: Y_s (HERK) or W_s (GEMM) as double2 from the workspace, A_s for GEMM
-            for (int e = tid; e < nb8 * BM; e += NT) {
+          }
+          if constexpr (!HERK) {
+            // left operand: A_d rows [r0, r0+BM) of every group of the pass, FP64
+            for (int e = tid; e < ncols * BM; e += NT) {
               const int cl = e / BM, row = e - cl * BM;
-              const int r = r0 + row;
+              const int g = cl / nb8, n = cl - g * nb8;
+              const int d = r0 + row;
               double re = 0.0, im = 0.0;
-              if (cl < nb && r < a.n_s) {
-                const double2 v = ((const double2*)a.ws)[pi.ws_off + ((long)(gbase + g) * nb + cl) * pi.ldw + r];
-                re = v.x; im = v.y;
+              if (n < nb && d < nd) {
+                const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + n) * pi.nmb + a.n_s + d));
+                re = p[0]; im = p[1];
               }
-              Ys[cl * LDR + row] = re;
-              Ys[YPL + cl * LDR + row] = im;
-              if constexpr (!HERK) {
-                double lre = 0.0, lim = 0.0;
-                if (cl < nb && r < a.n_s) {
-                  const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + cl) * pi.nmb + r));
-                  lre = p[0]; lim = p[1];
-                }
-                Ls[cl * (BM + 2) + row] = lre;
-                Ls[C::LPL + cl * (BM + 2) + row] = lim;
-              }
-            }
-          } else {
-            // sparse rows, reduced precision: the block-sparse kernel wrote Y_s already split
-            // into planes [n''][n][plane][row] (pitch ldw, zero padded to 8 rows): 16-byte copies
-            constexpr int EPV = 16 / ESZ;                       // elements per 16-byte vector
-            constexpr int VPC = BM / EPV;                       // vectors per column and plane
-            const lds_t* src = (const lds_t*)a.ws + pi.ws_off;
-            for (int v = tid; v < C::NPL * nb8 * VPC; v += NT) {
-              const int pl = v / (nb8 * VPC), rem = v - pl * (nb8 * VPC);
-              const int cl = rem / VPC, rv = rem - cl * VPC;
-              const int r = r0 + rv * EPV;
-              u4_t x = u4_t{0, 0, 0, 0};
-              if (cl < nb && r < pi.ldw)
-                x = *(const u4_t*)(src + (((long)(gbase + g) * nb + cl) * C::NPL + pl) * pi.ldw + r);
-              *(u4_t*)(Ys + pl * YPL + cl * LDR + rv * EPV) = x;
+              Ls[cl * (BM + 2) + row] = re;
+              Ls[C::LPL + cl * (BM + 2) + row] = im;
             }
           }
-          __syncthreads();
-          // contraction: this wave's Gram tiles, K = BM rows
-          auto contract = [&](int tp, accv_t acc) -> accv_t {
-            int I, J;
-            tp_to_ij(tp, I, J);
-            const int cA = I * 8 + c8, cB = J * 8 + c8;
-#pragma unroll 2
-            for (int ks = 0; ks < BM / KS; ++ks) {
-              const int kofs = ks * KS + KPL * lq;
-              if constexpr (HERK) {
-                decltype(lds_operand<MODE>(Ys)) ao[NP], bo[NP];
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                  ao[p] = lds_operand<MODE>(Ys + (part * NP + p) * YPL + cA * LDR + kofs);
-                  bo[p] = lds_operand<MODE>(Ys + (part * NP + p) * YPL + cB * LDR + kofs);
-                }
-                if constexpr (NP == 1) {
-                  acc = mfma(ao[0], bo[0], acc);
-                } else {
-#pragma unroll
-                  for (int pr = 0; pr < C::T::NPROD; ++pr)
-                    acc = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], acc);
-                }
-              } else {
-                const double ao = Ls[part * C::LPL + cA * (BM + 2) + kofs];
-                const double bo = Ys[part * YPL + cB * LDR + kofs];
-                acc = mfma(ao, bo, acc);
+        } else if constexpr (MODE == M_F64) {
+          // sparse rows: Y_s (HERK) or W_s (GEMM) as double2 from the workspace, A_s for GEMM
+          for (int e = tid; e < ncols * BM; e += NT) {
+            const int cl = e / BM, row = e - cl * BM;
+            const int g = cl / nb8, n = cl - g * nb8;
+            const int r = r0 + row;
+            double re = 0.0, im = 0.0;
+            if (n < nb && r < a.n_s) {
+              const double2 v = ((const double2*)a.ws)[pi.ws_off + ((long)(gbase + g) * nb + n) * pi.ldw + r];
+              re = v.x; im = v.y;
+            }
+            Ys[cl * LDR + row] = re;
+            Ys[YPL + cl * LDR + row] = im;
+            if constexpr (!HERK) {
+              double lre = 0.0, lim = 0.0;
+              if (n < nb && r < a.n_s) {
+                const double* p = (const double*)(mbase + 16 * (((long)(gbase + g) * nb + n) * pi.nmb + r));
+                lre = p[0]; lim = p[1];
               }
+              Ls[cl * (BM + 2) + row] = lre;
+              Ls[C::LPL + cl * (BM + 2) + row] = lim;
             }
-            return acc;
-          };
-          if constexpr (C::GSTREAM) {
-            for (int s = 0; s < C::NPW; ++s) {
-              const int tp = w + NW * s;
-              if (tp >= npt) break;
-              const accv_t acc = contract(tp, accv_t{0, 0, 0, 0});
+          }
+        } else {
+          // sparse rows, reduced precision: the block-sparse kernel wrote Y_s already split
+          // into planes [n''][n][plane][row] (pitch ldw, zero padded to ns_pad rows): 16-byte copies
+          constexpr int EPV = 16 / ESZ;                       // elements per 16-byte vector
+          constexpr int VPC = BM / EPV;                       // vectors per column and plane
+          const lds_t* src = (const lds_t*)a.ws + pi.ws_off;
+          for (int v = tid; v < C::NPL * ncols * VPC; v += NT) {
+            const int pl = v / (ncols * VPC), rem = v - pl * (ncols * VPC);
+            const int cl = rem / VPC, rv = rem - cl * VPC;
+            const int g = cl / nb8, n = cl - g * nb8;
+            const int r = r0 + rv * EPV;
+            u4_t x = u4_t{0, 0, 0, 0};
+            if (n < nb && r < a.ns_pad)
+              x = *(const u4_t*)(src + (((long)(gbase + g) * nb + n) * C::NPL + pl) * pi.ldw + r);
+            *(u4_t*)(Ys + pl * YPL + cl * LDR + rv * EPV) = x;
+          }
+        }
+        __syncthreads();
+        // contraction: this wave's Gram tiles over the BM rows of every group of the pass
+        auto contract = [&](int tp, int g, accv_t acc) -> accv_t {
+          int I, J;
+          tp_to_ij(tp, I, J);
+          const int cA = g * nb8 + I * 8 + c8, cB = g * nb8 + J * 8 + c8;
+#pragma unroll 2
+          for (int ks = 0; ks < BM / KS; ++ks) {
+            const int kofs = ks * KS + KPL * lq;
+            if constexpr (HERK) {
+              decltype(lds_operand<MODE>(Ys)) ao[NP], bo[NP];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] += acc[i];
-            }
-          } else {
+              for (int p = 0; p < NP; ++p) {
+                ao[p] = lds_operand<MODE>(Ys + (part * NP + p) * YPL + cA * LDR + kofs);
+                bo[p] = lds_operand<MODE>(Ys + (part * NP + p) * YPL + cB * LDR + kofs);
+              }
+              if constexpr (NP == 1) {
+                acc = mfma(ao[0], bo[0], acc);
+              } else {
 #pragma unroll
-            for (int s = 0; s < NPWR; ++s) {
-              const int tp = w + NW * s;
-              if (tp < npt) gacc[s] = contract(tp, gacc[s]);
+                for (int pr = 0; pr < C::T::NPROD; ++pr)
+                  acc = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], acc);
+              }
+            } else {
+              const double ao = Ls[part * C::LPL + cA * (BM + 2) + kofs];
+              const double bo = Ys[part * YPL + cB * LDR + kofs];
+              acc = mfma(ao, bo, acc);
             }
+          }
+          return acc;
+        };
+        if constexpr (C::GSTREAM) {
+          for (int s = 0; s < C::NPW; ++s) {
+            const int tp = w + NW * s;
+            if (tp >= npt) break;
+            accv_t acc = accv_t{0, 0, 0, 0};
+            for (int g = 0; g < ng; ++g) acc = contract(tp, g, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] += acc[i];
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < NPWR; ++s) {
+            const int tp = w + NW * s;
+            if (tp < npt)
+              for (int g = 0; g < ng; ++g) gacc[s] = contract(tp, g, gacc[s]);
           }
         }
       }
