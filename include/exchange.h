@@ -183,6 +183,86 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
  */
 exc_status exchange_timing(exc_ctx *ctx, int32_t n_slots);
 
+/* ==========================================================================
+ * Learned V^x extrapolator (extension of the nested self-consistency scheme
+ * of Sec. IV, where V^x stays fixed between outer steps). V^x is linear in the
+ * density matrix for fixed projections M, so between exact evaluations the
+ * change dV(k) is predicted from the change dP of the density matrix by a
+ * small network; the exact path stays the fallback and the judge.
+ *
+ * Network: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3, all
+ * FP32; parameters flat as [W1 (hidden x in), b1, W2 (hidden x hidden), b2,
+ * W3 (out x hidden), b3], row-major. Loss: mean squared error over samples and
+ * outputs. Training: full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction), one step per epoch. Samples are rows: X is n x in, Y is n x out.
+ * The network belongs to the context (one per context) and lives on its GPU.
+ * ========================================================================== */
+
+/* exchange_nn_init -- create (or replace) the context's network. Weights are
+ * (2u - 1)/sqrt(fan_in) with u the top 53 bits / 2^53 of output number
+ * (flat index) of the SplitMix64 stream started at seed; biases 0; Adam state
+ * zero. EXC_EINVAL for sizes < 1 or beyond 65536 (hidden: 8192). */
+exc_status exchange_nn_init(exc_ctx *ctx, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed);
+
+/* exchange_nn_params -- copy the n parameters out (set = 0) or in (set = 1;
+ * also resets the Adam state). params is a host (on_device = 0) or device
+ * pointer; n must equal the parameter count, else EXC_EINVAL. */
+exc_status exchange_nn_params(exc_ctx *ctx, float *params, int64_t n, int32_t set, int32_t on_device);
+
+/* exchange_nn_train -- epochs full-batch Adam steps on (X, Y), n samples; X, Y
+ * host or device (on_device) FP32 rows. One epoch is a HIP graph replayed per
+ * step. *loss_out (may be NULL) = the loss of the last step's forward pass.
+ * Synchronous. EXC_ESTATE before exchange_nn_init. */
+exc_status exchange_nn_train(exc_ctx *ctx, const float *X, const float *Y, int32_t n, int32_t epochs,
+                             float lr, int32_t on_device, float *loss_out);
+
+/* exchange_nn_grad -- the loss and its gradient with respect to the flat
+ * parameters (same layout) at the current parameters, without an update.
+ * grad_out host or device (on_device). Synchronous. */
+exc_status exchange_nn_grad(exc_ctx *ctx, const float *X, const float *Y, int32_t n, int32_t on_device,
+                            float *grad_out, float *loss_out);
+
+/* exchange_nn_predict -- Y_out (n x out) = network(X). Host pointers: the
+ * call returns when Y_out is written. Device pointers with a stream: ordered
+ * on that stream, asynchronous. */
+exc_status exchange_nn_predict(exc_ctx *ctx, const float *X, int32_t n, float *Y_out, int32_t on_device,
+                               void *stream);
+
+/* exchange_nn_features -- input encoding of a density-matrix change. P_new,
+ * P_old: device arrays of n_real doubles (the complex n_b x n_b matrices of
+ * every k', column-major, real and imaginary parts interleaved, k' outermost).
+ * With v = P_new - P_old: x_out[i] = sum_j S_ij v_j / |v| (device, m floats,
+ * zero if v = 0), S_ij = -1/sqrt(m) if the top bit of SplitMix64(seed) output
+ * number i*n_real + j is set, else +1/sqrt(m); *norm_out (device double) =
+ * |v|. 1 <= m <= 128. Asynchronous on stream (NULL: the context's stream,
+ * synchronous). */
+exc_status exchange_nn_features(exc_ctx *ctx, const double *P_new, const double *P_old, int64_t n_real,
+                                uint64_t seed, int32_t m, float *x_out, double *norm_out, void *stream);
+
+/* exchange_eigh -- eigen-decomposition of one Hermitian n_b(k) x n_b(k)
+ * complex128 column-major matrix per k of the context (A_k: host array of n_k
+ * device pointers; the Hermitian part is used). w_out: device, the ascending
+ * eigenvalues packed k after k (sum n_b(k) doubles); Z_out: device, the
+ * eigenvectors as columns, packed (sum n_b(k)^2 complex128). FP64 cyclic
+ * Jacobi (off-diagonal norm below 1e-14 of the norm). n_b <= 256, else
+ * EXC_EUNSUPPORTED. */
+exc_status exchange_eigh(exc_ctx *ctx, const void *const *A_k, double *w_out, void *Z_out, void *stream);
+
+/* exchange_nn_project -- output encoding: with B_k the first n_blk columns of
+ * Z_k (as packed by exchange_eigh) and H = B_k^H (Va_k - Vb_k) B_k,
+ * y_out[k][i*n_blk + j] = scale * Re H_ij (i <= j) and y_out[k][j*n_blk + i] =
+ * scale * Im H_ij (i < j); y_out device, n_k * n_blk^2 floats. Va_k, Vb_k: host
+ * arrays of device pointers to n_b(k)^2 complex128. Requires n_blk <= n_b(k)
+ * and n_b * n_blk <= 4096 (EXC_EUNSUPPORTED). */
+exc_status exchange_nn_project(exc_ctx *ctx, const void *const *Va_k, const void *const *Vb_k, const void *Z,
+                               int32_t n_blk, double scale, float *y_out, void *stream);
+
+/* exchange_nn_expand -- prediction: Vout_k = Vanchor_k + scale * B_k H_k B_k^H
+ * with H_k decoded from y (device, layout of exchange_nn_project). Vout_k may
+ * alias Vanchor_k. */
+exc_status exchange_nn_expand(exc_ctx *ctx, const void *const *Vanchor_k, const void *Z, int32_t n_blk,
+                              const float *y, double scale, void *const *Vout_k, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

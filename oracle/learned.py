@@ -4,9 +4,9 @@ Between exact evaluations of V^x (Sec. II.C) the extension predicts the change
 of V^x(k) caused by a change of the density matrix. V^x is linear in the
 density matrix for fixed product-basis projections, so the map to learn is
 dV = L(dP). The network sees a fixed-size encoding of dP and returns a
-fixed-size encoding of dV(k):
+fixed-size encoding of dV(k) for every k (the blocks of all k concatenated):
 
-* input  x(k) = [ S vec(dP) / |vec(dP)|  (m entries),  one-hot(k) (n_k entries) ]
+* input  x = S vec(dP) / |vec(dP)|  (m entries),
   where vec(dP) stacks, for every k' and column j and row i, Re then Im of
   dP_k'[i, j] (columns of n_b x n_b complex matrices, k' outermost), and S is
   the m x D Rademacher sketch S_ij = +-1/sqrt(m), the sign taken from the top
@@ -49,12 +49,6 @@ def sketch(v: np.ndarray, m: int, seed: int, stream):
     if nrm == 0.0:
         return np.zeros(m), 0.0
     return S @ (v / nrm), nrm
-
-
-def features(s: np.ndarray, k: int, n_k: int) -> np.ndarray:
-    oh = np.zeros(n_k)
-    oh[k] = 1.0
-    return np.concatenate([s, oh])
 
 
 def basis(V: np.ndarray, n_blk: int) -> np.ndarray:

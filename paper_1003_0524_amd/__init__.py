@@ -30,7 +30,10 @@ DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
-                    "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing")
+                    "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
+                    "exchange_nn_init", "exchange_nn_params", "exchange_nn_train", "exchange_nn_grad",
+                    "exchange_nn_predict", "exchange_nn_features", "exchange_eigh", "exchange_nn_project",
+                    "exchange_nn_expand")
 
 
 class ExchangeError(RuntimeError):
@@ -82,6 +85,23 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_query.restype = i32
     lib.exchange_timing.argtypes = [vp, i32]
     lib.exchange_timing.restype = i32
+    f32p, f64p, u64, i64 = ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64
+    vpp = ctypes.POINTER(vp)
+    sigs = {
+        "exchange_nn_init": [vp, i32, i32, i32, u64],
+        "exchange_nn_params": [vp, vp, i64, i32, i32],
+        "exchange_nn_train": [vp, vp, vp, i32, i32, ctypes.c_float, i32, f32p],
+        "exchange_nn_grad": [vp, vp, vp, i32, i32, vp, f32p],
+        "exchange_nn_predict": [vp, vp, i32, vp, i32, vp],
+        "exchange_nn_features": [vp, vp, vp, i64, u64, i32, vp, vp, vp],
+        "exchange_eigh": [vp, vpp, vp, vp, vp],
+        "exchange_nn_project": [vp, vpp, vpp, vp, i32, ctypes.c_double, vp, vp],
+        "exchange_nn_expand": [vp, vpp, vp, i32, vp, ctypes.c_double, vpp, vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = i32
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -223,6 +243,122 @@ class Exchange:
     def kernel_ms(self):
         """(mean tile-kernel ms, mean sparse-kernel ms, replays timed)."""
         return self.query(5), self.query(7), int(self.query(6))
+
+    # -- learned extrapolator ------------------------------------------------
+    @staticmethod
+    def _ptr(x):
+        """(pointer, on_device) of a contiguous torch tensor or numpy array."""
+        if hasattr(x, "data_ptr"):
+            if not x.is_contiguous():
+                raise ExchangeError(-1, "tensors must be contiguous")
+            return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda)
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ExchangeError(-1, "arrays must be C-contiguous")
+        return ctypes.c_void_p(x.ctypes.data), 0
+
+    def _ptab(self, xs):
+        if len(xs) != self.n_k:
+            raise ExchangeError(-1, f"need {self.n_k} device tensors")
+        for x in xs:
+            if not (x.is_cuda and x.is_contiguous()):
+                raise ExchangeError(-1, "per-k matrices must be contiguous device tensors")
+        return (ctypes.c_void_p * self.n_k)(*[x.data_ptr() for x in xs])
+
+    def nn_init(self, in_dim: int, hidden: int, out_dim: int, seed: int) -> None:
+        self._check(self.lib.exchange_nn_init(self.ctx, int(in_dim), int(hidden), int(out_dim),
+                                              ctypes.c_uint64(seed & (2 ** 64 - 1))))
+        self._nn = (int(in_dim), int(hidden), int(out_dim))
+
+    def nn_param_count(self) -> int:
+        I, H, O = self._nn
+        return H * I + H + H * H + H + O * H + O
+
+    def nn_get_params(self) -> np.ndarray:
+        out = np.empty(self.nn_param_count(), dtype=np.float32)
+        self._check(self.lib.exchange_nn_params(self.ctx, ctypes.c_void_p(out.ctypes.data), out.size, 0, 0))
+        return out
+
+    def nn_set_params(self, theta) -> None:
+        p, dev = self._ptr(theta)
+        self._check(self.lib.exchange_nn_params(self.ctx, p, self.nn_param_count(), 1, dev))
+
+    def nn_train(self, X, Y, epochs: int, lr: float) -> float:
+        (px, dx), (py, dy) = self._ptr(X), self._ptr(Y)
+        if dx != dy:
+            raise ExchangeError(-1, "X and Y must both be host or both be device buffers")
+        loss = ctypes.c_float()
+        self._check(self.lib.exchange_nn_train(self.ctx, px, py, int(X.shape[0]), int(epochs), float(lr), dx,
+                                               ctypes.byref(loss)))
+        return loss.value
+
+    def nn_grad(self, X, Y):
+        (px, dx), (py, dy) = self._ptr(X), self._ptr(Y)
+        if dx or dy:
+            raise ExchangeError(-1, "nn_grad takes host arrays")
+        g = np.empty(self.nn_param_count(), dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(self.lib.exchange_nn_grad(self.ctx, px, py, int(X.shape[0]), 0,
+                                              ctypes.c_void_p(g.ctypes.data), ctypes.byref(loss)))
+        return loss.value, g
+
+    def nn_predict(self, X, out=None):
+        t = self._torch
+        px, dx = self._ptr(X)
+        n = int(X.shape[0])
+        if dx:
+            if out is None:
+                out = t.empty((n, self._nn[2]), dtype=t.float32, device=X.device)
+            self._check(self.lib.exchange_nn_predict(self.ctx, px, n, ctypes.c_void_p(out.data_ptr()), 1,
+                                                     _stream_handle(t, self.device)))
+            return out
+        out = np.empty((n, self._nn[2]), dtype=np.float32)
+        self._check(self.lib.exchange_nn_predict(self.ctx, px, n, ctypes.c_void_p(out.ctypes.data), 0, None))
+        return out
+
+    def nn_features(self, P_new, P_old, m: int, seed: int):
+        """(x (m floats, device), |P_new - P_old| (device double)) for float64/complex128 device tensors."""
+        t = self._torch
+        if not (P_new.is_cuda and P_old.is_cuda and P_new.is_contiguous() and P_old.is_contiguous()):
+            raise ExchangeError(-1, "P_new and P_old must be contiguous device tensors")
+        a = t.view_as_real(P_new) if P_new.is_complex() else P_new
+        b = t.view_as_real(P_old) if P_old.is_complex() else P_old
+        if a.dtype != t.float64 or b.dtype != t.float64 or a.numel() != b.numel():
+            raise ExchangeError(-1, "P_new and P_old must be float64/complex128 of equal size")
+        x = t.empty(m, dtype=t.float32, device=P_new.device)
+        nrm = t.empty(1, dtype=t.float64, device=P_new.device)
+        self._check(self.lib.exchange_nn_features(self.ctx, ctypes.c_void_p(a.data_ptr()),
+                                                  ctypes.c_void_p(b.data_ptr()), a.numel(),
+                                                  ctypes.c_uint64(seed & (2 ** 64 - 1)), int(m),
+                                                  ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(nrm.data_ptr()),
+                                                  _stream_handle(t, self.device)))
+        return x, nrm
+
+    def eigh(self, A_k):
+        """(eigenvalues packed, eigenvectors packed) of the per-k Hermitian matrices (column-major storage)."""
+        t = self._torch
+        dev = A_k[0].device
+        w = t.empty(sum(self.n_bands), dtype=t.float64, device=dev)
+        Z = t.empty(sum(nb * nb for nb in self.n_bands), dtype=t.complex128, device=dev)
+        self._check(self.lib.exchange_eigh(self.ctx, self._ptab(A_k), ctypes.c_void_p(w.data_ptr()),
+                                           ctypes.c_void_p(Z.data_ptr()), _stream_handle(t, self.device)))
+        return w, Z
+
+    def nn_project(self, Va_k, Vb_k, Z, n_blk: int, scale: float):
+        t = self._torch
+        y = t.empty((self.n_k, n_blk * n_blk), dtype=t.float32, device=Z.device)
+        self._check(self.lib.exchange_nn_project(self.ctx, self._ptab(Va_k), self._ptab(Vb_k),
+                                                 ctypes.c_void_p(Z.data_ptr()), int(n_blk), float(scale),
+                                                 ctypes.c_void_p(y.data_ptr()), _stream_handle(t, self.device)))
+        return y
+
+    def nn_expand(self, Vanc_k, Z, n_blk: int, y, scale: float, outs):
+        t = self._torch
+        if not (y.is_cuda and y.is_contiguous() and y.dtype == t.float32):
+            raise ExchangeError(-1, "y must be a contiguous float32 device tensor")
+        self._check(self.lib.exchange_nn_expand(self.ctx, self._ptab(Vanc_k), ctypes.c_void_p(Z.data_ptr()),
+                                                int(n_blk), ctypes.c_void_p(y.data_ptr()), float(scale),
+                                                self._ptab(outs), _stream_handle(t, self.device)))
+        return outs
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -70,6 +70,9 @@ struct Plan {
 
 }  // namespace
 
+struct NnState;        // learned extrapolator (nn_abi.hpp)
+struct LearnScratch;
+
 struct exc_ctx {
   uint32_t magic = kAlive;
   std::string err;
@@ -132,6 +135,9 @@ struct exc_ctx {
   hipStream_t last_stream = nullptr;
   // accounting
   double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
+  // learned extrapolator
+  NnState* nn = nullptr;
+  LearnScratch* ls = nullptr;
 };
 
 namespace {
@@ -191,7 +197,10 @@ void release_timing(exc_ctx* c) {
   c->t_slots = c->t_next = c->t_count = 0;
 }
 
+void release_learned(exc_ctx* c);
+
 void release(exc_ctx* c) {
+  release_learned(c);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
   if (c->graph) hipGraphDestroy(c->graph);
@@ -1000,3 +1009,5 @@ exc_status exchange_timing(exc_ctx* c, int32_t n_slots) {
 }
 
 }  // extern "C"
+
+#include "nn_abi.hpp"

@@ -99,7 +99,7 @@ def normal_pairs(seed: int, start_pair: int, count: int):
 # ----------------------------------------------------------------------------
 # Configurations
 # ----------------------------------------------------------------------------
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "tiny", "small", "ragged")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "tiny", "small", "ragged", "learn")
 
 
 @dataclasses.dataclass
@@ -244,6 +244,13 @@ def make_config(name: str, seed: int = 0) -> Config:
         return Config(name, 7, seed, _hex(6.14, 9.84), q, n_k=3, n_occ=5,
                       n_bands=[13, 37, 21], ch_nrad=ch, n_pw=n_pw,
                       description="ragged tails in every dimension")
+    if name == "learn":
+        # outer-iteration tests of the learned extrapolator: more bands than the
+        # 8 x 8 block the network predicts, CPU-oracle sized
+        q = _mesh(2, 2, 2)
+        return Config(name, 8, seed, _fcc(10.26), q, n_k=4, n_occ=4, n_bands=[16] * 4,
+                      ch_nrad=_channels(1, 2, lambda l: 4 - l), n_pw=[60] * 8,
+                      description="learned-part tests: 4 k, 8 q, 16 bands, 4 occ")
     raise ValueError(f"unknown config {name!r}")
 
 
