@@ -444,6 +444,17 @@ __global__ __launch_bounds__(256) void prep_factor_kernel(const double2* src, co
   }
 }
 
+// Padded copy of each multipole-free row's coefficient run: out[r][t] =
+// coef[rowinfo[r].x + t] for t < min(rowinfo[r].y, mt), zero beyond.
+__global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, const int4* rowinfo, int n_s, int mt,
+                                                       double2* out) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n_s * mt) return;
+  const int r = (int)(e / mt), t = (int)(e % mt);
+  const int4 ri = rowinfo[r];
+  out[e] = t < ri.y ? coef[ri.x + t] : make_double2(0.0, 0.0);
+}
+
 __global__ void zero_int_kernel(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -17,6 +18,7 @@
 #include "../../include/exchange.h"
 #include "aux.hpp"
 #include "tile.hpp"
+#include "fused.hpp"
 
 using namespace exc;
 
@@ -55,6 +57,45 @@ const KernelCfg kCfgs[] = {
     CFG(M_BF16X6, 1, 64, 32, 13, 13, 4, 1, 1, 43), CFG(M_BF16X6, 1, 64, 32, 16, 16, 4, 1, 1, 42),
 };
 
+// Fused reduced-precision HERK kernels: RTW row tiles per wavefront (row
+// blocks of 64 RTW rows), NCT band tiles per pass, NB8M the largest band-tile
+// count per n'' value, KC complex k per K-loop panel.
+// coefficients per multipole-free row staged by the fused kernel (its MAXT)
+constexpr int kRunPad = FusedCfg<M_BF16X3, 1, 1, 1, 32>::MAXT;
+
+struct FusedKCfg {
+  int mode, RTW, NCT, NB8M, KC, CB, OCC;
+  void (*fn)(FusedArgs);
+  size_t lds;
+  int id;
+};
+
+#define FCFG(MODE, RTW, NCT, NB8M, KC, ID)                                                       \
+  FusedKCfg{MODE, RTW, NCT, NB8M, KC, 32, 1, fused_kernel<MODE, RTW, NCT, NB8M, KC>,               \
+            FusedCfg<MODE, RTW, NCT, NB8M, KC>::LDS_B, ID}
+// two workgroups per CU: at most 256 registers per lane and half the LDS each
+#define FCFG2(MODE, RTW, NCT, NB8M, ID)                                                          \
+  FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2>,       \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID}
+
+// Listed in order of preference among equal band-tile capacity (the two-per-CU
+// instances first: they hide more memory latency).
+const FusedKCfg kFused[] = {
+    FCFG2(M_F32, 2, 6, 3, 150),        FCFG2(M_F32, 3, 6, 3, 151),
+    FCFG2(M_BF16X3, 2, 6, 3, 160),     FCFG2(M_BF16X3, 3, 6, 3, 161),
+    FCFG2(M_BF16X6, 2, 6, 3, 170),     FCFG2(M_BF16X6, 3, 6, 3, 171),
+    FCFG2(M_BF16X3, 2, 8, 8, 162),
+    FCFG(M_F32, 3, 12, 3, 32, 120),    FCFG(M_F32, 5, 6, 3, 32, 124),
+    FCFG(M_F32, 4, 8, 8, 32, 121),     FCFG(M_F32, 2, 13, 13, 32, 123),
+    FCFG(M_F32, 2, 16, 16, 32, 122),
+    FCFG(M_BF16X3, 3, 12, 3, 32, 130), FCFG(M_BF16X3, 5, 6, 3, 32, 134),
+    FCFG(M_BF16X3, 4, 8, 8, 32, 131),  FCFG(M_BF16X3, 2, 13, 13, 32, 133),
+    FCFG(M_BF16X3, 2, 16, 16, 32, 132),
+    FCFG(M_BF16X6, 3, 12, 3, 32, 140), FCFG(M_BF16X6, 5, 6, 3, 32, 144),
+    FCFG(M_BF16X6, 4, 8, 8, 32, 141),  FCFG(M_BF16X6, 2, 13, 13, 32, 143),
+    FCFG(M_BF16X6, 2, 16, 16, 32, 142),
+};
+
 struct Plan {
   std::vector<WorkItem> items;      // generation order: pair-major, slot = index
   std::vector<int> pair_item;       // [n_pairs + 1] item range per pair
@@ -63,6 +104,9 @@ struct Plan {
   std::vector<double> slot_w;
   WorkItem* d_items = nullptr;      // generation order
   WorkItem* d_items_lpt = nullptr;  // longest-processing-time order
+  WorkItem* d_items_xq = nullptr;   // per-XCD queues, each in LPT order (fused path)
+  int32_t* d_qbeg = nullptr;        // [nq + 1]
+  int nq = 1;
   int32_t* d_slot_begin = nullptr;
   double* d_slot_w = nullptr;
   int n_slots = 0;
@@ -91,6 +135,8 @@ struct exc_ctx {
   std::vector<int64_t> u_off;
   std::vector<int> ldu;
   int32_t *d_row_chan = nullptr, *d_ch_off = nullptr, *d_ch_len = nullptr;
+  int4* d_rowinfo = nullptr;          // fused kernel: per multipole-free row (see FusedArgs)
+  double2* d_coefpad = nullptr;       // fused kernel: padded coefficient runs (see FusedArgs)
   int64_t* d_ch_coef = nullptr;
   // pairs, plans, buffers
   std::vector<PairInfo> pairs;
@@ -101,6 +147,8 @@ struct exc_ctx {
   int32_t* d_pair_begin = nullptr;
   Plan plain, bat;
   const KernelCfg* cfg = nullptr;
+  const FusedKCfg* fcfg = nullptr;    // non-null: reduced-precision HERK through the fused kernel
+  bool fused = false;
   void* d_ws = nullptr;
   double* d_dsp = nullptr;
   void* d_gpart = nullptr;
@@ -188,7 +236,9 @@ int npieces(int mode) { return mode == M_BF16X3 ? 2 : (mode == M_BF16X6 ? 3 : 1)
 
 void free_plan(Plan& p) {
   hipFree(p.d_items); hipFree(p.d_items_lpt); hipFree(p.d_slot_begin); hipFree(p.d_slot_w);
-  p.d_items = p.d_items_lpt = nullptr; p.d_slot_begin = nullptr; p.d_slot_w = nullptr;
+  hipFree(p.d_items_xq); hipFree(p.d_qbeg);
+  p.d_items = p.d_items_lpt = p.d_items_xq = nullptr; p.d_slot_begin = nullptr; p.d_slot_w = nullptr;
+  p.d_qbeg = nullptr;
 }
 
 void release_timing(exc_ctx* c) {
@@ -212,12 +262,20 @@ void release(exc_ctx* c) {
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
-                  c->d_ch_len, c->d_ch_coef, c->d_pairs, c->d_pair_w, c->d_pair_begin,
+                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
+}
+
+// Relative cost of the fused kernel's work on ncols columns of a pair: the
+// block-sparse rows and their contraction, the triangular dense product, the
+// dense contraction.
+double fused_cost(const exc_ctx* c, const PairInfo& p, int ncols) {
+  const double contract = (double)(c->n_s + p.nd) * p.nb8 * p.nb8;
+  return contract + 4.0 * c->n_s * ncols + (double)p.nd * p.nd * ncols;
 }
 
 // Relative cost of one row block (for balancing and LPT order).
@@ -238,7 +296,7 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
   P.k_item.assign(1, 0);
   P.slot_begin.assign(1, 0);
   P.slot_w.clear();
-  const int nct = c->cfg->NCT;
+  const int nct = c->fused ? c->fcfg->NCT : c->cfg->NCT;
   std::vector<double> cost;
   for (int k = 0; k < c->n_k; ++k) {
     for (int pidx = c->k_pair[k]; pidx < c->k_pair[k + 1]; ++pidx) {
@@ -255,14 +313,19 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
         w.pair = pidx; w.g0 = g0; w.g1 = g1; w.ngc = ngc; w.rb0 = rb0; w.rb1 = rb1;
         w.slot = (int)P.items.size();
         double cs = 0;
-        for (int g = g0; g < g1; g += ngc)
+        for (int g = g0; g < g1; g += ngc) {
+          if (c->fused) { cs += fused_cost(c, p, std::min(ngc, g1 - g) * p.nb8); continue; }
           for (int rb = rb0; rb < rb1; ++rb) cs += block_cost(c, p, rb, std::min(ngc, g1 - g) * p.nb8);
+        }
         P.items.push_back(w);
         P.slot_w.push_back(c->wq[p.q]);
         cost.push_back(cs);
       };
       if (!split_rows) {
         push(0, c->n_occ, 0, nrb);
+      } else if (c->fused) {
+        // the fused kernel runs every row of a column chunk: one item per n'' chunk
+        for (int g = 0; g < c->n_occ; g += ngc) push(g, std::min(c->n_occ, g + ngc), 0, nrb);
       } else {
         for (int g = 0; g < c->n_occ; g += ngc)
           for (int rb = 0; rb < nrb; ++rb) push(g, std::min(c->n_occ, g + ngc), rb, rb + 1);
@@ -280,10 +343,52 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
   for (size_t i = 0; i < order.size(); ++i) lpt[i] = P.items[order[i]];
   TRY(upload(c, &P.d_items, P.items));
   TRY(upload(c, &P.d_items_lpt, lpt));
+  // XCD queues: the q of the Coulomb factor decides the queue (all k of one q
+  // share one factor, kept in that XCD's L2); q are dealt to the queues by
+  // decreasing total cost onto the least loaded queue; LPT order inside a queue
+  {
+    const int nq = NQ_MAX;
+    std::vector<double> qcost(c->n_q, 0.0);
+    for (size_t i = 0; i < P.items.size(); ++i) qcost[c->pairs[P.items[i].pair].q] += cost[i];
+    std::vector<int> qord(c->n_q);
+    std::iota(qord.begin(), qord.end(), 0);
+    std::stable_sort(qord.begin(), qord.end(), [&](int x, int y) { return qcost[x] > qcost[y]; });
+    std::vector<int> qof(c->n_q, 0);
+    std::vector<double> load(nq, 0.0);
+    for (int q : qord) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      qof[q] = b;
+      load[b] += qcost[q];
+    }
+    std::vector<WorkItem> xq;
+    std::vector<int32_t> qbeg(1, 0);
+    for (int b = 0; b < nq; ++b) {
+      for (int i : order)
+        if (qof[c->pairs[P.items[i].pair].q] == b) xq.push_back(P.items[i]);
+      qbeg.push_back((int32_t)xq.size());
+    }
+    TRY(upload(c, &P.d_items_xq, xq));
+    TRY(upload(c, &P.d_qbeg, qbeg));
+    P.nq = nq;
+  }
   std::vector<int32_t> sb(P.slot_begin.begin(), P.slot_begin.end());
   TRY(upload(c, &P.d_slot_begin, sb));
   TRY(upload(c, &P.d_slot_w, P.slot_w));
   return EXC_OK;
+}
+
+const FusedKCfg* pick_fused(int mode, int nbt_max) {
+  const FusedKCfg* best = nullptr;
+  if (const char* ev = getenv("EXC_FUSED_CFG")) {      // a fixed configuration id (tuning runs)
+    const int id = atoi(ev);
+    for (const auto& k : kFused)
+      if (k.id == id && k.mode == mode && k.NB8M >= nbt_max && k.NCT >= nbt_max) return &k;
+  }
+  for (const auto& k : kFused) {
+    if (k.mode != mode || k.NB8M < nbt_max || k.NCT < nbt_max) continue;
+    if (!best || k.NB8M < best->NB8M) best = &k;
+  }
+  return best;
 }
 
 const KernelCfg* pick_cfg(int mode, int form, int nbt_max) {
@@ -344,6 +449,26 @@ SparseArgs sparse_args(exc_ctx* c, int dtype) {
   return s;
 }
 
+FusedArgs fused_args(exc_ctx* c, int dtype) {
+  FusedArgs f{};
+  f.pairs = c->d_pairs;
+  f.mtab = (const void* const*)c->d_mtab;
+  f.m_c64 = dtype == EXC_C64;
+  f.n_s = c->n_s; f.n_ch = c->n_ch; f.n_occ = c->n_occ;
+  f.U = c->d_U;
+  f.row_chan = c->d_row_chan; f.ch_off = c->d_ch_off; f.ch_len = c->d_ch_len; f.ch_coef = c->d_ch_coef;
+  f.coef = c->d_coef; f.cvec = c->d_cvec; f.rowinfo = c->d_rowinfo; f.coefpad = c->d_coefpad;
+  f.gpart = c->d_gpart; f.dpart = c->d_dpart;
+  f.gstride = c->gstride; f.dstride = c->dstride;
+  return f;
+}
+
+// Argument storage of the main kernel launch (tile or fused kernel).
+struct MainArgs {
+  TileArgs t;
+  FusedArgs f;
+};
+
 // A configured kernel launch: enqueued directly or added to a graph as a node.
 struct KLaunch {
   const void* fn = nullptr;
@@ -383,6 +508,7 @@ const void* sparse_fn(const exc_ctx* c) {
 
 // Block-sparse rows of pairs [pair0, pair0 + npairs). Returns false when there is nothing to do.
 bool cfg_sparse(exc_ctx* c, int dtype, int pair0, int npairs, SparseArgs& s, KLaunch& L) {
+  if (c->fused) return false;                    // the fused kernel does the block-sparse rows itself
   const bool packs = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;   // packs the dense rows too
   if (!packs && c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return false;
   s = sparse_args(c, dtype);
@@ -418,15 +544,29 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   L.arg = &r;
 }
 
-void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent, TileArgs& a,
+void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent, MainArgs& m,
               KLaunch& L) {
+  L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
+  L.shmem = 0;
+  if (c->fused) {
+    FusedArgs& f = m.f;
+    f = fused_args(c, dtype);
+    f.items = persistent ? c->bat.d_items_xq : items;
+    f.n_items = n;
+    f.counter = persistent ? c->d_counter : nullptr;
+    f.qbeg = c->bat.d_qbeg;
+    f.nq = c->bat.nq;
+    L.block = dim3(256);
+    L.fn = (const void*)c->fcfg->fn;
+    L.arg = &f;
+    return;
+  }
+  TileArgs& a = m.t;
   a = tile_args(c, dtype);
   a.items = items;
   a.n_items = n;
   a.counter = persistent ? c->d_counter : nullptr;
-  L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
   L.block = dim3(64 * c->cfg->NW());
-  L.shmem = 0;
   L.fn = (const void*)c->cfg->fn;
   L.arg = &a;
 }
@@ -446,7 +586,7 @@ void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
 
 void launch_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, hipStream_t st) {
   if (n <= 0) return;
-  TileArgs a;
+  MainArgs a;
   KLaunch L;
   cfg_tile(c, dtype, items, n, false, a, L);
   (void)enqueue(L, st);
@@ -481,7 +621,7 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   HIPCHK(c, hipGraphCreate(&g, 0));
   const bool timed = c->t_slots > 0;
   for (auto& t : c->tnode) t = nullptr;
-  int32_t one = 1;
+  int32_t one = NQ_MAX;                 // work counters to clear (one per queue)
   int32_t* ctr = c->d_counter;
   void* zargs[2] = {&ctr, &one};
   hipKernelNodeParams zp{};
@@ -507,7 +647,7 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
     last = node;
   }
   e = add_ev(1);
-  TileArgs ta;
+  MainArgs ta;
   if (e == hipSuccess) {
     cfg_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
     e = add_node(g, L, &last, &node);
@@ -622,6 +762,15 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   c->nbt_max = (c->nb_max + 7) / 8;
   c->cfg = pick_cfg(c->precision, c->form, c->nbt_max);
   if (!c->cfg) { fail(c, EXC_EUNSUPPORTED, "no tile configuration for n_b = %d", c->nb_max); return bail(EXC_EUNSUPPORTED); }
+  if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
+    const char* ev = getenv("EXC_FUSED");
+    c->fcfg = pick_fused(c->precision, c->nbt_max);
+    // the fused kernel stages 64 rows per column for a chunk of 32 multipole-free
+    // rows: channels of up to 33 rows
+    int maxb = 0;
+    for (int ch = 0; ch < c->n_ch; ++ch) maxb = std::max(maxb, c->nrad[ch] - 1);
+    c->fused = c->fcfg && maxb <= 33 && !(ev && ev[0] == '0');
+  }
   const int BM = c->cfg->BM;
 
   c->nd.resize(c->n_q); c->nmb.resize(c->n_q); c->ldu.resize(c->n_q); c->u_off.resize(c->n_q);
@@ -649,6 +798,17 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       IHIP(hipMemcpy(c->d_cvec, cv->C, (size_t)c->n_s * 16, kind));
     }
     ITRY(upload(c, &c->d_row_chan, row_chan));
+    {
+      // per multipole-free row r (entry i of channel ch, b = ch_len): the coefficient
+      // run L_c[i..b-1][i] starts at column-major index i*b + i of the channel's block
+      std::vector<int4> ri(std::max(1, c->n_s));
+      for (int r = 0; r < c->n_s; ++r) {
+        const int ch = row_chan[r], i = r - c->ch_off[ch], b = c->ch_len[ch];
+        ri[r] = make_int4((int)(c->ch_coef[ch] + (int64_t)i * b + i), b - i, c->n_s + ch, 0);
+      }
+      ITRY(upload(c, &c->d_rowinfo, ri));
+      ITRY(dalloc(c, &c->d_coefpad, (size_t)std::max(1, c->n_s) * kRunPad));
+    }
     ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));
     ITRY(upload(c, &c->d_ch_len, std::vector<int32_t>(c->ch_len.begin(), c->ch_len.end())));
     ITRY(upload(c, &c->d_ch_coef, c->ch_coef));
@@ -717,6 +877,14 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       return bail(EXC_EHIP);
     }
     if (info[c->n_q]) { fail(c, EXC_ENOTPD, "a multipole-free channel block D_c is not positive definite"); return bail(EXC_ENOTPD); }
+    if (c->n_s > 0) {
+      // the fused kernel's padded runs of the (now factored) channel coefficients
+      const long ne = (long)c->n_s * kRunPad;
+      hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, c->d_coef,
+                         c->d_rowinfo, c->n_s, kRunPad, c->d_coefpad);
+      IHIP(hipGetLastError());
+      IHIP(hipStreamSynchronize(st));
+    }
     for (int q = 0; q < c->n_q; ++q)
       if (info[q]) { fail(c, EXC_ENOTPD, "v(q) is not positive definite at q = %d (pivot %d)", q, info[q]); return bail(EXC_ENOTPD); }
   }
@@ -729,7 +897,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   // multipole corrections). Reduced precision: each column packed into split
   // planes [plane][row], rows = sparse rows padded to 8 then dense rows padded
   // to 32 (elements of the mode's storage type).
-  const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
+  const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64 && !c->fused;
   c->ns_pad = (c->n_s + 7) / 8 * 8;
   const int ws_cols = split_ws ? 2 * npieces(c->precision) : 1;   // planes per column
   int64_t ws_total = 0, m_max = 0;
@@ -745,7 +913,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
                                : (c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch);
       p.m_off = moff; p.ws_off = ws_total; p.u_off = c->u_off[q]; p.ldu = c->ldu[q]; p.ldw = std::max(1, ldw);
       moff += (int64_t)c->n_occ * p.nb * p.nmb;
-      ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
+      if (!c->fused) ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
       c->pairs.push_back(p);
       c->pair_w.push_back(c->wq[q]);
       // accounting (nominal: sparse-aware method, Hermitian upper triangle)
@@ -779,7 +947,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(upload(c, &c->d_pair_begin, std::vector<int32_t>(c->k_pair.begin(), c->k_pair.end())));
   const size_t wsz = split_ws ? lds_elem_size(c->precision) : 16;
   ITRY(dalloc(c, (char**)&c->d_ws, (size_t)std::max<int64_t>(1, ws_total) * wsz));
-  if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
+  if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64 && !c->fused) {
     ITRY(dalloc(c, &c->d_dsp, c->pairs.size() * (size_t)c->n_occ * c->nb_max));
     IHIP(hipMemset(c->d_dsp, 0, c->pairs.size() * (size_t)c->n_occ * c->nb_max * sizeof(double)));
   }
@@ -808,21 +976,23 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   c->h_vtab.assign(c->n_k, nullptr);
   IHIP(hipMemset(c->d_mtab, 0, c->n_k * sizeof(void*)));
   IHIP(hipMemset(c->d_vtab, 0, c->n_k * sizeof(void*)));
-  ITRY(dalloc(c, &c->d_counter, 1));
+  ITRY(dalloc(c, &c->d_counter, (size_t)NQ_MAX));
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
 
+  const void* main_fn = c->fused ? (const void*)c->fcfg->fn : (const void*)c->cfg->fn;
+  const int main_threads = c->fused ? 256 : 64 * c->cfg->NW();
   {
     hipFuncAttributes fa{};
-    IHIP(hipFuncGetAttributes(&fa, (const void*)c->cfg->fn));
-    if (fa.maxThreadsPerBlock < 64 * c->cfg->NW()) {
-      fail(c, EXC_EUNSUPPORTED, "tile kernel %d allows %d threads per block, needs %d", c->cfg->id,
-           fa.maxThreadsPerBlock, 64 * c->cfg->NW());
+    IHIP(hipFuncGetAttributes(&fa, main_fn));
+    if (fa.maxThreadsPerBlock < main_threads) {
+      fail(c, EXC_EUNSUPPORTED, "kernel %d allows %d threads per block, needs %d",
+           c->fused ? c->fcfg->id : c->cfg->id, fa.maxThreadsPerBlock, main_threads);
       return bail(EXC_EUNSUPPORTED);
     }
   }
   int n_cu = 0, occ = 0;
   IHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)c->cfg->fn, 64 * c->cfg->NW(), 0));
+  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, main_fn, main_threads, 0));
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   c->persist_grid = std::max(1, n_cu * std::max(1, occ));
@@ -972,7 +1142,7 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 0: *value = c->bat.n_slots; return EXC_OK;
     case 1: *value = c->flops_nominal; return EXC_OK;
     case 2: *value = c->flops_exec; return EXC_OK;
-    case 3: *value = c->cfg ? c->cfg->id : -1; return EXC_OK;
+    case 3: *value = c->fused ? c->fcfg->id : (c->cfg ? c->cfg->id : -1); return EXC_OK;
     case 4: *value = c->bytes_alg; return EXC_OK;
     case 5:
     case 7: {

@@ -1,0 +1,604 @@
+// Fused exchange kernel for the reduced-precision Cholesky/HERK form: one work
+// item (pair (k,q), a range of n'' values) reads its columns of M once and
+// produces the item's Gram partial
+//
+//   G = sum_{n''} Y_{n''}^H Y_{n''},   Y = [ Y_s ; Y_d ],
+//   Y_s = L_c^H A_c + l_c a_{j(c)}   (block-sparse multipole-free rows, FP64 VALU)
+//   Y_d = L22^H A_d                  (dense rows, MFMA in the mode's pieces)
+//
+// the vector-matrix-vector form of Sec. II.C with v = L L^H and the sparse
+// structure of the transformed Coulomb matrix (Fig. 1).
+//
+// Layout of the work in one workgroup (4 wavefronts, one per SIMD):
+//  * sparse rows, in chunks of GR = 64 rows: each lane computes one row of Y_s
+//    for the columns of its wavefront in FP64, writes its split pieces to LDS
+//    and adds |Y|^2 to the FP64 diagonal; then the Gram tiles are contracted
+//    over the chunk on MFMA;
+//  * dense rows, in row blocks of BM = 64 RTW rows: the accumulators of the
+//    whole row block live in registers (wavefront w owns row tiles w, w+4, ...),
+//    the K loop streams double-buffered LDS panels of A_d (converted from M to
+//    the mode's pieces on the way in) and reads the factor's pieces straight
+//    from global memory (L2: the factor of q is shared by every k); row tiles
+//    whose rows precede the chunk's k range are skipped (L22^H is upper
+//    triangular); then the rows go through LDS, GR at a time, into the Gram
+//    contraction.
+// Partials: one slot per item (Gram tiles in accumulator order and the FP64
+// diagonal per band), summed per k in a fixed order by the reduction kernel.
+#pragma once
+#include "common.hpp"
+#include "tile.hpp"
+
+#include <type_traits>
+
+namespace exc {
+
+// Buffer loads: one scalar resource per item (base, size in bytes), a per-lane
+// 32-bit offset and a wave-uniform scalar offset, so that the many loads of a
+// K panel share one address register. Offsets at or beyond the size read zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class OP>
+__device__ __forceinline__ OP buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(OP) == 16) {
+    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  } else if constexpr (sizeof(OP) == 8) {
+    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  } else {
+    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  }
+}
+
+// 16 bytes per lane from a buffer straight into LDS: lane l writes lds + 16 l
+// (the LDS address must be wave-uniform). A device function, not a lambda: the
+// host pass of the compiler has no such builtin.
+__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t r, void* lds, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, (int)voff,
+                                           (int)soff, 0, 0);
+}
+
+// Values the whole workgroup shares, moved to scalar registers: loads of them
+// are vector loads (the kernel also writes global memory), and buffer
+// resources built from vector registers would need a loop over lanes.
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* p) { return (T*)uni((int64_t)p); }
+
+// Work queues of the persistent launch: NQ queues (one per XCD: consecutive
+// workgroups are dispatched to the 8 XCDs in turn, so workgroup b serves queue
+// b % NQ first), each a range of the item array with its own atomic counter;
+// a workgroup whose queue is empty takes items from the following queues.
+constexpr int NQ_MAX = 8;
+
+struct FusedArgs {
+  const PairInfo* pairs;
+  const WorkItem* items;
+  int32_t n_items;
+  int32_t* counter;               // non-null: persistent mode ([nq] counters)
+  const int32_t* qbeg;            // [nq + 1] item range of each queue (persistent mode)
+  int32_t nq;
+  const void* const* mtab;
+  int32_t m_c64;
+  int32_t n_s, n_ch, n_occ;
+  const void* U;                  // prepared factor planes
+  const int32_t* row_chan;
+  const int32_t* ch_off;
+  const int32_t* ch_len;
+  const int64_t* ch_coef;
+  const double2* coef;            // L_c (column-major, per channel)
+  const double2* cvec;            // l_c per multipole-free row
+  const double2* coefpad;         // [n_s][MAXT] the first MAXT entries of each row's run, zero padded
+  const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
+                                  // {index in coef of conj-coefficient run L_c[i..b-1][i], b - i,
+                                  //  multipole row n_s + c, 0}
+  void* gpart;
+  double* dpart;
+  int32_t gstride, dstride;
+};
+
+template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 32, int OCC = 1>
+struct FusedCfg {
+  using T = Traits<MODE>;
+  using lds_t = typename T::lds_t;
+  using acc_t = typename T::acc_t;
+  using accv_t = typename T::accv_t;
+  static constexpr int NW = 4, NT = 256;
+  static constexpr int NRT = 4 * RTW, BM = 16 * NRT;   // row tiles / rows of a dense row block
+  static constexpr int GR = 64;                         // rows per Gram chunk (one row tile per wavefront)
+  static constexpr int NP = T::NPIECE, KS = T::KS, KPL = KS / 4, NPL = 2 * NP;
+  static constexpr int NCC = NCT * 8;
+  static constexpr int ESZ = (int)sizeof(lds_t);
+  static constexpr int EPV = 16 / ESZ;                  // elements per 16 bytes
+  static constexpr int LDK = KC + EPV;                  // A panel pitch (k contiguous per column)
+  static constexpr int APL = NCC * LDK;
+  static constexpr int ABUF = NPL * APL;
+  static constexpr int LDR = GR + EPV;                  // Gram stage pitch (rows contiguous per column)
+  static constexpr int YPL = NCC * LDR;
+  static constexpr int YS = NPL * YPL;
+  static constexpr int NPT = NB8M * (NB8M + 1) / 2;
+  static constexpr int NPW = (NPT + NW - 1) / NW;
+  static constexpr bool GSTREAM = NPW > 8;
+  static constexpr int NU = NCC * KC / EPV;             // A panel units (EPV consecutive k of one column)
+  static constexpr int GS = 32, CB = CBX;                // sparse step: rows, columns
+  static constexpr int MAXT = 16;                        // coefficients per row staged in LDS (longer runs: global)
+  static constexpr int SPL = GS + EPV;                   // sparse stage pitch
+  static constexpr int COEF_B = GS * MAXT * 16;          // one row chunk of the padded coefficient table
+  static constexpr int SPARSE_B = 2 * CB * 1024 + NPL * NCC * SPL * ESZ + 2 * COEF_B;
+  static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel (complex128 worst case)
+  static constexpr int PL_B = ABUF * ESZ;               // converted panel
+  static constexpr size_t DENSE_B = (size_t)(RAW_B + PL_B > YS * ESZ ? RAW_B + PL_B : YS * ESZ);
+  static constexpr size_t MAIN_RAW = DENSE_B > (size_t)SPARSE_B ? DENSE_B : (size_t)SPARSE_B;
+  static constexpr size_t MAIN_B = (MAIN_RAW + 15) / 16 * 16;
+  // s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: expcnt and lgkmcnt at their maxima)
+  static constexpr int WAIT_VM0 = 0x0F70;
+  static constexpr size_t DACC_B = (size_t)NW * NCC * 2 * sizeof(double);
+  static constexpr size_t LDS_B = MAIN_B + DACC_B;
+  static_assert(MODE != M_F64, "the fused kernel serves the reduced-precision modes");
+  static_assert(RTW >= 1 && RTW <= 5, "one to five row tiles per wavefront");
+  static_assert(KC % KS == 0 && KC % EPV == 0, "K panel is a whole number of MFMA steps");
+  static_assert(GR % KS == 0, "Gram chunk is a whole number of MFMA steps");
+  static_assert(LDS_B + 16 <= 163840 / OCC, "fused configuration exceeds its share of the 160 KB of LDS");
+  static_assert(CB % 8 == 0 && CB >= 8, "sparse step: whole column pairs per wavefront");
+};
+
+template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 32, int OCC = 1>
+__global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
+  using C = FusedCfg<MODE, RTW, NCT, NB8M, KC, CBX, OCC>;
+  using lds_t = typename C::lds_t;
+  using acc_t = typename C::acc_t;
+  using accv_t = typename C::accv_t;
+  using op_t = decltype(lds_operand<MODE>((const lds_t*)nullptr));
+  constexpr int NW = C::NW, NT = C::NT, NP = C::NP, KS = C::KS, KPL = C::KPL, NPL = C::NPL;
+  constexpr int NCC = C::NCC, LDK = C::LDK, APL = C::APL, LDR = C::LDR, YPL = C::YPL, GR = C::GR;
+  constexpr int EPV = C::EPV, BM = C::BM, NRT = C::NRT;
+
+  __shared__ __align__(16) unsigned char smem[C::LDS_B];
+  __shared__ int s_item;
+  unsigned char* Raw = smem;                   // [NCC][KC] complex, as loaded   (K loop)
+  lds_t* Apl = (lds_t*)(smem + C::RAW_B);      // [NPL][NCC][LDK] pieces          (K loop)
+  lds_t* Ys = (lds_t*)smem;                    // [NPL][NCC][LDR] (Gram stage; aliases the K panels)
+  double* Dacc = (double*)(smem + C::MAIN_B);  // [NW][NCC][2]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: branches on it stay scalar
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int c8 = l16 & 7, part = l16 >> 3;
+
+  int qi = a.counter ? (int)(blockIdx.x % a.nq) : 0, empty = 0;
+  for (int iter = 0;; ++iter) {
+    int idx;
+    if (a.counter) {
+      if (tid == 0) s_item = atomicAdd(a.counter + qi, 1);
+      __syncthreads();
+      idx = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+      const int q0 = a.qbeg[qi], q1 = a.qbeg[qi + 1];
+      if (q0 + idx >= q1) {                        // this queue is drained: try the next one
+        if (++empty >= a.nq) break;
+        qi = (qi + 1) % a.nq;
+        continue;
+      }
+      empty = 0;
+      idx = __builtin_amdgcn_readfirstlane(q0 + idx);
+    } else {
+      if (iter > 0) break;
+      idx = blockIdx.x;
+      if (idx >= a.n_items) break;
+    }
+
+    WorkItem wi = a.items[idx];
+    wi.pair = uni(wi.pair); wi.g0 = uni(wi.g0); wi.g1 = uni(wi.g1); wi.ngc = uni(wi.ngc); wi.slot = uni(wi.slot);
+    PairInfo pi = a.pairs[wi.pair];
+    pi.k = uni(pi.k); pi.nb = uni(pi.nb); pi.nmb = uni(pi.nmb); pi.nd = uni(pi.nd); pi.nb8 = uni(pi.nb8);
+    pi.m_off = uni(pi.m_off); pi.u_off = uni(pi.u_off); pi.ldu = uni(pi.ldu);
+    const int nb = pi.nb, nb8 = pi.nb8, nbt = nb8 >> 3;
+    const int npt = nbt * (nbt + 1) / 2;
+    const int nd = pi.nd;
+    const int esz = a.m_c64 ? 8 : 16;
+    const char* mbase = uni((const char*)a.mtab[pi.k]) + pi.m_off * esz;
+    const __amdgpu_buffer_rsrc_t mrs = make_rsrc(mbase, (uint32_t)((long)a.n_occ * nb * pi.nmb * esz));
+    const lds_t* Ug = (const lds_t*)a.U + pi.u_off;
+    const long plane = (long)pi.ldu * pi.ldu;
+    const __amdgpu_buffer_rsrc_t urs = make_rsrc(Ug, (uint32_t)(NPL * plane * C::ESZ));
+    const uint32_t u_lane = (uint32_t)((l16 * pi.ldu + KPL * lq) * C::ESZ);
+
+    constexpr int NPWR = C::GSTREAM ? 1 : C::NPW;
+    accv_t gacc[NPWR];
+#pragma unroll
+    for (int s = 0; s < NPWR; ++s) gacc[s] = accv_t{0, 0, 0, 0};
+    acc_t* gp = (acc_t*)a.gpart + (long)wi.slot * a.gstride;
+    if constexpr (C::GSTREAM) {
+      for (int s = 0; s < C::NPW; ++s) {
+        const int tp = w + NW * s;
+        if (tp < npt)
+          for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] = (acc_t)0;
+      }
+    }
+    for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
+
+    // ---- contraction of the staged GR rows into this wave's Gram tiles ----
+    // rows_c: rows of the stage (GR dense, GS sparse), pitch: its row pitch
+    auto contract_chunk = [&](const lds_t* Ys, int ng, auto rows_c, int pitch) {
+      constexpr int ROWS = decltype(rows_c)::value;
+      auto one = [&](int tp, accv_t acc) -> accv_t {
+        int I, J;
+        tp_to_ij(tp, I, J);
+        for (int g = 0; g < ng; ++g) {
+          const int cA = g * nb8 + I * 8 + c8, cB = g * nb8 + J * 8 + c8;
+#pragma unroll
+          for (int ks = 0; ks < ROWS / KS; ++ks) {
+            const int kofs = ks * KS + KPL * lq;
+            op_t ao[NP], bo[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              ao[p] = lds_operand<MODE>(Ys + (part * NP + p) * NCC * pitch + cA * pitch + kofs);
+              bo[p] = lds_operand<MODE>(Ys + (part * NP + p) * NCC * pitch + cB * pitch + kofs);
+            }
+            if constexpr (NP == 1) {
+              acc = mfma(ao[0], bo[0], acc);
+            } else {
+#pragma unroll
+              for (int pr = 0; pr < C::T::NPROD; ++pr) acc = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], acc);
+            }
+          }
+        }
+        return acc;
+      };
+      if constexpr (C::GSTREAM) {
+        for (int s = 0; s < C::NPW; ++s) {
+          const int tp = w + NW * s;
+          if (tp >= npt) break;
+          const accv_t acc = one(tp, accv_t{0, 0, 0, 0});
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] += acc[i];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NPWR; ++s) {
+          const int tp = w + NW * s;
+          if (tp < npt) gacc[s] = one(tp, gacc[s]);
+        }
+      }
+    };
+
+    for (int gbase = wi.g0; gbase < wi.g1; gbase += wi.ngc) {
+      const int ng = min(wi.ngc, wi.g1 - gbase);
+      const int ncols = ng * nb8;
+      auto col_index = [&](int c, int& n) -> long {       // item column -> M column (n'', n); n >= nb: padding
+        const int g = c / nb8;
+        n = c - g * nb8;
+        return (long)(gbase + g) * nb + n;
+      };
+
+      // ================= multipole-free rows (block-sparse) =================
+      // Steps of GS rows x CB columns. The rows [sr0, sr0 + 64) of each column of the
+      // step (every row a multipole-free row of the chunk needs: channels are at most
+      // 33 rows long) go straight from M into LDS one step ahead (1 KB per column,
+      // double buffered); the multipole values come through registers, also one step
+      // ahead. Each wavefront owns two columns per pass (lanes 0-31 and 32-63, one
+      // row each), so the FP64 sums of |Y|^2 are reduced in a fixed order.
+      if (a.n_s > 0) {
+        constexpr int GS = C::GS, CB = C::CB, SPL = C::SPL;
+        const int nrc = (a.n_s + GS - 1) / GS, ncb = (ncols + CB - 1) / CB;
+        const int nsteps = nrc * ncb;
+        const int rl = lane & 31, half = lane >> 5;
+        lds_t* Ss = (lds_t*)(smem + 2 * CB * 1024);       // sparse stage, after the two M buffers
+        u4_t mp_next[CB / 8];
+        // row data of the lane's row: l_c, run length, multipole row; the coefficient runs
+        // of a row chunk go to LDS (rows of 16 complex), one chunk ahead
+        const double2* Cf = (const double2*)(smem + 2 * CB * 1024 + NPL * NCC * SPL * C::ESZ);   // [2][GS][MAXT]
+        const __amdgpu_buffer_rsrc_t crs = make_rsrc(a.coefpad, (uint32_t)(a.n_s * C::MAXT * 16));
+        struct RowData { double2 lc; int cs, len, mrow; };
+        auto load_rows = [&](int sr, RowData& d) {
+          const int rr = sr + rl;
+          d.len = 0; d.cs = 0; d.mrow = a.n_s;
+          d.lc = make_double2(0.0, 0.0);
+          if (rr < a.n_s) {
+            const int4 ri = a.rowinfo[rr];
+            d.cs = ri.x; d.len = ri.y; d.mrow = ri.z;
+            d.lc = a.cvec[rr];
+          }
+          // GS rows x MAXT complex = 8 KB: 8 instructions of 4 rows each
+          const int cbuf = (sr / GS) & 1;
+#pragma unroll
+          for (int t = 0; t < (C::COEF_B / 1024 + NW - 1) / NW; ++t) {
+            const int m = w + NW * t;
+            if (m < C::COEF_B / 1024)
+              lds_load16(crs, (void*)(Cf + (cbuf * GS + m * 4) * C::MAXT),
+                         (uint32_t)(((sr + m * 4) * C::MAXT) * 16 + lane * 16), 0u);
+          }
+        };
+        RowData rd, rd_next;
+        auto sparse_prefetch = [&](int st) {
+          const int sr0 = (st / ncb) * GS, cb0 = (st % ncb) * CB;
+          unsigned char* S1 = Raw + (st & 1) * (CB * 1024);
+          // 1 KB per column: rows sr0 .. sr0 + 63 (complex128) or .. + 127 (complex64)
+#pragma unroll
+          for (int t = 0; t < CB / NW; ++t) {
+            const int cl = w + NW * t, c = cb0 + cl;
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = c < ncols && n < nb;
+            const uint32_t vo = ok ? (uint32_t)((col * pi.nmb + sr0) * esz + lane * 16) : 0x80000000u;
+            lds_load16(mrs, S1 + cl * 1024, vo, 0u);
+          }
+          // multipole value of each (row, column) this lane computes
+#pragma unroll
+          for (int t = 0; t < CB / 8; ++t) {
+            const int c = cb0 + 2 * (w + NW * t) + half, r = sr0 + rl;
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = c < ncols && n < nb && r < a.n_s;
+            // the step's row chunk is the current one or the next
+            const int mrow = (st % ncb == 0) ? rd_next.mrow : rd.mrow;
+            const uint32_t vo = ok ? (uint32_t)((col * pi.nmb + mrow) * esz) : 0x80000000u;
+            if (a.m_c64) {
+              const uint2 v = buf_load<uint2>(mrs, vo, 0u);
+              mp_next[t] = u4_t{v.x, v.y, 0u, 0u};
+            } else {
+              mp_next[t] = buf_load<u4_t>(mrs, vo, 0u);
+            }
+          }
+        };
+        __syncthreads();                              // earlier users of the LDS are done
+        load_rows(0, rd_next);
+        sparse_prefetch(0);
+        for (int st = 0; st < nsteps; ++st) {
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
+          __syncthreads();                            // step st staged; the other buffer and the stage are free
+          u4_t mp[CB / 8];
+#pragma unroll
+          for (int t = 0; t < CB / 8; ++t) mp[t] = mp_next[t];
+          const int sr0 = (st / ncb) * GS, cb0 = (st % ncb) * CB;
+          const unsigned char* S1 = Raw + (st & 1) * (CB * 1024);
+          if (st % ncb == 0) {                        // a new row chunk: its row data, then the next chunk's
+            rd = rd_next;
+            load_rows(sr0 + GS, rd_next);
+          }
+          if (st + 1 < nsteps) sparse_prefetch(st + 1);   // needs the row data of step st + 1's chunk
+          const int r = sr0 + rl;
+#pragma unroll
+          for (int t = 0; t < CB / 8; ++t) {
+            const int cl = 2 * (w + NW * t) + half, c = cb0 + cl;
+            double yr = 0.0, yi = 0.0;
+            int n = 0;
+            (void)col_index(c, n);
+            if (r < a.n_s && c < ncols && n < nb) {
+              // Y_s[r] = sum_{j >= i} conj(L_c[j][i]) A[first + j] + l_c[i] A[multipole row of c]:
+              // the run of L_c[j][i], j >= i, meets the rows r, r + 1, ... of M
+              auto term = [&](double2 l, int row) {
+                double xr, xi;
+                if (a.m_c64) {
+                  const float2 v = *(const float2*)(S1 + cl * 1024 + row * 8);
+                  xr = v.x; xi = v.y;
+                } else {
+                  const double2 v = *(const double2*)(S1 + cl * 1024 + row * 16);
+                  xr = v.x; xi = v.y;
+                }
+                yr += l.x * xr + l.y * xi;
+                yi += l.x * xi - l.y * xr;
+              };
+              const double2* cfl = Cf + (((st / ncb) & 1) * GS + rl) * C::MAXT;
+              const int tl = min(rd.len, C::MAXT);
+              for (int t = 0; t < tl; ++t) term(cfl[t], rl + t);
+              for (int t = C::MAXT; t < rd.len; ++t) term(a.coef[rd.cs + t], rl + t);
+              const double2 lc = rd.lc;
+              double xmr, xmi;
+              if (a.m_c64) {
+                xmr = __uint_as_float(mp[t].x); xmi = __uint_as_float(mp[t].y);
+              } else {
+                xmr = __hiloint2double((int)mp[t].y, (int)mp[t].x);
+                xmi = __hiloint2double((int)mp[t].w, (int)mp[t].z);
+              }
+              yr += lc.x * xmr - lc.y * xmi;
+              yi += lc.x * xmi + lc.y * xmr;
+            }
+            if (c < NCC) {
+              put_real<MODE>(Ss + (0 * NP) * NCC * SPL + c * SPL + rl, NCC * SPL, yr);
+              put_real<MODE>(Ss + (1 * NP) * NCC * SPL + c * SPL + rl, NCC * SPL, yi);
+            }
+            double d = yr * yr + yi * yi;
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) d += __shfl_xor(d, o);    // within the 32-lane half
+            if (rl == 0 && c < NCC) Dacc[(w * NCC + c) * 2] += d;
+          }
+          if (st % ncb == ncb - 1) {                  // the chunk's columns are staged: contract
+            __syncthreads();
+            contract_chunk(Ss, ng, std::integral_constant<int, GS>{}, SPL);
+          }
+        }
+      }
+
+      // ================= dense rows: row blocks of BM rows =================
+      for (int r0 = 0; r0 < nd; r0 += BM) {
+        accv_t acc[RTW][NCT];
+#pragma unroll
+        for (int ii = 0; ii < RTW; ++ii)
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) acc[ii][j] = accv_t{0, 0, 0, 0};
+        const int kc0 = (r0 / KC) * KC;
+        const int kend = (nd + KC - 1) / KC * KC;
+        const int nrt_nd = (nd - r0 + 15) / 16;          // row tiles holding rows < nd
+
+        // ---- K panels of A_d: global -> LDS directly (buffer_load ... lds), then
+        // converted in LDS into the mode's pieces. One wave instruction moves 1 KB:
+        // two columns of KC complex128 (or four of complex64), lanes in order.
+        constexpr int NI = C::RAW_B / 1024;                // instructions per panel
+        constexpr int NIW = (NI + NW - 1) / NW;            // per wavefront
+        uint32_t r_off[NIW];
+        {
+          const int cpi = a.m_c64 ? 4 : 2;                 // columns per instruction
+          const int lpc = 64 / cpi;                        // lanes per column
+#pragma unroll
+          for (int t = 0; t < NIW; ++t) {
+            const int idx = w + NW * t;
+            const int c = idx * cpi + lane / lpc;
+            const int k = (lane % lpc) * (a.m_c64 ? 2 : 1);
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = idx < NI && c < ncols && n < nb && c * KC * esz < C::RAW_B;
+            // invalid columns: an offset past the end of any pair block (2 GiB; no wrap-around
+            // with the scalar offset added) reads zero
+            r_off[t] = ok ? (uint32_t)((col * pi.nmb + a.n_s + k) * esz) : 0x80000000u;
+          }
+        }
+        const int ni = (NCC * KC * esz + 1023) / 1024;     // instructions this dtype needs
+        auto issue_raw = [&](int kc) {
+#pragma unroll
+          for (int t = 0; t < NIW; ++t) {
+            const int idx = w + NW * t;
+            if (idx < ni)
+              lds_load16(mrs, Raw + idx * 1024, r_off[t], (uint32_t)(kc * esz));
+          }
+        };
+        // raw -> pieces: consecutive lanes take consecutive elements (a wavefront reads
+        // 1 KB of contiguous LDS per instruction, free of bank conflicts) and write
+        // their pieces as single elements of the planes
+        auto convert = [&](int kc) {
+          for (int e = tid; e < NCC * KC; e += NT) {
+            const int c = e / KC, k = e % KC;
+            double re = 0.0, im = 0.0;
+            if (kc + k < nd) {
+              if (a.m_c64) {
+                const float2 v = *(const float2*)(Raw + e * 8);
+                re = (double)v.x;
+                im = (double)v.y;
+              } else {
+                const double2 v = *(const double2*)(Raw + e * 16);
+                re = v.x;
+                im = v.y;
+              }
+            }
+            put_real<MODE>(Apl + c * LDK + k, APL, re);
+            put_real<MODE>(Apl + NP * APL + c * LDK + k, APL, im);
+          }
+        };
+
+        __syncthreads();                              // the stage is free
+        issue_raw(kc0);
+        __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
+        __syncthreads();
+        for (int kc = kc0; kc < kend; kc += KC) {
+          convert(kc);
+          __syncthreads();                            // pieces ready, raw panel free
+          // active row tiles: rows r0 + 16 rt <= kc + KC - 1 (upper triangular factor), rows < nd;
+          // this wave owns tiles w, w + 4, ...: its first na of them are active
+          const int nact = min(min(NRT, (kc + KC - 1 - r0) / 16 + 1), nrt_nd);
+          const int na = min(RTW, max(0, (nact - w + 3) / 4));
+          const bool more = kc + KC < kend;
+          // straight-line panel body for a compile-time count of active tiles
+          auto body = [&](auto na_c) {
+            constexpr int NA = decltype(na_c)::value;
+            // factor pieces of the active tiles, straight from global memory (L2)
+            op_t ureg[NA > 0 ? NA : 1][KC / KS][2][NP];
+#pragma unroll
+            for (int ii = 0; ii < NA; ++ii) {
+              const long row0 = (long)(r0 + 16 * (w + 4 * ii)) * pi.ldu + kc;
+#pragma unroll
+              for (int ks = 0; ks < KC / KS; ++ks)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                  for (int p = 0; p < NP; ++p)
+                    ureg[ii][ks][h][p] = buf_load<op_t>(
+                        urs, u_lane, (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ));
+            }
+            if (more) issue_raw(kc + KC);              // in flight while this panel runs on MFMA
+#pragma unroll
+            for (int ks = 0; ks < KC / KS; ++ks) {
+              const int kofs = ks * KS + KPL * lq;
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int bpart = part ^ h;
+                const bool neg = (h == 1) && (part == 0);
+#pragma unroll
+                for (int j = 0; j < NCT; ++j) {
+                  op_t bop[NP];
+#pragma unroll
+                  for (int p = 0; p < NP; ++p) {
+                    bop[p] = lds_operand<MODE>(Apl + (bpart * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
+                    if (neg) bop[p] = negate(bop[p]);
+                  }
+                  // products outer, tiles inner: consecutive MFMAs use different accumulators
+#pragma unroll
+                  for (int pr = 0; pr < C::T::NPROD; ++pr)
+#pragma unroll
+                    for (int ii = 0; ii < NA; ++ii)
+                      acc[ii][j] = mfma(ureg[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
+                                        bop[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
+                }
+              }
+            }
+          };
+#ifdef FUSED_SWITCH
+          switch (na) {
+            case 0: body(std::integral_constant<int, 0>{}); break;
+            case 1: body(std::integral_constant<int, 1>{}); break;
+            case 2: if constexpr (RTW >= 2) body(std::integral_constant<int, 2>{}); break;
+            case 3: if constexpr (RTW >= 3) body(std::integral_constant<int, 3>{}); break;
+            case 4: if constexpr (RTW >= 4) body(std::integral_constant<int, 4>{}); break;
+            default: if constexpr (RTW >= 5) body(std::integral_constant<int, (RTW >= 5 ? 5 : 1)>{}); break;
+          }
+#else
+          (void)na;
+          body(std::integral_constant<int, RTW>{});
+#endif
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);    // this wave's part of the next panel has landed
+          __syncthreads();
+        }
+
+        // ---- the row block's rows through LDS into the Gram tiles, GR rows at a time ----
+#pragma unroll
+        for (int ii = 0; ii < RTW; ++ii) {
+          if (r0 + ii * GR >= nd) break;              // uniform
+          __syncthreads();                            // the stage is free
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) {
+            const int cl = j * 8 + c8;
+            double d = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = w * 16 + acc_row<MODE>(lq, e);
+              // rows past N_d: the factor rows read there belong to padding or other planes
+              const float y = (r0 + ii * GR + row < nd) ? (float)acc[ii][j][e] : 0.f;
+              put_realf<MODE>(Ys + (part * NP) * YPL + cl * LDR + row, YPL, y);
+              d += (double)y * (double)y;
+            }
+            d += __shfl_xor(d, 16);
+            d += __shfl_xor(d, 32);
+            if (lq == 0) Dacc[(w * NCC + cl) * 2 + part] += d;
+          }
+          __syncthreads();
+          contract_chunk(Ys, ng, std::integral_constant<int, GR>{}, LDR);
+        }
+      }
+    }  // n'' chunks
+
+    // ---- the item's partials ----
+    if constexpr (!C::GSTREAM) {
+#pragma unroll
+      for (int s = 0; s < NPWR; ++s) {
+        const int tp = w + NW * s;
+        if (tp < npt) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] = gacc[s][i];
+        }
+      }
+    }
+    __syncthreads();
+    for (int n = tid; n < nb8; n += NT) {
+      double s = 0.0;
+      for (int c = n; c < NCC; c += nb8)
+        for (int ww = 0; ww < NW; ++ww) s += Dacc[(ww * NCC + c) * 2] + Dacc[(ww * NCC + c) * 2 + 1];
+      a.dpart[(long)wi.slot * a.dstride + n] = s;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace exc
