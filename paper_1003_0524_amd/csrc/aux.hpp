@@ -444,15 +444,23 @@ __global__ __launch_bounds__(256) void prep_factor_kernel(const double2* src, co
   }
 }
 
-// Padded copy of each multipole-free row's coefficient run: out[r][t] =
-// coef[rowinfo[r].x + t] for t < min(rowinfo[r].y, mt), zero beyond.
+// Padded copy of each multipole-free row's coefficient run, transposed per
+// chunk of 32 rows: out[((r / 32) * mt + t) * 32 + r % 32] = coef[rowinfo[r].x + t]
+// for t < min(rowinfo[r].y, mt), zero beyond (and for the padding rows of the
+// last chunk). Lanes that hold consecutive rows then read consecutive entries.
 __global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, const int4* rowinfo, int n_s, int mt,
                                                        double2* out) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)n_s * mt) return;
-  const int r = (int)(e / mt), t = (int)(e % mt);
-  const int4 ri = rowinfo[r];
-  out[e] = t < ri.y ? coef[ri.x + t] : make_double2(0.0, 0.0);
+  const int nchunk = (n_s + 31) / 32;
+  if (e >= (long)nchunk * 32 * mt) return;
+  const int rr = (int)(e % 32), t = (int)((e / 32) % mt), ck = (int)(e / (32L * mt));
+  const int r = ck * 32 + rr;
+  double2 v = make_double2(0.0, 0.0);
+  if (r < n_s) {
+    const int4 ri = rowinfo[r];
+    if (t < ri.y) v = coef[ri.x + t];
+  }
+  out[e] = v;
 }
 
 __global__ void zero_int_kernel(int32_t* p, int n) {

@@ -807,7 +807,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         ri[r] = make_int4((int)(c->ch_coef[ch] + (int64_t)i * b + i), b - i, c->n_s + ch, 0);
       }
       ITRY(upload(c, &c->d_rowinfo, ri));
-      ITRY(dalloc(c, &c->d_coefpad, (size_t)std::max(1, c->n_s) * kRunPad));
+      ITRY(dalloc(c, &c->d_coefpad, (size_t)std::max(1, (c->n_s + 31) / 32 * 32) * kRunPad));
     }
     ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));
     ITRY(upload(c, &c->d_ch_len, std::vector<int32_t>(c->ch_len.begin(), c->ch_len.end())));
@@ -879,7 +879,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     if (info[c->n_q]) { fail(c, EXC_ENOTPD, "a multipole-free channel block D_c is not positive definite"); return bail(EXC_ENOTPD); }
     if (c->n_s > 0) {
       // the fused kernel's padded runs of the (now factored) channel coefficients
-      const long ne = (long)c->n_s * kRunPad;
+      const long ne = (long)(c->n_s + 31) / 32 * 32 * kRunPad;
       hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, c->d_coef,
                          c->d_rowinfo, c->n_s, kRunPad, c->d_coefpad);
       IHIP(hipGetLastError());

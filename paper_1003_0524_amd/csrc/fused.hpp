@@ -92,7 +92,8 @@ struct FusedArgs {
   const int64_t* ch_coef;
   const double2* coef;            // L_c (column-major, per channel)
   const double2* cvec;            // l_c per multipole-free row
-  const double2* coefpad;         // [n_s][MAXT] the first MAXT entries of each row's run, zero padded
+  const double2* coefpad;         // per chunk of 32 multipole-free rows, [MAXT][32]: the first MAXT
+                                  // entries of each row's run (transposed), zero padded
   const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
                                   // {index in coef of conj-coefficient run L_c[i..b-1][i], b - i,
                                   //  multipole row n_s + c, 0}
@@ -291,8 +292,9 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         u4_t mp_next[CB / 8];
         // row data of the lane's row: l_c, run length, multipole row; the coefficient runs
         // of a row chunk go to LDS (rows of 16 complex), one chunk ahead
-        const double2* Cf = (const double2*)(smem + 2 * CB * 1024 + NPL * NCC * SPL * C::ESZ);   // [2][GS][MAXT]
-        const __amdgpu_buffer_rsrc_t crs = make_rsrc(a.coefpad, (uint32_t)(a.n_s * C::MAXT * 16));
+        const double2* Cf = (const double2*)(smem + 2 * CB * 1024 + NPL * NCC * SPL * C::ESZ);   // [2][MAXT][GS]
+        const __amdgpu_buffer_rsrc_t crs =
+            make_rsrc(a.coefpad, (uint32_t)((a.n_s + GS - 1) / GS * GS * C::MAXT * 16));
         struct RowData { double2 lc; int cs, len, mrow; };
         auto load_rows = [&](int sr, RowData& d) {
           const int rr = sr + rl;
@@ -303,14 +305,14 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             d.cs = ri.x; d.len = ri.y; d.mrow = ri.z;
             d.lc = a.cvec[rr];
           }
-          // GS rows x MAXT complex = 8 KB: 8 instructions of 4 rows each
+          // the chunk's MAXT x GS table (8 KB, contiguous in global memory): 8 instructions
           const int cbuf = (sr / GS) & 1;
 #pragma unroll
           for (int t = 0; t < (C::COEF_B / 1024 + NW - 1) / NW; ++t) {
             const int m = w + NW * t;
             if (m < C::COEF_B / 1024)
-              lds_load16(crs, (void*)(Cf + (cbuf * GS + m * 4) * C::MAXT),
-                         (uint32_t)(((sr + m * 4) * C::MAXT) * 16 + lane * 16), 0u);
+              lds_load16(crs, (void*)((const unsigned char*)Cf + cbuf * C::COEF_B + m * 1024),
+                         (uint32_t)(sr * C::MAXT * 16 + m * 1024 + lane * 16), 0u);
           }
         };
         RowData rd, rd_next;
@@ -383,9 +385,9 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
                 yr += l.x * xr + l.y * xi;
                 yi += l.x * xi - l.y * xr;
               };
-              const double2* cfl = Cf + (((st / ncb) & 1) * GS + rl) * C::MAXT;
+              const double2* cfl = Cf + ((st / ncb) & 1) * (GS * C::MAXT) + rl;
               const int tl = min(rd.len, C::MAXT);
-              for (int t = 0; t < tl; ++t) term(cfl[t], rl + t);
+              for (int t = 0; t < tl; ++t) term(cfl[t * GS], rl + t);
               for (int t = C::MAXT; t < rd.len; ++t) term(a.coef[rd.cs + t], rl + t);
               const double2 lc = rd.lc;
               double xmr, xmi;
@@ -480,76 +482,72 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         };
 
         __syncthreads();                              // the stage is free
+        // factor pieces of this wave's tiles, one K panel ahead in registers (L2 latency
+        // hides behind the current panel's MFMAs)
+        op_t ucur[RTW][KC / KS][2][NP], unext[RTW][KC / KS][2][NP];
+        auto load_u = [&](int kc, op_t (&u)[RTW][KC / KS][2][NP]) {
+#pragma unroll
+          for (int ii = 0; ii < RTW; ++ii) {
+            const long row0 = (long)(r0 + 16 * (w + 4 * ii)) * pi.ldu + kc;
+#pragma unroll
+            for (int ks = 0; ks < KC / KS; ++ks)
+#pragma unroll
+              for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                  u[ii][ks][h][p] = buf_load<op_t>(urs, u_lane,
+                                                   (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ));
+          }
+        };
         issue_raw(kc0);
+        load_u(kc0, ucur);
         __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
         __syncthreads();
         for (int kc = kc0; kc < kend; kc += KC) {
           convert(kc);
           __syncthreads();                            // pieces ready, raw panel free
-          // active row tiles: rows r0 + 16 rt <= kc + KC - 1 (upper triangular factor), rows < nd;
-          // this wave owns tiles w, w + 4, ...: its first na of them are active
-          const int nact = min(min(NRT, (kc + KC - 1 - r0) / 16 + 1), nrt_nd);
-          const int na = min(RTW, max(0, (nact - w + 3) / 4));
           const bool more = kc + KC < kend;
-          // straight-line panel body for a compile-time count of active tiles
-          auto body = [&](auto na_c) {
-            constexpr int NA = decltype(na_c)::value;
-            // factor pieces of the active tiles, straight from global memory (L2)
-            op_t ureg[NA > 0 ? NA : 1][KC / KS][2][NP];
+          if (more) {                                 // next panel and its factor pieces in flight
+            issue_raw(kc + KC);
+            load_u(kc + KC, unext);
+          }
 #pragma unroll
-            for (int ii = 0; ii < NA; ++ii) {
-              const long row0 = (long)(r0 + 16 * (w + 4 * ii)) * pi.ldu + kc;
+          for (int ks = 0; ks < KC / KS; ++ks) {
+            const int kofs = ks * KS + KPL * lq;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int bpart = part ^ h;
+              const bool neg = (h == 1) && (part == 0);
+#pragma unroll
+              for (int j = 0; j < NCT; ++j) {
+                op_t bop[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                  bop[p] = lds_operand<MODE>(Apl + (bpart * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
+                  if (neg) bop[p] = negate(bop[p]);
+                }
+                // products outer, tiles inner: consecutive MFMAs use different accumulators
+#pragma unroll
+                for (int pr = 0; pr < C::T::NPROD; ++pr)
+#pragma unroll
+                  for (int ii = 0; ii < RTW; ++ii)
+                    acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
+                                      bop[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
+              }
+            }
+          }
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);    // this wave's part of the next panel has landed
+          __syncthreads();
+          if (more) {
+#pragma unroll
+            for (int ii = 0; ii < RTW; ++ii)
 #pragma unroll
               for (int ks = 0; ks < KC / KS; ++ks)
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                  for (int p = 0; p < NP; ++p)
-                    ureg[ii][ks][h][p] = buf_load<op_t>(
-                        urs, u_lane, (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ));
-            }
-            if (more) issue_raw(kc + KC);              // in flight while this panel runs on MFMA
-#pragma unroll
-            for (int ks = 0; ks < KC / KS; ++ks) {
-              const int kofs = ks * KS + KPL * lq;
-#pragma unroll
-              for (int h = 0; h < 2; ++h) {
-                const int bpart = part ^ h;
-                const bool neg = (h == 1) && (part == 0);
-#pragma unroll
-                for (int j = 0; j < NCT; ++j) {
-                  op_t bop[NP];
-#pragma unroll
-                  for (int p = 0; p < NP; ++p) {
-                    bop[p] = lds_operand<MODE>(Apl + (bpart * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
-                    if (neg) bop[p] = negate(bop[p]);
-                  }
-                  // products outer, tiles inner: consecutive MFMAs use different accumulators
-#pragma unroll
-                  for (int pr = 0; pr < C::T::NPROD; ++pr)
-#pragma unroll
-                    for (int ii = 0; ii < NA; ++ii)
-                      acc[ii][j] = mfma(ureg[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
-                                        bop[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
-                }
-              }
-            }
-          };
-#ifdef FUSED_SWITCH
-          switch (na) {
-            case 0: body(std::integral_constant<int, 0>{}); break;
-            case 1: body(std::integral_constant<int, 1>{}); break;
-            case 2: if constexpr (RTW >= 2) body(std::integral_constant<int, 2>{}); break;
-            case 3: if constexpr (RTW >= 3) body(std::integral_constant<int, 3>{}); break;
-            case 4: if constexpr (RTW >= 4) body(std::integral_constant<int, 4>{}); break;
-            default: if constexpr (RTW >= 5) body(std::integral_constant<int, (RTW >= 5 ? 5 : 1)>{}); break;
+                  for (int p = 0; p < NP; ++p) ucur[ii][ks][h][p] = unext[ii][ks][h][p];
           }
-#else
-          (void)na;
-          body(std::integral_constant<int, RTW>{});
-#endif
-          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);    // this wave's part of the next panel has landed
-          __syncthreads();
         }
 
         // ---- the row block's rows through LDS into the Gram tiles, GR rows at a time ----
