@@ -165,12 +165,26 @@ void exchange_destroy(exc_ctx *ctx);
  *   what = 1: nominal flops of the method per exchange_matrix_all (sparse-aware,
  *             complex multiply-add = 8 flops, Hermitian upper triangle only)
  *   what = 2: flops the chosen form executes per exchange_matrix_all (padding included)
- *   what = 3: tile configuration id chosen by the autotuner (-1 if not tuned)
+ *   what = 3: id of the main kernel's configuration (a fused instance, or the
+ *             tile kernel of the block-sparse + tile path)
+ *   what = 8: how it was chosen: 0 default, 1 timed by the autotuner on the first
+ *             batched exchange_matrix_all, 2 read from the EXC_TUNE_CACHE file
  *   what = 4: algorithmic HBM bytes of one exchange_matrix_all
  *             (M read once, v(q) read once, Vx written once)
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
+
+/*
+ * Autotuning (reduced-precision Cholesky/HERK contexts, batched path): the first
+ * exchange_matrix_all times every main-kernel configuration that can serve the
+ * context (fused instances with enough band tiles; the block-sparse + tile
+ * kernels) on the caller's own inputs, one untimed and three timed runs each,
+ * and keeps the fastest. Environment: EXC_TUNE=0 keeps the default choice;
+ * EXC_TUNE_CACHE=<file> looks the choice up / appends it under a key of the
+ * problem's sizes; EXC_FUSED_CFG=<id> fixes a fused instance and EXC_FUSED=0 the
+ * block-sparse + tile path (neither is then tuned).
+ */
 
 /*
  * exchange_timing -- live kernel timing of the batched exchange_matrix_all

@@ -149,6 +149,10 @@ struct exc_ctx {
   const KernelCfg* cfg = nullptr;
   const FusedKCfg* fcfg = nullptr;    // non-null: reduced-precision HERK through the fused kernel
   bool fused = false;
+  bool fused_ok = false;              // the fused kernel can serve this context
+  int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
+  bool tune_done = false;
+  size_t ws_bytes = 0;                // block-sparse workspace the unfused path needs
   void* d_ws = nullptr;
   double* d_dsp = nullptr;
   void* d_gpart = nullptr;
@@ -672,6 +676,140 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   return EXC_OK;
 }
 
+// Switch the context to a main-kernel configuration: a fused instance, or
+// (f == nullptr) the block-sparse + tile kernels. Rebuilds the plans, sizes
+// the partial slots and the persistent grid, allocates or releases the
+// block-sparse workspace, and drops the captured graph.
+exc_status configure(exc_ctx* c, const FusedKCfg* f, hipStream_t st) {
+  const bool mixed_herk = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
+  c->fcfg = f;
+  c->fused = f != nullptr;
+  if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+  HIPCHK(c, hipStreamSynchronize(st));
+  if (c->own) HIPCHK(c, hipStreamSynchronize(c->own));
+  const bool need_ws = !c->fused;
+  if (need_ws && !c->d_ws) TRY(dalloc(c, (char**)&c->d_ws, c->ws_bytes));
+  if (!need_ws && c->d_ws) { hipFree(c->d_ws); c->d_ws = nullptr; }
+  if (need_ws && mixed_herk && !c->d_dsp) {
+    const size_t n = c->pairs.size() * (size_t)c->n_occ * c->nb_max;
+    TRY(dalloc(c, &c->d_dsp, n));
+    HIPCHK(c, hipMemset(c->d_dsp, 0, n * sizeof(double)));
+  }
+  if (!need_ws && c->d_dsp) { hipFree(c->d_dsp); c->d_dsp = nullptr; }
+  free_plan(c->plain);
+  free_plan(c->bat);
+  TRY(build_plan(c, c->plain, 1));
+  TRY(build_plan(c, c->bat, 0));
+  const size_t nslot = std::max(c->plain.n_slots, c->bat.n_slots);
+  const size_t asz = c->precision == EXC_FP64 ? 8 : 4;
+  hipFree(c->d_gpart);
+  hipFree(c->d_dpart);
+  c->d_gpart = nullptr;
+  c->d_dpart = nullptr;
+  TRY(dalloc(c, (char**)&c->d_gpart, nslot * c->gstride * asz));
+  TRY(dalloc(c, &c->d_dpart, nslot * (size_t)c->dstride));
+  HIPCHK(c, hipMemset(c->d_gpart, 0, nslot * c->gstride * asz));
+  HIPCHK(c, hipMemset(c->d_dpart, 0, nslot * (size_t)c->dstride * 8));
+  const void* main_fn = c->fused ? (const void*)c->fcfg->fn : (const void*)c->cfg->fn;
+  const int main_threads = c->fused ? 256 : 64 * c->cfg->NW();
+  hipFuncAttributes fa{};
+  HIPCHK(c, hipFuncGetAttributes(&fa, main_fn));
+  if (fa.maxThreadsPerBlock < main_threads)
+    return fail(c, EXC_EUNSUPPORTED, "kernel %d allows %d threads per block, needs %d",
+                c->fused ? c->fcfg->id : c->cfg->id, fa.maxThreadsPerBlock, main_threads);
+  int n_cu = 0, occ = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, main_fn, main_threads, 0));
+  c->persist_grid = std::max(1, n_cu * std::max(1, occ));
+  return EXC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the batched path: on the first batched call of a reduced-
+// precision HERK context, every main-kernel configuration that can serve it
+// (the fused instances with enough band tiles, and the block-sparse + tile
+// kernels) runs the caller's own inputs once untimed and three times timed on
+// the context's stream; the fastest is kept. With EXC_TUNE_CACHE=<file> the
+// choice is looked up / recorded under a key of the problem's size bucket.
+// EXC_TUNE=0 keeps the default configuration.
+// ---------------------------------------------------------------------------
+std::string tune_key(const exc_ctx* c, int dtype) {
+  long nmb = 0, nbs = 0;
+  for (int q = 0; q < c->n_q; ++q) nmb += c->nmb[q];
+  for (int k = 0; k < c->n_k; ++k) nbs += c->nb[k];
+  char buf[256];
+  snprintf(buf, sizeof buf, "v1 prec=%d form=%d dtype=%d nk=%d nq=%d nocc=%d nbt=%d nmb_avg=%ld nb_avg=%ld ns=%d",
+           c->precision, c->form, dtype, c->n_k, c->n_q, c->n_occ, c->nbt_max, nmb / std::max(1, c->n_q),
+           nbs / std::max(1, c->n_k), c->n_s);
+  return buf;
+}
+
+int cfg_id(const exc_ctx* c) { return c->fused ? c->fcfg->id : c->cfg->id; }
+
+exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
+  c->tuned = 0;
+  std::vector<const FusedKCfg*> cands;
+  if (c->fused_ok)
+    for (const auto& k : kFused)
+      if (k.mode == c->precision && k.NB8M >= c->nbt_max && k.NCT >= c->nbt_max) cands.push_back(&k);
+  cands.push_back(nullptr);                      // block-sparse + tile kernels
+  const std::string key = tune_key(c, dtype);
+  const char* cache = getenv("EXC_TUNE_CACHE");
+  if (cache) {
+    if (FILE* fp = fopen(cache, "r")) {
+      char line[512];
+      int found = -1;
+      while (fgets(line, sizeof line, fp)) {
+        char* tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        if (key == line) found = atoi(tab + 1);
+      }
+      fclose(fp);
+      for (const FusedKCfg* f : cands) {
+        const int id = f ? f->id : c->cfg->id;
+        if (id == found) {
+          TRY(configure(c, f, st));
+          c->tuned = 2;
+          return EXC_OK;
+        }
+      }
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  const FusedKCfg* best = c->fcfg;
+  float best_ms = 1e30f;
+  bool any = false;
+  for (const FusedKCfg* f : cands) {
+    exc_status s2 = configure(c, f, st);
+    if (s2 == EXC_ENOMEM) { c->err.clear(); continue; }   // e.g. no room for the block-sparse workspace
+    if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
+    if ((s2 = build_batched_graph(c, dtype)) != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
+    HIPCHK(c, hipEventRecord(e0, c->own));
+    for (int r = 0; r < 3; ++r) HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
+    HIPCHK(c, hipEventRecord(e1, c->own));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = f; any = true; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!any) return fail(c, EXC_ENOMEM, "no main-kernel configuration fits in device memory");
+  TRY(configure(c, best, st));
+  c->tuned = 1;
+  if (cache) {
+    if (FILE* fp = fopen(cache, "a")) {
+      fprintf(fp, "%s\t%d\n", key.c_str(), cfg_id(c));
+      fclose(fp);
+    }
+  }
+  return EXC_OK;
+}
+
 exc_status check_ctx(const exc_ctx* c) {
   if (!c) return EXC_EINVAL;
   if (c->magic != kAlive) return EXC_ESTATE;
@@ -769,7 +907,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     // rows: channels of up to 33 rows
     int maxb = 0;
     for (int ch = 0; ch < c->n_ch; ++ch) maxb = std::max(maxb, c->nrad[ch] - 1);
-    c->fused = c->fcfg && maxb <= 33 && !(ev && ev[0] == '0');
+    c->fused_ok = c->fcfg && maxb <= 33;
+    c->fused = c->fused_ok && !(ev && ev[0] == '0');
+    if (!c->fused) c->fcfg = nullptr;
   }
   const int BM = c->cfg->BM;
 
@@ -897,7 +1037,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   // multipole corrections). Reduced precision: each column packed into split
   // planes [plane][row], rows = sparse rows padded to 8 then dense rows padded
   // to 32 (elements of the mode's storage type).
-  const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64 && !c->fused;
+  const bool split_ws = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
   c->ns_pad = (c->n_s + 7) / 8 * 8;
   const int ws_cols = split_ws ? 2 * npieces(c->precision) : 1;   // planes per column
   int64_t ws_total = 0, m_max = 0;
@@ -913,7 +1053,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
                                : (c->form == EXC_FORM_CHOL_HERK ? c->n_s : c->n_s + c->n_ch);
       p.m_off = moff; p.ws_off = ws_total; p.u_off = c->u_off[q]; p.ldu = c->ldu[q]; p.ldw = std::max(1, ldw);
       moff += (int64_t)c->n_occ * p.nb * p.nmb;
-      if (!c->fused) ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
+      ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
       c->pairs.push_back(p);
       c->pair_w.push_back(c->wq[q]);
       // accounting (nominal: sparse-aware method, Hermitian upper triangle)
@@ -946,23 +1086,10 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(upload(c, &c->d_pair_w, c->pair_w));
   ITRY(upload(c, &c->d_pair_begin, std::vector<int32_t>(c->k_pair.begin(), c->k_pair.end())));
   const size_t wsz = split_ws ? lds_elem_size(c->precision) : 16;
-  ITRY(dalloc(c, (char**)&c->d_ws, (size_t)std::max<int64_t>(1, ws_total) * wsz));
-  if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64 && !c->fused) {
-    ITRY(dalloc(c, &c->d_dsp, c->pairs.size() * (size_t)c->n_occ * c->nb_max));
-    IHIP(hipMemset(c->d_dsp, 0, c->pairs.size() * (size_t)c->n_occ * c->nb_max * sizeof(double)));
-  }
-
-  ITRY(build_plan(c, c->plain, 1));
-  ITRY(build_plan(c, c->bat, 0));
+  c->ws_bytes = (size_t)std::max<int64_t>(1, ws_total) * wsz;
   const int nbt = c->nbt_max;
   c->gstride = nbt * (nbt + 1) / 2 * 256;
   c->dstride = nbt * 8;
-  const size_t nslot = std::max(c->plain.n_slots, c->bat.n_slots);
-  const size_t asz = c->precision == EXC_FP64 ? 8 : 4;
-  ITRY(dalloc(c, (char**)&c->d_gpart, nslot * c->gstride * asz));
-  ITRY(dalloc(c, &c->d_dpart, nslot * (size_t)c->dstride));
-  IHIP(hipMemsetAsync(c->d_gpart, 0, nslot * c->gstride * asz, st));
-  IHIP(hipMemsetAsync(c->d_dpart, 0, nslot * (size_t)c->dstride * 8, st));
 
   int64_t vtot = 0;
   for (int k = 0; k < c->n_k; ++k) { c->v_off.push_back(vtot); vtot += (int64_t)c->nb[k] * c->nb[k]; }
@@ -979,23 +1106,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(dalloc(c, &c->d_counter, (size_t)NQ_MAX));
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
 
-  const void* main_fn = c->fused ? (const void*)c->fcfg->fn : (const void*)c->cfg->fn;
-  const int main_threads = c->fused ? 256 : 64 * c->cfg->NW();
-  {
-    hipFuncAttributes fa{};
-    IHIP(hipFuncGetAttributes(&fa, main_fn));
-    if (fa.maxThreadsPerBlock < main_threads) {
-      fail(c, EXC_EUNSUPPORTED, "kernel %d allows %d threads per block, needs %d",
-           c->fused ? c->fcfg->id : c->cfg->id, fa.maxThreadsPerBlock, main_threads);
-      return bail(EXC_EUNSUPPORTED);
-    }
-  }
-  int n_cu = 0, occ = 0;
-  IHIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-  IHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, main_fn, main_threads, 0));
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
-  c->persist_grid = std::max(1, n_cu * std::max(1, occ));
+  ITRY(configure(c, c->fused ? c->fcfg : nullptr, st));
   IHIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   IHIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   IHIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -1065,6 +1178,20 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
     for (int k = 0; k < c->n_k; ++k) run_k_plain(c, k, dtype, st);
     HIPCHK(c, hipGetLastError());
   } else {
+    if (!c->tune_done) {
+      const char* ev = getenv("EXC_TUNE");
+      const char* fixed = getenv("EXC_FUSED_CFG");      // an explicit configuration is not tuned
+      const char* off = getenv("EXC_FUSED");
+      const bool mixed_herk = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64 && !fixed &&
+                              !(off && off[0] == '0');
+      TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
+      if (mixed_herk && !(ev && ev[0] == '0')) {
+        HIPCHK(c, hipEventRecord(c->ev_in, st));          // the inputs are ready on the caller's stream
+        HIPCHK(c, hipStreamWaitEvent(c->own, c->ev_in, 0));
+        TRY(autotune(c, dtype, st));
+      }
+      c->tune_done = true;
+    }
     bool same = c->gexec && c->g_dtype == dtype;
     for (int k = 0; k < c->n_k && same; ++k)
       if (c->h_mtab[k] != M_k[k] || c->h_vtab[k] != Vx_k[k]) same = false;
@@ -1160,6 +1287,7 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
       return EXC_OK;
     }
     case 6: *value = c->t_count; return EXC_OK;
+    case 8: *value = c->tuned; return EXC_OK;
     default: return EXC_EINVAL;
   }
 }

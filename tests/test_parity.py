@@ -186,3 +186,60 @@ def test_energy_before_matrix_is_state_error():
         ex.energy()
     assert ei.value.status == -5
     ex.close()
+
+
+# ------------------------------------------------------------------ tuning ---
+def _fused_ids(precision, nbt):
+    """Fused instances that can serve nbt band tiles (from the library's table order)."""
+    table = {"fp32": [(150, 3), (151, 3), (120, 3), (124, 3), (121, 8), (123, 13), (122, 16)],
+             "bf16x3": [(160, 3), (161, 3), (162, 8), (130, 3), (134, 3), (131, 8), (133, 13), (132, 16)],
+             "bf16x6": [(170, 3), (171, 3), (140, 3), (144, 3), (141, 8), (143, 13), (142, 16)]}
+    return [i for i, cap in table[precision] if cap >= nbt]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_every_tuner_candidate_matches_oracle(name, precision, monkeypatch):
+    """Each configuration the autotuner may pick is correct on its own."""
+    cfg = synth.make_config(name)
+    nbt = max((nb + 7) // 8 for nb in cfg.n_bands)
+    refs = [_oracle(name, k) for k in range(cfg.n_k)]
+    choices = [("cfg", i) for i in _fused_ids(precision, nbt)] + [("unfused", None)]
+    for kind, cid in choices:
+        monkeypatch.delenv("EXC_FUSED_CFG", raising=False)
+        monkeypatch.delenv("EXC_FUSED", raising=False)
+        if kind == "cfg":
+            monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
+        else:
+            monkeypatch.setenv("EXC_FUSED", "0")
+        print(f"[parity] {name} {precision} {kind} {cid}", flush=True)
+        cfg_, Vs = _run_all(name, precision, "herk", True)
+        for k in range(cfg.n_k):
+            pred = pr.normwise_error(_emulated(name, k, precision), refs[k])
+            err = pr.normwise_error(Vs[k], refs[k])
+            assert err <= 4.0 * pred + 1e-12, (name, precision, kind, cid, k, err, pred)
+
+
+def test_autotuner_choice_and_cache(tmp_path, monkeypatch):
+    import paper_1003_0524_amd as lib
+    monkeypatch.delenv("EXC_FUSED_CFG", raising=False)
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_TUNE", raising=False)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("EXC_TUNE_CACHE", str(cache))
+    cfg = synth.make_config("small")
+    E, D, C = synth.coulomb_blocks(cfg)
+    Ms = [_m(cfg, k) for k in range(cfg.n_k)]
+    ids = []
+    for expect in (1, 2):
+        ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                          precision="bf16x3", form="herk", batched=True)
+        assert ex.query(8) == 0
+        ex.matrix_all(Ms)
+        torch.cuda.synchronize()
+        assert ex.query(8) == expect
+        ids.append(int(ex.query(3)))
+        ex.close()
+    assert ids[0] == ids[1]
+    assert ids[0] in _fused_ids("bf16x3", 1) + [31, 30]
+    assert cache.read_text().count("\t") == 1
