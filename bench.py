@@ -43,14 +43,14 @@ WORKLOADS = {
 
 def _kernel_src_hash() -> str:
     h = hashlib.sha256()
-    for f in ("tile.hpp", "common.hpp", "aux.hpp", "exchange.hip"):
+    for f in ("tile.hpp", "fused.hpp", "common.hpp", "aux.hpp", "exchange.hip"):
         with open(os.path.join(ROOT, "paper_1003_0524_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(workload: str, mode: str):
-    """HBM bytes per launch of the tile kernel from committed rocprofv3 counters,
+def _traffic(workload: str, mode: str, kernel_cfg: int = -1):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counters,
     or None when they were taken on a different kernel source."""
     p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
@@ -59,6 +59,8 @@ def _traffic(workload: str, mode: str):
     e = d.get(mode)
     if not e or e.get("src_hash") != _kernel_src_hash():
         return None
+    if e.get("cfg_id") is not None and e.get("cfg_id") != kernel_cfg:
+        return None                      # counters of another configuration
     return e.get("bytes_per_launch")
 
 
@@ -152,9 +154,11 @@ def main() -> int:
         V = [o.view(nb, nb).T.cpu().numpy() for o, nb in zip(outs, cfg.n_bands)]
         results[mode] = dict(ms=ms, init_ms=init_ms, energy=energy, kt=kt, V=V,
                              flops_nom=ex.query(1), flops_exec=ex.query(2), bytes_alg=ex.query(4),
-                             items=int(ex.query(0)))
+                             items=int(ex.query(0)), cfg=int(ex.query(3)), tuned=int(ex.query(8)),
+                             ws_bytes=ex.query(9), fused=bool(ex.query(10)))
         log(f"[bench] {mode}: {ms:.4f} ms/step, E_x = {energy:.8f}"
-            + (f", tile kernel {kt[0]:.4f} ms, sparse kernel {kt[1]:.4f} ms" if kt else ""))
+            + (f", main kernel {kt[0]:.4f} ms, sparse kernel {kt[1]:.4f} ms" if kt else "")
+            + f", config {results[mode]['cfg']}{' (autotuned)' if results[mode]['tuned'] else ''}")
         ex.close()
 
     # errors against the float64 oracle (all k)
@@ -174,17 +178,38 @@ def main() -> int:
     H = results[head]
     value = H["flops_nom"] / (H["ms"] * 1e-3) / 1e9
 
-    # roofline of the dominant (tile) kernel, timed live with graph event nodes
+    # roofline of the dominant kernel, timed live with graph event nodes. Its bound
+    # follows from its arithmetic intensity (algorithmic flops / algorithmic HBM
+    # bytes) against the ridge point peak_flops / peak_bandwidth of its dtype.
     roof = None
     if H["kt"] and H["kt"][0] > 0:
-        t_tile = H["kt"][0] * 1e-3
-        ach = H["flops_exec"] / t_tile / 1e12
-        peak = PEAK_TFLOPS[head]
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 5), "traffic": _traffic(args.workload, head),
-                "kernel": "tile_kernel (dense rows Y = L^H A on MFMA + band contraction)",
-                "kernel_ms": round(H["kt"][0], 5), "launches_timed": H["kt"][2],
-                "algorithmic_flops_per_launch": H["flops_exec"]}
+        t_main, t_sparse = H["kt"][0], H["kt"][1]
+        m_bytes = sum(cfg.n_occ * cfg.n_bands[k] * cfg.n_mb(q) for k in range(cfg.n_k) for q in range(cfg.n_q)) * 16.0
+        if H["fused"]:
+            name, t_k = "fused_kernel (block-sparse rows, dense rows on MFMA, band contraction; M read once)", t_main
+            flops, byts = H["flops_exec"], H["bytes_alg"]
+        elif t_main >= t_sparse:
+            name, t_k = "tile_kernel (dense rows Y = L^H A on MFMA + band contraction)", t_main
+            flops, byts = H["flops_exec"], H["ws_bytes"] + (H["bytes_alg"] - m_bytes)
+        else:
+            name, t_k = "sparse_kernel (block-sparse rows, packs the tile kernel's operands)", t_sparse
+            flops, byts = 0.0, m_bytes + H["ws_bytes"]
+        peak_f = PEAK_TFLOPS[head]
+        ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+        intensity = flops / byts if byts > 0 else float("inf")
+        if intensity < ridge:
+            ach = byts / (t_k * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 5)}
+        else:
+            ach = flops / (t_k * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak_f, "unit": "TFLOP/s",
+                    "frac": round(ach / peak_f, 5)}
+        roof.update({"traffic": _traffic(args.workload, head, H["cfg"]), "kernel": name, "kernel_ms": round(t_k, 5),
+                     "launches_timed": H["kt"][2], "algorithmic_bytes_per_launch": byts,
+                     "algorithmic_flops_per_launch": flops,
+                     "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 1),
+                     "mfma_frac": round(flops / (t_k * 1e-3) / 1e12 / peak_f, 5)})
 
     # CPU baseline: the oracle as it stands on the host cores, bounded sample
     cpu = None
@@ -209,7 +234,7 @@ def main() -> int:
                "ms_per_step": round(t_cpu / reps * 1e3, 2)}
 
     sparse = None
-    if H["kt"] and H["kt"][1] > 0:
+    if H["kt"] and H["kt"][1] > 0 and not H["fused"]:
         # block-sparse rows: read the MT rows of M (+ multipole rows), write Y_s
         n_s, n_ch = cfg.n_s, cfg.n_ch
         elems = sum(cfg.n_occ * cfg.n_bands[k] for k in range(cfg.n_k)) * cfg.n_q
@@ -227,7 +252,8 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[head], "data": "synthetic (seeded SplitMix64/Box-Muller M, synthetic PD Coulomb blocks)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "mode": head,
-                   "form": "cholesky-herk, one persistent launch in a HIP graph"},
+                   "form": "cholesky-herk, one persistent launch in a HIP graph",
+                   "kernel_config": H["cfg"], "autotuned": H["tuned"]},
         "kpoints_per_s": round(cfg.n_k / (H["ms"] * 1e-3), 1),
         "pairs_per_s": round(cfg.n_k * cfg.n_q / (H["ms"] * 1e-3), 1),
         "gflops_executed": round(H["flops_exec"] / (H["ms"] * 1e-3) / 1e9, 3),
@@ -237,7 +263,8 @@ def main() -> int:
         "modes": {m: {"ms_per_step": round(r["ms"], 5),
                       "gflops": round(r["flops_nom"] / (r["ms"] * 1e-3) / 1e9, 3),
                       "err_eig_ha": r["err_eig_ha"], "err_normwise": r["err_norm"],
-                      "tile_kernel_ms": (round(r["kt"][0], 5) if r["kt"] else None)}
+                      "main_kernel_ms": (round(r["kt"][0], 5) if r["kt"] else None),
+                      "config": r["cfg"], "fused": r["fused"], "tuned": r["tuned"]}
                   for m, r in results.items()},
         "speedup_vs_plain_fp64": (round(P["ms"] / H["ms"], 2) if P else None),
     }

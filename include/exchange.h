@@ -169,6 +169,9 @@ void exchange_destroy(exc_ctx *ctx);
  *             tile kernel of the block-sparse + tile path)
  *   what = 8: how it was chosen: 0 default, 1 timed by the autotuner on the first
  *             batched exchange_matrix_all, 2 read from the EXC_TUNE_CACHE file
+ *   what = 9: bytes of the block-sparse workspace of the block-sparse + tile path
+ *             (written once and read once per exchange_matrix_all on that path)
+ *   what = 10: 1 if the fused kernel serves the batched path, else 0
  *   what = 4: algorithmic HBM bytes of one exchange_matrix_all
  *             (M read once, v(q) read once, Vx written once)
  *   what = 5, 6, 7: see exchange_timing
@@ -179,8 +182,8 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
  * Autotuning (reduced-precision Cholesky/HERK contexts, batched path): the first
  * exchange_matrix_all times every main-kernel configuration that can serve the
  * context (fused instances with enough band tiles; the block-sparse + tile
- * kernels) on the caller's own inputs, one untimed and three timed runs each,
- * and keeps the fastest. Environment: EXC_TUNE=0 keeps the default choice;
+ * kernels) on the caller's own inputs, one untimed and five timed runs each,
+ * and keeps the fastest (later candidates must win by more than 3 %). Environment: EXC_TUNE=0 keeps the default choice;
  * EXC_TUNE_CACHE=<file> looks the choice up / appends it under a key of the
  * problem's sizes; EXC_FUSED_CFG=<id> fixes a fused instance and EXC_FUSED=0 the
  * block-sparse + tile path (neither is then tuned).
