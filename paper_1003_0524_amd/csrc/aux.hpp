@@ -448,16 +448,17 @@ __global__ __launch_bounds__(256) void prep_factor_kernel(const double2* src, co
 // chunk of 32 rows: out[((r / 32) * mt + t) * 32 + r % 32] = coef[rowinfo[r].x + t]
 // for t < min(rowinfo[r].y, mt), zero beyond (and for the padding rows of the
 // last chunk). Lanes that hold consecutive rows then read consecutive entries.
-__global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, const int4* rowinfo, int n_s, int mt,
+__global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, const int4* rowinfo,
+                                                       const int4* chunks, int nchunk, int mt, int gr,
                                                        double2* out) {
+  // out[chunk][t][rr] = L_c[i+t][i] of the chunk's row rr (entry i of channel c), zero past the run
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  const int nchunk = (n_s + 31) / 32;
-  if (e >= (long)nchunk * 32 * mt) return;
-  const int rr = (int)(e % 32), t = (int)((e / 32) % mt), ck = (int)(e / (32L * mt));
-  const int r = ck * 32 + rr;
+  if (e >= (long)nchunk * mt * gr) return;
+  const int rr = (int)(e % gr), t = (int)((e / gr) % mt), ck = (int)(e / ((long)gr * mt));
+  const int4 ci = chunks[ck];
   double2 v = make_double2(0.0, 0.0);
-  if (r < n_s) {
-    const int4 ri = rowinfo[r];
+  if (rr < ci.y) {
+    const int4 ri = rowinfo[ci.x + rr];
     if (t < ri.y) v = coef[ri.x + t];
   }
   out[e] = v;

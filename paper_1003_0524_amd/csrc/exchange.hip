@@ -62,6 +62,8 @@ const KernelCfg kCfgs[] = {
 // count per n'' value, KC complex k per K-loop panel.
 // coefficients per multipole-free row staged by the fused kernel (its MAXT)
 constexpr int kRunPad = FusedCfg<M_BF16X3, 1, 1, 1, 32>::MAXT;
+// rows per chunk of multipole-free rows (one per lane)
+constexpr int kChunkRows = FusedCfg<M_BF16X3, 1, 1, 1, 32>::GR;
 
 struct FusedKCfg {
   int mode, RTW, NCT, NB8M, KC, CB, OCC;
@@ -71,8 +73,8 @@ struct FusedKCfg {
 };
 
 #define FCFG(MODE, RTW, NCT, NB8M, KC, ID)                                                       \
-  FusedKCfg{MODE, RTW, NCT, NB8M, KC, 32, 1, fused_kernel<MODE, RTW, NCT, NB8M, KC>,               \
-            FusedCfg<MODE, RTW, NCT, NB8M, KC>::LDS_B, ID}
+  FusedKCfg{MODE, RTW, NCT, NB8M, KC, 16, 1, fused_kernel<MODE, RTW, NCT, NB8M, KC, 16, 1>,        \
+            FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::LDS_B, ID}
 // two workgroups per CU: at most 256 registers per lane and half the LDS each
 #define FCFG2(MODE, RTW, NCT, NB8M, ID)                                                          \
   FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2>,       \
@@ -137,6 +139,8 @@ struct exc_ctx {
   int32_t *d_row_chan = nullptr, *d_ch_off = nullptr, *d_ch_len = nullptr;
   int4* d_rowinfo = nullptr;          // fused kernel: per multipole-free row (see FusedArgs)
   double2* d_coefpad = nullptr;       // fused kernel: padded coefficient runs (see FusedArgs)
+  int4* d_schunk = nullptr;           // fused kernel: chunks of whole channels (see FusedArgs)
+  int n_schunk = 0;
   int64_t* d_ch_coef = nullptr;
   // pairs, plans, buffers
   std::vector<PairInfo> pairs;
@@ -266,7 +270,7 @@ void release(exc_ctx* c) {
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
-                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_pairs, c->d_pair_w, c->d_pair_begin,
+                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout};
   for (void* p : ptrs) if (p) hipFree(p);
@@ -462,6 +466,7 @@ FusedArgs fused_args(exc_ctx* c, int dtype) {
   f.U = c->d_U;
   f.row_chan = c->d_row_chan; f.ch_off = c->d_ch_off; f.ch_len = c->d_ch_len; f.ch_coef = c->d_ch_coef;
   f.coef = c->d_coef; f.cvec = c->d_cvec; f.rowinfo = c->d_rowinfo; f.coefpad = c->d_coefpad;
+  f.schunk = c->d_schunk; f.n_schunk = c->n_schunk;
   f.gpart = c->d_gpart; f.dpart = c->d_dpart;
   f.gstride = c->gstride; f.dstride = c->dstride;
   return f;
@@ -906,11 +911,11 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
     const char* ev = getenv("EXC_FUSED");
     c->fcfg = pick_fused(c->precision, c->nbt_max);
-    // the fused kernel stages 64 rows per column for a chunk of 32 multipole-free
-    // rows: channels of up to 33 rows
+    // the fused kernel takes the multipole-free rows in chunks of whole channels of at
+    // most 64 rows
     int maxb = 0;
     for (int ch = 0; ch < c->n_ch; ++ch) maxb = std::max(maxb, c->nrad[ch] - 1);
-    c->fused_ok = c->fcfg && maxb <= 33;
+    c->fused_ok = c->fcfg && maxb <= kChunkRows;
     c->fused = c->fused_ok && !(ev && ev[0] == '0');
     if (!c->fused) c->fcfg = nullptr;
   }
@@ -950,7 +955,29 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         ri[r] = make_int4((int)(c->ch_coef[ch] + (int64_t)i * b + i), b - i, c->n_s + ch, 0);
       }
       ITRY(upload(c, &c->d_rowinfo, ri));
-      ITRY(dalloc(c, &c->d_coefpad, (size_t)std::max(1, (c->n_s + 31) / 32 * 32) * kRunPad));
+      // chunks of whole channels of at most kChunkRows rows (the fused kernel's lane = row);
+      // needs every channel to fit one chunk
+      std::vector<int4> ck;
+      bool fits = true;
+      for (int ch = 0; ch < c->n_ch; ++ch) fits = fits && c->ch_len[ch] <= kChunkRows;
+      if (fits) {
+        int r = 0;
+        while (r < c->n_s) {
+          const int r0 = r;
+          int longest = 0;
+          while (r < c->n_s) {
+            const int b = c->ch_len[row_chan[r]];        // r is the first row of its channel
+            if (r - r0 + b > kChunkRows) break;
+            longest = std::max(longest, b);
+            r += b;
+          }
+          ck.push_back(make_int4(r0, r - r0, longest, 0));
+        }
+      }
+      c->n_schunk = (int)ck.size();
+      if (ck.empty()) ck.push_back(make_int4(0, 0, 0, 0));
+      ITRY(upload(c, &c->d_schunk, ck));
+      ITRY(dalloc(c, &c->d_coefpad, (size_t)ck.size() * kChunkRows * kRunPad));
     }
     ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));
     ITRY(upload(c, &c->d_ch_len, std::vector<int32_t>(c->ch_len.begin(), c->ch_len.end())));
@@ -1022,9 +1049,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     if (info[c->n_q]) { fail(c, EXC_ENOTPD, "a multipole-free channel block D_c is not positive definite"); return bail(EXC_ENOTPD); }
     if (c->n_s > 0) {
       // the fused kernel's padded runs of the (now factored) channel coefficients
-      const long ne = (long)(c->n_s + 31) / 32 * 32 * kRunPad;
+      const long ne = (long)std::max(1, c->n_schunk) * kChunkRows * kRunPad;
       hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, c->d_coef,
-                         c->d_rowinfo, c->n_s, kRunPad, c->d_coefpad);
+                         c->d_rowinfo, c->d_schunk, c->n_schunk, kRunPad, kChunkRows, c->d_coefpad);
       IHIP(hipGetLastError());
       IHIP(hipStreamSynchronize(st));
     }

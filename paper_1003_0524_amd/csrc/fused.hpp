@@ -92,8 +92,10 @@ struct FusedArgs {
   const int64_t* ch_coef;
   const double2* coef;            // L_c (column-major, per channel)
   const double2* cvec;            // l_c per multipole-free row
-  const double2* coefpad;         // per chunk of 32 multipole-free rows, [MAXT][32]: the first MAXT
-                                  // entries of each row's run (transposed), zero padded
+  const int4* schunk;             // chunks of whole channels, at most 64 rows: {first row, rows,
+  int32_t n_schunk;               //  longest run, 0}
+  const double2* coefpad;         // per chunk, [MAXT][64]: the first MAXT entries of each row's
+                                  // run (transposed), zero padded
   const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
                                   // {index in coef of conj-coefficient run L_c[i..b-1][i], b - i,
                                   //  multipole row n_s + c, 0}
@@ -102,7 +104,7 @@ struct FusedArgs {
   int32_t gstride, dstride;
 };
 
-template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 32, int OCC = 1>
+template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
 struct FusedCfg {
   using T = Traits<MODE>;
   using lds_t = typename T::lds_t;
@@ -125,11 +127,14 @@ struct FusedCfg {
   static constexpr int NPW = (NPT + NW - 1) / NW;
   static constexpr bool GSTREAM = NPW > 8;
   static constexpr int NU = NCC * KC / EPV;             // A panel units (EPV consecutive k of one column)
-  static constexpr int GS = 32, CB = CBX;                // sparse step: rows, columns
+  static constexpr int CB = CBX;                         // sparse step: columns (CB / NW per wavefront)
+  static constexpr int CPW = CB / NW;
+  static constexpr int NCB = (NCC + CB - 1) / CB;        // column blocks of a sparse chunk (at most)
   static constexpr int MAXT = 16;                        // coefficients per row staged in LDS (longer runs: global)
-  static constexpr int SPL = GS + EPV;                   // sparse stage pitch
-  static constexpr int COEF_B = GS * MAXT * 16;          // one row chunk of the padded coefficient table
-  static constexpr int SPARSE_B = 2 * CB * 1024 + NPL * NCC * SPL * ESZ + 2 * COEF_B;
+  static constexpr int CFL = MAXT * GR / NT;             // coefficient table: 16-byte loads per thread
+  static constexpr int SP_CF = CB * GR * 16;             // sparse phase LDS: [NW][CPW][GR] rows of M,
+  static constexpr int SP_ST = SP_CF + MAXT * GR * 16;   // then [MAXT][GR] coefficients, then the Gram stage
+  static constexpr int SPARSE_B = SP_ST + YS * ESZ;
   static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel (complex128 worst case)
   static constexpr int PL_B = ABUF * ESZ;               // converted panel
   static constexpr size_t DENSE_B = (size_t)(RAW_B + PL_B > YS * ESZ ? RAW_B + PL_B : YS * ESZ);
@@ -144,10 +149,11 @@ struct FusedCfg {
   static_assert(KC % KS == 0 && KC % EPV == 0, "K panel is a whole number of MFMA steps");
   static_assert(GR % KS == 0, "Gram chunk is a whole number of MFMA steps");
   static_assert(LDS_B + 16 <= 163840 / OCC, "fused configuration exceeds its share of the 160 KB of LDS");
-  static_assert(CB % 8 == 0 && CB >= 8, "sparse step: whole column pairs per wavefront");
+  static_assert(CB % NW == 0 && CB >= NW, "sparse step: whole columns per wavefront");
+  static_assert((MAXT * GR) % NT == 0, "coefficient table: whole loads per thread");
 };
 
-template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 32, int OCC = 1>
+template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
 __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
   using C = FusedCfg<MODE, RTW, NCT, NB8M, KC, CBX, OCC>;
   using lds_t = typename C::lds_t;
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
     for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
 
     // ---- contraction of the staged GR rows into this wave's Gram tiles ----
-    // rows_c: rows of the stage (GR dense, GS sparse), pitch: its row pitch
+    // rows_c: rows of the stage (GR), pitch: its row pitch
     auto contract_chunk = [&](const lds_t* Ys, int ng, auto rows_c, int pitch) {
       constexpr int ROWS = decltype(rows_c)::value;
       auto one = [&](int tp, accv_t acc) -> accv_t {
@@ -277,143 +283,176 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
       };
 
       // ================= multipole-free rows (block-sparse) =================
-      // Steps of GS rows x CB columns. The rows [sr0, sr0 + 64) of each column of the
-      // step (every row a multipole-free row of the chunk needs: channels are at most
-      // 33 rows long) go straight from M into LDS one step ahead (1 KB per column,
-      // double buffered); the multipole values come through registers, also one step
-      // ahead. Each wavefront owns two columns per pass (lanes 0-31 and 32-63, one
-      // row each), so the FP64 sums of |Y|^2 are reduced in a fixed order.
+      // Chunks of whole channels of at most GR rows (lane = row of the chunk), so that
+      // every run L_c[i..b-1][i] meets rows of its own chunk only. A step is one chunk
+      // and a block of CB columns; wavefront w owns the columns w, w + NW, ... of the
+      // block: their rows of M and the multipole value of each row's channel come to
+      // registers one step ahead, go to the wavefront's own LDS slots, and Y_s is
+      // computed from there with no workgroup barrier (one coefficient read serves all
+      // CPW columns of the lane). The workgroup meets once per chunk, when every column
+      // is staged, to contract it. The FP64 sums of |Y|^2 stay in registers, one per
+      // lane (row) and column, and are summed over the rows once at the end.
       if (a.n_s > 0) {
-        constexpr int GS = C::GS, CB = C::CB, SPL = C::SPL;
-        const int nrc = (a.n_s + GS - 1) / GS, ncb = (ncols + CB - 1) / CB;
-        const int nsteps = nrc * ncb;
-        const int rl = lane & 31, half = lane >> 5;
-        lds_t* Ss = (lds_t*)(smem + 2 * CB * 1024);       // sparse stage, after the two M buffers
-        u4_t mp_next[CB / 8];
-        // row data of the lane's row: l_c, run length, multipole row; the coefficient runs
-        // of a row chunk go to LDS (rows of 16 complex), one chunk ahead
-        const double2* Cf = (const double2*)(smem + 2 * CB * 1024 + NPL * NCC * SPL * C::ESZ);   // [2][MAXT][GS]
-        const __amdgpu_buffer_rsrc_t crs =
-            make_rsrc(a.coefpad, (uint32_t)((a.n_s + GS - 1) / GS * GS * C::MAXT * 16));
+        constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, CFL = C::CFL;
+        const int nck = a.n_schunk;
+        const int ncb = (ncols + CB - 1) / CB;
+        const int nsteps = nck * ncb;
+        double2* Ms = (double2*)(smem + w * CPW * GR * 16);   // this wavefront's [CPW][GR] rows of M
+        double2* Cf = (double2*)(smem + C::SP_CF);            // [MAXT][GR] coefficient runs of the chunk
+        lds_t* Ss = (lds_t*)(smem + C::SP_ST);                // [NPL][NCC][LDR] Gram stage
+        double dreg[NCB][CPW];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) dreg[b][j] = 0.0;
+
         struct RowData { double2 lc; int cs, len, mrow; };
-        auto load_rows = [&](int sr, RowData& d) {
-          const int rr = sr + rl;
-          d.len = 0; d.cs = 0; d.mrow = a.n_s;
+        auto chunk_info = [&](int ck) -> int4 {       // {first row, rows, longest run, 0}
+          int4 v = a.schunk[ck];
+          v.x = uni(v.x); v.y = uni(v.y); v.z = uni(v.z);
+          return v;
+        };
+        auto load_rows = [&](const int4& ci, RowData& d) {
+          d.len = 0; d.cs = 0; d.mrow = 0;
           d.lc = make_double2(0.0, 0.0);
-          if (rr < a.n_s) {
-            const int4 ri = a.rowinfo[rr];
+          if (lane < ci.y) {
+            const int4 ri = a.rowinfo[ci.x + lane];
             d.cs = ri.x; d.len = ri.y; d.mrow = ri.z;
-            d.lc = a.cvec[rr];
-          }
-          // the chunk's MAXT x GS table (8 KB, contiguous in global memory): 8 instructions
-          const int cbuf = (sr / GS) & 1;
-#pragma unroll
-          for (int t = 0; t < (C::COEF_B / 1024 + NW - 1) / NW; ++t) {
-            const int m = w + NW * t;
-            if (m < C::COEF_B / 1024)
-              lds_load16(crs, (void*)((const unsigned char*)Cf + cbuf * C::COEF_B + m * 1024),
-                         (uint32_t)(sr * C::MAXT * 16 + m * 1024 + lane * 16), 0u);
+            d.lc = a.cvec[ci.x + lane];
           }
         };
-        RowData rd, rd_next;
-        auto sparse_prefetch = [&](int st) {
-          const int sr0 = (st / ncb) * GS, cb0 = (st % ncb) * CB;
-          unsigned char* S1 = Raw + (st & 1) * (CB * 1024);
-          // 1 KB per column: rows sr0 .. sr0 + 63 (complex128) or .. + 127 (complex64)
+        u4_t cfn[CFL];                                // the next chunk's coefficient table
+        auto load_coef = [&](int ck) {
+          const u4_t* src = (const u4_t*)(a.coefpad + (long)ck * MAXT * GR);
 #pragma unroll
-          for (int t = 0; t < CB / NW; ++t) {
-            const int cl = w + NW * t, c = cb0 + cl;
+          for (int i = 0; i < CFL; ++i) cfn[i] = src[tid + NT * i];
+        };
+        auto store_coef = [&]() {
+#pragma unroll
+          for (int i = 0; i < CFL; ++i) ((u4_t*)Cf)[tid + NT * i] = cfn[i];
+        };
+        u4_t xn[CPW], mn[CPW];                        // the next step's values of M
+        auto fetch = [&](int st, const int4& ci, const RowData& d) {
+          const int cb0 = (st % ncb) * CB;
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            const int c = cb0 + w + NW * j;
             int n = 0;
             const long col = col_index(c, n);
-            const bool ok = c < ncols && n < nb;
-            const uint32_t vo = ok ? (uint32_t)((col * pi.nmb + sr0) * esz + lane * 16) : 0x80000000u;
-            lds_load16(mrs, S1 + cl * 1024, vo, 0u);
-          }
-          // multipole value of each (row, column) this lane computes
-#pragma unroll
-          for (int t = 0; t < CB / 8; ++t) {
-            const int c = cb0 + 2 * (w + NW * t) + half, r = sr0 + rl;
-            int n = 0;
-            const long col = col_index(c, n);
-            const bool ok = c < ncols && n < nb && r < a.n_s;
-            // the step's row chunk is the current one or the next
-            const int mrow = (st % ncb == 0) ? rd_next.mrow : rd.mrow;
-            const uint32_t vo = ok ? (uint32_t)((col * pi.nmb + mrow) * esz) : 0x80000000u;
+            const bool ok = c < ncols && n < nb && lane < ci.y;
+            const uint32_t vx = ok ? (uint32_t)((col * pi.nmb + ci.x + lane) * esz) : 0x80000000u;
+            const uint32_t vm = ok ? (uint32_t)((col * pi.nmb + d.mrow) * esz) : 0x80000000u;
             if (a.m_c64) {
-              const uint2 v = buf_load<uint2>(mrs, vo, 0u);
-              mp_next[t] = u4_t{v.x, v.y, 0u, 0u};
+              const uint2 x = buf_load<uint2>(mrs, vx, 0u), m = buf_load<uint2>(mrs, vm, 0u);
+              xn[j] = u4_t{x.x, x.y, 0u, 0u};
+              mn[j] = u4_t{m.x, m.y, 0u, 0u};
             } else {
-              mp_next[t] = buf_load<u4_t>(mrs, vo, 0u);
+              xn[j] = buf_load<u4_t>(mrs, vx, 0u);
+              mn[j] = buf_load<u4_t>(mrs, vm, 0u);
             }
           }
         };
+        auto to_d2 = [&](u4_t v) -> double2 {
+          if (a.m_c64) return make_double2((double)__uint_as_float(v.x), (double)__uint_as_float(v.y));
+          return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+        };
+
+        int4 ci = chunk_info(0), ci_next = ci;
+        RowData rd, rd_next;
+        load_rows(ci, rd);
+        rd_next = rd;
+        load_coef(0);
         __syncthreads();                              // earlier users of the LDS are done
-        load_rows(0, rd_next);
-        sparse_prefetch(0);
+        store_coef();
+        if (nck > 1) {
+          ci_next = chunk_info(1);
+          load_rows(ci_next, rd_next);
+          load_coef(1);
+        }
+        fetch(0, ci, rd);
+        __syncthreads();                              // the first chunk's coefficients are visible
         for (int st = 0; st < nsteps; ++st) {
-          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
-          __syncthreads();                            // step st staged; the other buffer and the stage are free
-          u4_t mp[CB / 8];
+          const int cbk = st % ncb, cb0 = cbk * CB;
+          double2 xm[CPW];
 #pragma unroll
-          for (int t = 0; t < CB / 8; ++t) mp[t] = mp_next[t];
-          const int sr0 = (st / ncb) * GS, cb0 = (st % ncb) * CB;
-          const unsigned char* S1 = Raw + (st & 1) * (CB * 1024);
-          if (st % ncb == 0) {                        // a new row chunk: its row data, then the next chunk's
-            rd = rd_next;
-            load_rows(sr0 + GS, rd_next);
+          for (int j = 0; j < CPW; ++j) {             // this step's columns to the wavefront's slots
+            Ms[j * GR + lane] = to_d2(xn[j]);
+            xm[j] = to_d2(mn[j]);
           }
-          if (st + 1 < nsteps) sparse_prefetch(st + 1);   // needs the row data of step st + 1's chunk
-          const int r = sr0 + rl;
+          if (st + 1 < nsteps) {
+            if (cbk + 1 < ncb) fetch(st + 1, ci, rd);
+            else fetch(st + 1, ci_next, rd_next);
+          }
+          // LDS operations of one wavefront take effect in order: the slots just written
+          // are read below by other lanes of the same wavefront
+          __builtin_amdgcn_wave_barrier();
+          // Y_s[r] = sum_{j >= i} conj(L_c[j][i]) A[first + j] + l_c[i] A[multipole row of c]
+          double2 y[CPW];
 #pragma unroll
-          for (int t = 0; t < CB / 8; ++t) {
-            const int cl = 2 * (w + NW * t) + half, c = cb0 + cl;
-            double yr = 0.0, yi = 0.0;
-            int n = 0;
-            (void)col_index(c, n);
-            if (r < a.n_s && c < ncols && n < nb) {
-              // Y_s[r] = sum_{j >= i} conj(L_c[j][i]) A[first + j] + l_c[i] A[multipole row of c]:
-              // the run of L_c[j][i], j >= i, meets the rows r, r + 1, ... of M
-              auto term = [&](double2 l, int row) {
-                double xr, xi;
-                if (a.m_c64) {
-                  const float2 v = *(const float2*)(S1 + cl * 1024 + row * 8);
-                  xr = v.x; xi = v.y;
-                } else {
-                  const double2 v = *(const double2*)(S1 + cl * 1024 + row * 16);
-                  xr = v.x; xi = v.y;
-                }
-                yr += l.x * xr + l.y * xi;
-                yi += l.x * xi - l.y * xr;
-              };
-              const double2* cfl = Cf + ((st / ncb) & 1) * (GS * C::MAXT) + rl;
-              const int tl = min(rd.len, C::MAXT);
-              for (int t = 0; t < tl; ++t) term(cfl[t * GS], rl + t);
-              for (int t = C::MAXT; t < rd.len; ++t) term(a.coef[rd.cs + t], rl + t);
-              const double2 lc = rd.lc;
-              double xmr, xmi;
-              if (a.m_c64) {
-                xmr = __uint_as_float(mp[t].x); xmi = __uint_as_float(mp[t].y);
-              } else {
-                xmr = __hiloint2double((int)mp[t].y, (int)mp[t].x);
-                xmi = __hiloint2double((int)mp[t].w, (int)mp[t].z);
+          for (int j = 0; j < CPW; ++j) {
+            y[j].x = rd.lc.x * xm[j].x - rd.lc.y * xm[j].y;
+            y[j].y = rd.lc.x * xm[j].y + rd.lc.y * xm[j].x;
+          }
+          const int T = min(ci.z, MAXT);
+          for (int t = 0; t < T; ++t) {
+            const double2 l = Cf[t * GR + lane];
+            if (t < rd.len) {
+#pragma unroll
+              for (int j = 0; j < CPW; ++j) {
+                const double2 x = Ms[j * GR + lane + t];
+                y[j].x += l.x * x.x + l.y * x.y;
+                y[j].y += l.x * x.y - l.y * x.x;
               }
-              yr += lc.x * xmr - lc.y * xmi;
-              yi += lc.x * xmi + lc.y * xmr;
             }
-            if (c < NCC) {
-              put_real<MODE>(Ss + (0 * NP) * NCC * SPL + c * SPL + rl, NCC * SPL, yr);
-              put_real<MODE>(Ss + (1 * NP) * NCC * SPL + c * SPL + rl, NCC * SPL, yi);
-            }
-            double d = yr * yr + yi * yi;
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) d += __shfl_xor(d, o);    // within the 32-lane half
-            if (rl == 0 && c < NCC) Dacc[(w * NCC + c) * 2] += d;
           }
-          if (st % ncb == ncb - 1) {                  // the chunk's columns are staged: contract
-            __syncthreads();
-            contract_chunk(Ss, ng, std::integral_constant<int, GS>{}, SPL);
+          for (int t = MAXT; t < rd.len; ++t) {       // runs longer than the staged table
+            const double2 l = a.coef[rd.cs + t];
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+              const double2 x = Ms[j * GR + lane + t];
+              y[j].x += l.x * x.x + l.y * x.y;
+              y[j].y += l.x * x.y - l.y * x.x;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            const int c = cb0 + w + NW * j;
+            if (c < NCC) {
+              put_real<MODE>(Ss + (0 * NP) * NCC * LDR + c * LDR + lane, NCC * LDR, y[j].x);
+              put_real<MODE>(Ss + (1 * NP) * NCC * LDR + c * LDR + lane, NCC * LDR, y[j].y);
+            }
+            const double d = y[j].x * y[j].x + y[j].y * y[j].y;
+#pragma unroll
+            for (int b = 0; b < NCB; ++b)
+              if (b == cbk) dreg[b][j] += d;
+          }
+          if (cbk == ncb - 1) {                       // the chunk's columns are staged
+            __syncthreads();                          // (its coefficients are no longer read)
+            const int ck = st / ncb;
+            if (ck + 1 < nck) {
+              store_coef();
+              ci = ci_next;
+              rd = rd_next;
+              if (ck + 2 < nck) {
+                ci_next = chunk_info(ck + 2);
+                load_rows(ci_next, rd_next);
+                load_coef(ck + 2);
+              }
+            }
+            contract_chunk(Ss, ng, std::integral_constant<int, GR>{}, LDR);
+            __syncthreads();                          // the stage is free, the next coefficients visible
           }
         }
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            double d = dreg[b][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+            const int c = b * CB + w + NW * j;
+            if (lane == 0 && c < NCC) Dacc[(w * NCC + c) * 2] += d;
+          }
       }
 
       // ================= dense rows: row blocks of BM rows =================
