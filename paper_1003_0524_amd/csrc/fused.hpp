@@ -135,7 +135,7 @@ struct FusedCfg {
   static constexpr int SP_CF = CB * GR * 16;             // sparse phase LDS: [NW][CPW][GR] rows of M,
   static constexpr int SP_ST = SP_CF + MAXT * GR * 16;   // then [MAXT][GR] coefficients, then the Gram stage
   static constexpr int SPARSE_B = SP_ST + YS * ESZ;
-  static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel (complex128 worst case)
+  static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel in bytes (complex128 worst case)
   static constexpr int PL_B = ABUF * ESZ;               // converted panel
   static constexpr size_t DENSE_B = (size_t)(RAW_B + PL_B > YS * ESZ ? RAW_B + PL_B : YS * ESZ);
   static constexpr size_t MAIN_RAW = DENSE_B > (size_t)SPARSE_B ? DENSE_B : (size_t)SPARSE_B;
@@ -151,6 +151,7 @@ struct FusedCfg {
   static_assert(LDS_B + 16 <= 163840 / OCC, "fused configuration exceeds its share of the 160 KB of LDS");
   static_assert(CB % NW == 0 && CB >= NW, "sparse step: whole columns per wavefront");
   static_assert((MAXT * GR) % NT == 0, "coefficient table: whole loads per thread");
+  static_assert(MAXT % 2 == 0, "the sparse run loop takes two terms per pass");
 };
 
 template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
@@ -171,16 +172,13 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
   lds_t* Ys = (lds_t*)smem;                    // [NPL][NCC][LDR] (Gram stage; aliases the K panels)
   double* Dacc = (double*)(smem + C::MAIN_B);  // [NW][NCC][2]
 
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: branches on it stay scalar
-  const int l16 = lane & 15, lq = lane >> 4;
-  const int c8 = l16 & 7, part = l16 >> 3;
+  const int tid0 = threadIdx.x;
 
   int qi = a.counter ? (int)(blockIdx.x % a.nq) : 0, empty = 0;
   for (int iter = 0;; ++iter) {
     int idx;
     if (a.counter) {
-      if (tid == 0) s_item = atomicAdd(a.counter + qi, 1);
+      if (tid0 == 0) s_item = atomicAdd(a.counter + qi, 1);
       __syncthreads();
       idx = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
@@ -198,12 +196,24 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
       if (idx >= a.n_items) break;
     }
 
+    // Lane indices, derived afresh for every item from a copy of the thread index that the
+    // compiler cannot see through: values computed from them (addresses, masks) are not
+    // hoisted out of the item loop and kept live, in registers or spilled, for the whole
+    // kernel.
+    int tid_o = tid0;
+    asm volatile("" : "+v"(tid_o));
+    const int tid = tid_o, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: branches on it stay scalar
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int c8 = l16 & 7, part = l16 >> 3;
+
     WorkItem wi = a.items[idx];
     wi.pair = uni(wi.pair); wi.g0 = uni(wi.g0); wi.g1 = uni(wi.g1); wi.ngc = uni(wi.ngc); wi.slot = uni(wi.slot);
     PairInfo pi = a.pairs[wi.pair];
     pi.k = uni(pi.k); pi.nb = uni(pi.nb); pi.nmb = uni(pi.nmb); pi.nd = uni(pi.nd); pi.nb8 = uni(pi.nb8);
     pi.m_off = uni(pi.m_off); pi.u_off = uni(pi.u_off); pi.ldu = uni(pi.ldu);
     const int nb = pi.nb, nb8 = pi.nb8, nbt = nb8 >> 3;
+    const uint32_t nb8_rcp = uni((int32_t)(0xFFFFFFFFu / (uint32_t)nb8 + 1u));
     const int npt = nbt * (nbt + 1) / 2;
     const int nd = pi.nd;
     const int esz = a.m_c64 ? 8 : 16;
@@ -276,8 +286,10 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
     for (int gbase = wi.g0; gbase < wi.g1; gbase += wi.ngc) {
       const int ng = min(wi.ngc, wi.g1 - gbase);
       const int ncols = ng * nb8;
-      auto col_index = [&](int c, int& n) -> long {       // item column -> M column (n'', n); n >= nb: padding
-        const int g = c / nb8;
+      // item column -> M column (n'', n); n >= nb: padding. c / nb8 as a multiply-high by
+      // ceil(2^32 / nb8), exact for c * nb8 < 2^32
+      auto col_index = [&](int c, int& n) -> long {
+        const int g = (int)__umulhi((uint32_t)c, nb8_rcp);
         n = c - g * nb8;
         return (long)(gbase + g) * nb + n;
       };
@@ -393,16 +405,30 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             y[j].x = rd.lc.x * xm[j].x - rd.lc.y * xm[j].y;
             y[j].y = rd.lc.x * xm[j].y + rd.lc.y * xm[j].x;
           }
+          // Coefficients past a row's run are zero in the table and every row slot of the
+          // wavefront holds finite data (zero past the chunk), so all lanes run T terms
+          // without a branch; rows past the slot's end are clamped (their coefficient is
+          // zero). Two terms per pass: all LDS reads first, then the FMAs.
           const int T = min(ci.z, MAXT);
-          for (int t = 0; t < T; ++t) {
-            const double2 l = Cf[t * GR + lane];
-            if (t < rd.len) {
+          for (int t = 0; t < T; t += 2) {            // row T < MAXT of the table is zero if T is odd
+            const double2 l0 = Cf[t * GR + lane], l1 = Cf[(t + 1) * GR + lane];
+            const int r0 = min(lane + t, GR - 1), r1 = min(lane + t + 1, GR - 1);
+            double2 x0[CPW], x1[CPW];
 #pragma unroll
-              for (int j = 0; j < CPW; ++j) {
-                const double2 x = Ms[j * GR + lane + t];
-                y[j].x += l.x * x.x + l.y * x.y;
-                y[j].y += l.x * x.y - l.y * x.x;
-              }
+            for (int j = 0; j < CPW; ++j) {
+              x0[j] = Ms[j * GR + r0];
+              x1[j] = Ms[j * GR + r1];
+            }
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+              y[j].x = fma(l0.x, x0[j].x, y[j].x);
+              y[j].x = fma(l0.y, x0[j].y, y[j].x);
+              y[j].y = fma(l0.x, x0[j].y, y[j].y);
+              y[j].y = fma(-l0.y, x0[j].x, y[j].y);
+              y[j].x = fma(l1.x, x1[j].x, y[j].x);
+              y[j].x = fma(l1.y, x1[j].y, y[j].x);
+              y[j].y = fma(l1.x, x1[j].y, y[j].y);
+              y[j].y = fma(-l1.y, x1[j].x, y[j].y);
             }
           }
           for (int t = MAXT; t < rd.len; ++t) {       // runs longer than the staged table
@@ -475,11 +501,13 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         {
           const int cpi = a.m_c64 ? 4 : 2;                 // columns per instruction
           const int lpc = 64 / cpi;                        // lanes per column
+          int lane_d = lane;                               // (not hoisted above the sparse phase)
+          asm volatile("" : "+v"(lane_d));
 #pragma unroll
           for (int t = 0; t < NIW; ++t) {
             const int idx = w + NW * t;
-            const int c = idx * cpi + lane / lpc;
-            const int k = (lane % lpc) * (a.m_c64 ? 2 : 1);
+            const int c = idx * cpi + lane_d / lpc;
+            const int k = (lane_d % lpc) * (a.m_c64 ? 2 : 1);
             int n = 0;
             const long col = col_index(c, n);
             const bool ok = idx < NI && c < ncols && n < nb && c * KC * esz < C::RAW_B;
