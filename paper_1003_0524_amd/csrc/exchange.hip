@@ -62,8 +62,10 @@ const KernelCfg kCfgs[] = {
 // count per n'' value, KC complex k per K-loop panel.
 // coefficients per multipole-free row staged by the fused kernel (its MAXT)
 constexpr int kRunPad = FusedCfg<M_BF16X3, 1, 1, 1, 32>::MAXT;
-// rows per chunk of multipole-free rows (one per lane)
+// chunks of multipole-free rows: rows (one per lane), multipole rows, chunks (at most)
 constexpr int kChunkRows = FusedCfg<M_BF16X3, 1, 1, 1, 32>::GR;
+constexpr int kChunkMP = FusedCfg<M_BF16X3, 1, 1, 1, 32>::MPC;
+constexpr int kMaxChunks = FusedCfg<M_BF16X3, 1, 1, 1, 32>::MAXCK;
 
 struct FusedKCfg {
   int mode, RTW, NCT, NB8M, KC, CB, OCC;
@@ -140,6 +142,7 @@ struct exc_ctx {
   int4* d_rowinfo = nullptr;          // fused kernel: per multipole-free row (see FusedArgs)
   double2* d_coefpad = nullptr;       // fused kernel: padded coefficient runs (see FusedArgs)
   int4* d_schunk = nullptr;           // fused kernel: chunks of whole channels (see FusedArgs)
+  std::vector<int4> h_schunk;
   int n_schunk = 0;
   int64_t* d_ch_coef = nullptr;
   // pairs, plans, buffers
@@ -284,6 +287,28 @@ void release(exc_ctx* c) {
 double fused_cost(const exc_ctx* c, const PairInfo& p, int ncols) {
   const double contract = (double)(c->n_s + p.nd) * p.nb8 * p.nb8;
   return contract + 4.0 * c->n_s * ncols + (double)p.nd * p.nd * ncols;
+}
+
+// The fused kernel's chunks of multipole-free rows: whole channels, at most kChunkRows
+// rows, multipole rows (n_s + channel) within kChunkMP consecutive rows; {first row, rows,
+// longest run, first multipole row}. False if a channel does not fit one chunk or there
+// are more than kMaxChunks chunks.
+bool sparse_chunks(const exc_ctx* c, const std::vector<int>& row_chan, std::vector<int4>& out) {
+  out.clear();
+  int r = 0;
+  while (r < c->n_s) {
+    const int r0 = r, ch0 = row_chan[r];
+    int longest = 0;
+    while (r < c->n_s) {
+      const int ch = row_chan[r], b = c->ch_len[ch];      // r is the first row of channel ch
+      if (r - r0 + b > kChunkRows || ch - ch0 >= kChunkMP) break;
+      longest = std::max(longest, b);
+      r += b;
+    }
+    if (r == r0) return false;                            // a channel longer than a chunk
+    out.push_back(make_int4(r0, r - r0, longest, c->n_s + ch0));
+  }
+  return (int)out.size() <= kMaxChunks;
 }
 
 // Relative cost of one row block (for balancing and LPT order).
@@ -911,11 +936,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
     const char* ev = getenv("EXC_FUSED");
     c->fcfg = pick_fused(c->precision, c->nbt_max);
-    // the fused kernel takes the multipole-free rows in chunks of whole channels of at
-    // most 64 rows
-    int maxb = 0;
-    for (int ch = 0; ch < c->n_ch; ++ch) maxb = std::max(maxb, c->nrad[ch] - 1);
-    c->fused_ok = c->fcfg && maxb <= kChunkRows;
+    c->fused_ok = c->fcfg && sparse_chunks(c, row_chan, c->h_schunk);
+    if (!c->fused_ok) c->h_schunk.clear();
     c->fused = c->fused_ok && !(ev && ev[0] == '0');
     if (!c->fused) c->fcfg = nullptr;
   }
@@ -955,25 +977,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         ri[r] = make_int4((int)(c->ch_coef[ch] + (int64_t)i * b + i), b - i, c->n_s + ch, 0);
       }
       ITRY(upload(c, &c->d_rowinfo, ri));
-      // chunks of whole channels of at most kChunkRows rows (the fused kernel's lane = row);
-      // needs every channel to fit one chunk
-      std::vector<int4> ck;
-      bool fits = true;
-      for (int ch = 0; ch < c->n_ch; ++ch) fits = fits && c->ch_len[ch] <= kChunkRows;
-      if (fits) {
-        int r = 0;
-        while (r < c->n_s) {
-          const int r0 = r;
-          int longest = 0;
-          while (r < c->n_s) {
-            const int b = c->ch_len[row_chan[r]];        // r is the first row of its channel
-            if (r - r0 + b > kChunkRows) break;
-            longest = std::max(longest, b);
-            r += b;
-          }
-          ck.push_back(make_int4(r0, r - r0, longest, 0));
-        }
-      }
+      std::vector<int4> ck = c->h_schunk;
       c->n_schunk = (int)ck.size();
       if (ck.empty()) ck.push_back(make_int4(0, 0, 0, 0));
       ITRY(upload(c, &c->d_schunk, ck));

@@ -57,6 +57,16 @@ __device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t r, void* lds, 
                                            (int)soff, 0, 0);
 }
 
+// Lane l takes the value of lane l + 1 (the last lane takes zero): a whole-wavefront DPP
+// shift, per 32-bit half.
+__device__ __forceinline__ double shift_down1(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x130, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double2 shift_down1(double2 v) { return make_double2(shift_down1(v.x), shift_down1(v.y)); }
+
 // Values the whole workgroup shares, moved to scalar registers: loads of them
 // are vector loads (the kernel also writes global memory), and buffer
 // resources built from vector registers would need a loop over lanes.
@@ -71,8 +81,12 @@ __device__ __forceinline__ T* uni(T* p) { return (T*)uni((int64_t)p); }
 
 // Work queues of the persistent launch: NQ queues (one per XCD: consecutive
 // workgroups are dispatched to the 8 XCDs in turn, so workgroup b serves queue
-// b % NQ first), each a range of the item array with its own atomic counter;
-// a workgroup whose queue is empty takes items from the following queues.
+// b % NQ first), each a range of the item array. The first item of every workgroup
+// is fixed (workgroup b takes item b / NQ of its queue); the rest are claimed with
+// the queue's atomic counter, one item ahead (the claim is issued when an item
+// starts and read when it ends: counters shared by the XCDs are far away). A
+// workgroup whose queue is empty reads all counters at once and takes items from
+// queues that still have some.
 constexpr int NQ_MAX = 8;
 
 struct FusedArgs {
@@ -92,8 +106,8 @@ struct FusedArgs {
   const int64_t* ch_coef;
   const double2* coef;            // L_c (column-major, per channel)
   const double2* cvec;            // l_c per multipole-free row
-  const int4* schunk;             // chunks of whole channels, at most 64 rows: {first row, rows,
-  int32_t n_schunk;               //  longest run, 0}
+  const int4* schunk;             // chunks of whole channels, at most 64 rows and 16 multipole rows:
+  int32_t n_schunk;               //  {first row, rows, longest run, first multipole row}
   const double2* coefpad;         // per chunk, [MAXT][64]: the first MAXT entries of each row's
                                   // run (transposed), zero padded
   const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
@@ -130,10 +144,13 @@ struct FusedCfg {
   static constexpr int CB = CBX;                         // sparse step: columns (CB / NW per wavefront)
   static constexpr int CPW = CB / NW;
   static constexpr int NCB = (NCC + CB - 1) / CB;        // column blocks of a sparse chunk (at most)
-  static constexpr int MAXT = 16;                        // coefficients per row staged in LDS (longer runs: global)
+  static constexpr int MAXT = 12;                        // coefficients per row staged in LDS (longer runs: global)
   static constexpr int CFL = MAXT * GR / NT;             // coefficient table: 16-byte loads per thread
-  static constexpr int SP_CF = CB * GR * 16;             // sparse phase LDS: [NW][CPW][GR] rows of M,
-  static constexpr int SP_ST = SP_CF + MAXT * GR * 16;   // then [MAXT][GR] coefficients, then the Gram stage
+  static constexpr int MPC = GR / CPW;                   // multipole rows per sparse chunk (at most)
+  static constexpr int MAXCK = 64;                       // sparse chunks (at most)
+  static constexpr int SP_MP = 0;                        // sparse phase LDS: [NW][CPW][MPC] multipole rows,
+  static constexpr int SP_CF = SP_MP + CB * MPC * 16;    // [MAXT][GR] coefficients,
+  static constexpr int SP_ST = SP_CF + MAXT * GR * 16;   // then the Gram stage
   static constexpr int SPARSE_B = SP_ST + YS * ESZ;
   static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel in bytes (complex128 worst case)
   static constexpr int PL_B = ABUF * ESZ;               // converted panel
@@ -148,10 +165,10 @@ struct FusedCfg {
   static_assert(RTW >= 1 && RTW <= 5, "one to five row tiles per wavefront");
   static_assert(KC % KS == 0 && KC % EPV == 0, "K panel is a whole number of MFMA steps");
   static_assert(GR % KS == 0, "Gram chunk is a whole number of MFMA steps");
-  static_assert(LDS_B + 16 <= 163840 / OCC, "fused configuration exceeds its share of the 160 KB of LDS");
+  static_assert(LDS_B + 16 * MAXCK + 16 <= 163840 / OCC, "fused configuration exceeds its share of the 160 KB of LDS");
   static_assert(CB % NW == 0 && CB >= NW, "sparse step: whole columns per wavefront");
   static_assert((MAXT * GR) % NT == 0, "coefficient table: whole loads per thread");
-  static_assert(MAXT % 2 == 0, "the sparse run loop takes two terms per pass");
+  static_assert(CPW * MPC == 64, "one multipole block load per wavefront and sparse step");
 };
 
 template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
@@ -167,6 +184,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 
   __shared__ __align__(16) unsigned char smem[C::LDS_B];
   __shared__ int s_item;
+  __shared__ int4 s_chunk[C::MAXCK];
   unsigned char* Raw = smem;                   // [NCC][KC] complex, as loaded   (K loop)
   lds_t* Apl = (lds_t*)(smem + C::RAW_B);      // [NPL][NCC][LDK] pieces          (K loop)
   lds_t* Ys = (lds_t*)smem;                    // [NPL][NCC][LDR] (Gram stage; aliases the K panels)
@@ -174,27 +192,50 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 
   const int tid0 = threadIdx.x;
 
-  int qi = a.counter ? (int)(blockIdx.x % a.nq) : 0, empty = 0;
-  for (int iter = 0;; ++iter) {
-    int idx;
-    if (a.counter) {
-      if (tid0 == 0) s_item = atomicAdd(a.counter + qi, 1);
-      __syncthreads();
-      idx = __builtin_amdgcn_readfirstlane(s_item);
-      __syncthreads();
-      const int q0 = a.qbeg[qi], q1 = a.qbeg[qi + 1];
-      if (q0 + idx >= q1) {                        // this queue is drained: try the next one
-        if (++empty >= a.nq) break;
-        qi = (qi + 1) % a.nq;
-        continue;
-      }
-      empty = 0;
-      idx = __builtin_amdgcn_readfirstlane(q0 + idx);
-    } else {
-      if (iter > 0) break;
-      idx = blockIdx.x;
-      if (idx >= a.n_items) break;
+  __shared__ int s_left[NQ_MAX];
+  const int nq = a.counter ? a.nq : 1;
+  const int G = (int)gridDim.x;
+  const int qi = a.counter ? (int)(blockIdx.x % nq) : 0;
+  auto n_static = [&](int q) { return (G - q + nq - 1) / nq; };   // workgroups whose first queue is q
+  int qh0 = 0, qh1 = 0;                           // the first queue's item range
+  int idx;
+  if (a.counter) {
+    qh0 = uni(a.qbeg[qi]);
+    qh1 = uni(a.qbeg[qi + 1]);
+    const int j = qh0 + (int)blockIdx.x / nq;
+    idx = j < qh1 ? j : -1;
+  } else {
+    idx = (int)blockIdx.x < a.n_items ? (int)blockIdx.x : -1;
+  }
+  bool home = a.counter != nullptr;
+  // an item of another queue, or -1 when every queue is drained
+  auto steal = [&]() -> int {
+    if (tid0 < nq) {
+      const int cnt = __hip_atomic_load(a.counter + tid0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_left[tid0] = a.qbeg[tid0] + n_static(tid0) + cnt < a.qbeg[tid0 + 1];
     }
+    __syncthreads();
+    int got = -1;
+    for (int o = 1; o < nq && got < 0; ++o) {
+      const int q = (qi + o) % nq;
+      if (!s_left[q]) continue;
+      if (tid0 == 0) s_item = atomicAdd(a.counter + q, 1);
+      __syncthreads();
+      const int j = a.qbeg[q] + n_static(q) + __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+      if (j < a.qbeg[q + 1]) got = j;
+    }
+    __syncthreads();
+    return uni(got);
+  };
+  for (;;) {
+    if (idx < 0) {
+      if (!a.counter) break;
+      idx = steal();
+      if (idx < 0) break;
+    }
+    int claim = 0;                                // the first queue's next item, claimed now
+    if (home && tid0 == 0) claim = atomicAdd(a.counter + qi, 1);
 
     // Lane indices, derived afresh for every item from a copy of the thread index that the
     // compiler cannot see through: values computed from them (addresses, masks) are not
@@ -295,21 +336,24 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
       };
 
       // ================= multipole-free rows (block-sparse) =================
-      // Chunks of whole channels of at most GR rows (lane = row of the chunk), so that
-      // every run L_c[i..b-1][i] meets rows of its own chunk only. A step is one chunk
-      // and a block of CB columns; wavefront w owns the columns w, w + NW, ... of the
-      // block: their rows of M and the multipole value of each row's channel come to
-      // registers one step ahead, go to the wavefront's own LDS slots, and Y_s is
-      // computed from there with no workgroup barrier (one coefficient read serves all
-      // CPW columns of the lane). The workgroup meets once per chunk, when every column
-      // is staged, to contract it. The FP64 sums of |Y|^2 stay in registers, one per
-      // lane (row) and column, and are summed over the rows once at the end.
+      // Chunks of whole channels of at most GR rows (lane = row of the chunk) whose
+      // multipole rows lie within MPC consecutive rows, so that every run L_c[i..b-1][i]
+      // meets rows of its own chunk only. A step is one chunk and a block of CB columns;
+      // wavefront w owns the columns w, w + NW, ... of the block: their rows of M (one
+      // per lane) and the chunk's multipole rows (one 16-row block per column) come to
+      // registers two steps ahead (two register sets, used in turn). Y_s is computed in
+      // registers: term t of a row's run needs the row t below it, which the lane gets
+      // by shifting the column's values down one lane per term (DPP), so each term costs
+      // one LDS read (its coefficient, shared by the lane's CPW columns) and no barrier.
+      // The workgroup meets once per chunk, when every column is staged, to contract it.
+      // The FP64 sums of |Y|^2 stay in registers, one per lane (row) and column, and are
+      // summed over the rows once at the end.
       if (a.n_s > 0) {
-        constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, CFL = C::CFL;
+        constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, CFL = C::CFL, MPC = C::MPC;
         const int nck = a.n_schunk;
         const int ncb = (ncols + CB - 1) / CB;
         const int nsteps = nck * ncb;
-        double2* Ms = (double2*)(smem + w * CPW * GR * 16);   // this wavefront's [CPW][GR] rows of M
+        double2* Mp = (double2*)(smem + C::SP_MP + w * CPW * MPC * 16);   // this wavefront's [CPW][MPC] multipole rows
         double2* Cf = (double2*)(smem + C::SP_CF);            // [MAXT][GR] coefficient runs of the chunk
         lds_t* Ss = (lds_t*)(smem + C::SP_ST);                // [NPL][NCC][LDR] Gram stage
         double dreg[NCB][CPW];
@@ -318,18 +362,17 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int j = 0; j < CPW; ++j) dreg[b][j] = 0.0;
 
-        struct RowData { double2 lc; int cs, len, mrow; };
-        auto chunk_info = [&](int ck) -> int4 {       // {first row, rows, longest run, 0}
-          int4 v = a.schunk[ck];
-          v.x = uni(v.x); v.y = uni(v.y); v.z = uni(v.z);
-          return v;
+        struct RowData { double2 lc; int cs, len, mloc; };
+        auto chunk_info = [&](int ck) -> int4 {       // {first row, rows, longest run, first multipole row}
+          const int4 v = s_chunk[ck];
+          return make_int4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
         };
         auto load_rows = [&](const int4& ci, RowData& d) {
-          d.len = 0; d.cs = 0; d.mrow = 0;
+          d.len = 0; d.cs = 0; d.mloc = 0;
           d.lc = make_double2(0.0, 0.0);
           if (lane < ci.y) {
             const int4 ri = a.rowinfo[ci.x + lane];
-            d.cs = ri.x; d.len = ri.y; d.mrow = ri.z;
+            d.cs = ri.x; d.len = ri.y; d.mloc = ri.z - ci.w;
             d.lc = a.cvec[ci.x + lane];
           }
         };
@@ -343,8 +386,11 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int i = 0; i < CFL; ++i) ((u4_t*)Cf)[tid + NT * i] = cfn[i];
         };
-        u4_t xn[CPW], mn[CPW];                        // the next step's values of M
-        auto fetch = [&](int st, const int4& ci, const RowData& d) {
+        // one step's values of M: xn[j] = row (first + lane) of column j, pn = multipole
+        // row (first multipole row + lane % MPC) of column lane / MPC
+        struct StepRegs { u4_t xn[CPW]; u4_t pn; };
+        auto fetch = [&](int st, StepRegs& X) {
+          const int4 ci = chunk_info(st / ncb);
           const int cb0 = (st % ncb) * CB;
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
@@ -353,14 +399,24 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             const long col = col_index(c, n);
             const bool ok = c < ncols && n < nb && lane < ci.y;
             const uint32_t vx = ok ? (uint32_t)((col * pi.nmb + ci.x + lane) * esz) : 0x80000000u;
-            const uint32_t vm = ok ? (uint32_t)((col * pi.nmb + d.mrow) * esz) : 0x80000000u;
             if (a.m_c64) {
-              const uint2 x = buf_load<uint2>(mrs, vx, 0u), m = buf_load<uint2>(mrs, vm, 0u);
-              xn[j] = u4_t{x.x, x.y, 0u, 0u};
-              mn[j] = u4_t{m.x, m.y, 0u, 0u};
+              const uint2 x = buf_load<uint2>(mrs, vx, 0u);
+              X.xn[j] = u4_t{x.x, x.y, 0u, 0u};
             } else {
-              xn[j] = buf_load<u4_t>(mrs, vx, 0u);
-              mn[j] = buf_load<u4_t>(mrs, vm, 0u);
+              X.xn[j] = buf_load<u4_t>(mrs, vx, 0u);
+            }
+          }
+          {
+            const int c = cb0 + w + NW * (lane / MPC);
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = c < ncols && n < nb;
+            const uint32_t vm = ok ? (uint32_t)((col * pi.nmb + ci.w + lane % MPC) * esz) : 0x80000000u;
+            if (a.m_c64) {
+              const uint2 m = buf_load<uint2>(mrs, vm, 0u);
+              X.pn = u4_t{m.x, m.y, 0u, 0u};
+            } else {
+              X.pn = buf_load<u4_t>(mrs, vm, 0u);
             }
           }
         };
@@ -369,32 +425,32 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
           return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
         };
 
-        int4 ci = chunk_info(0), ci_next = ci;
+        __syncthreads();                              // earlier users of the LDS are done
+        for (int e = tid; e < nck; e += NT) s_chunk[e] = a.schunk[e];
+        load_coef(0);
+        store_coef();
+        __syncthreads();                              // chunk table and first coefficients visible
+        int4 ci = chunk_info(0);
         RowData rd, rd_next;
         load_rows(ci, rd);
         rd_next = rd;
-        load_coef(0);
-        __syncthreads();                              // earlier users of the LDS are done
-        store_coef();
         if (nck > 1) {
-          ci_next = chunk_info(1);
-          load_rows(ci_next, rd_next);
+          load_rows(chunk_info(1), rd_next);
           load_coef(1);
         }
-        fetch(0, ci, rd);
-        __syncthreads();                              // the first chunk's coefficients are visible
-        for (int st = 0; st < nsteps; ++st) {
+        StepRegs SA, SB;
+        fetch(0, SA);
+        if (nsteps > 1) fetch(1, SB);
+
+        auto step = [&](int st, StepRegs& X) {
           const int cbk = st % ncb, cb0 = cbk * CB;
-          double2 xm[CPW];
+          // this step's values to registers (rows) and to the wavefront's LDS slots
+          // (multipole rows), then the step two ahead into X
+          double2 xs[CPW];
 #pragma unroll
-          for (int j = 0; j < CPW; ++j) {             // this step's columns to the wavefront's slots
-            Ms[j * GR + lane] = to_d2(xn[j]);
-            xm[j] = to_d2(mn[j]);
-          }
-          if (st + 1 < nsteps) {
-            if (cbk + 1 < ncb) fetch(st + 1, ci, rd);
-            else fetch(st + 1, ci_next, rd_next);
-          }
+          for (int j = 0; j < CPW; ++j) xs[j] = to_d2(X.xn[j]);
+          Mp[lane] = to_d2(X.pn);
+          if (st + 2 < nsteps) fetch(st + 2, X);
           // LDS operations of one wavefront take effect in order: the slots just written
           // are read below by other lanes of the same wavefront
           __builtin_amdgcn_wave_barrier();
@@ -402,44 +458,28 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
           double2 y[CPW];
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
-            y[j].x = rd.lc.x * xm[j].x - rd.lc.y * xm[j].y;
-            y[j].y = rd.lc.x * xm[j].y + rd.lc.y * xm[j].x;
+            const double2 xm = Mp[j * MPC + rd.mloc];
+            y[j].x = rd.lc.x * xm.x - rd.lc.y * xm.y;
+            y[j].y = rd.lc.x * xm.y + rd.lc.y * xm.x;
           }
-          // Coefficients past a row's run are zero in the table and every row slot of the
-          // wavefront holds finite data (zero past the chunk), so all lanes run T terms
-          // without a branch; rows past the slot's end are clamped (their coefficient is
-          // zero). Two terms per pass: all LDS reads first, then the FMAs.
+          // Term t: coefficient L_c[i+t][i] (zero past the row's run, in the table) times
+          // the value of row r + t, which xs holds after t shifts (zero past the chunk:
+          // lanes past the chunk hold zeros and the last lane takes in zero). All lanes
+          // run the chunk's longest run and shift together.
+          auto term = [&](const double2 l) {
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+              y[j].x = fma(l.x, xs[j].x, y[j].x);
+              y[j].x = fma(l.y, xs[j].y, y[j].x);
+              y[j].y = fma(l.x, xs[j].y, y[j].y);
+              y[j].y = fma(-l.y, xs[j].x, y[j].y);
+              xs[j] = shift_down1(xs[j]);
+            }
+          };
           const int T = min(ci.z, MAXT);
-          for (int t = 0; t < T; t += 2) {            // row T < MAXT of the table is zero if T is odd
-            const double2 l0 = Cf[t * GR + lane], l1 = Cf[(t + 1) * GR + lane];
-            const int r0 = min(lane + t, GR - 1), r1 = min(lane + t + 1, GR - 1);
-            double2 x0[CPW], x1[CPW];
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-              x0[j] = Ms[j * GR + r0];
-              x1[j] = Ms[j * GR + r1];
-            }
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-              y[j].x = fma(l0.x, x0[j].x, y[j].x);
-              y[j].x = fma(l0.y, x0[j].y, y[j].x);
-              y[j].y = fma(l0.x, x0[j].y, y[j].y);
-              y[j].y = fma(-l0.y, x0[j].x, y[j].y);
-              y[j].x = fma(l1.x, x1[j].x, y[j].x);
-              y[j].x = fma(l1.y, x1[j].y, y[j].x);
-              y[j].y = fma(l1.x, x1[j].y, y[j].y);
-              y[j].y = fma(-l1.y, x1[j].x, y[j].y);
-            }
-          }
-          for (int t = MAXT; t < rd.len; ++t) {       // runs longer than the staged table
-            const double2 l = a.coef[rd.cs + t];
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-              const double2 x = Ms[j * GR + lane + t];
-              y[j].x += l.x * x.x + l.y * x.y;
-              y[j].y += l.x * x.y - l.y * x.x;
-            }
-          }
+          for (int t = 0; t < T; ++t) term(Cf[t * GR + lane]);
+          for (int t = MAXT; t < ci.z; ++t)           // runs longer than the staged table
+            term(t < rd.len ? a.coef[rd.cs + t] : make_double2(0.0, 0.0));
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
             const int c = cb0 + w + NW * j;
@@ -457,17 +497,20 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             const int ck = st / ncb;
             if (ck + 1 < nck) {
               store_coef();
-              ci = ci_next;
+              ci = chunk_info(ck + 1);
               rd = rd_next;
               if (ck + 2 < nck) {
-                ci_next = chunk_info(ck + 2);
-                load_rows(ci_next, rd_next);
+                load_rows(chunk_info(ck + 2), rd_next);
                 load_coef(ck + 2);
               }
             }
             contract_chunk(Ss, ng, std::integral_constant<int, GR>{}, LDR);
             __syncthreads();                          // the stage is free, the next coefficients visible
           }
+        };
+        for (int st = 0; st < nsteps; st += 2) {
+          step(st, SA);
+          if (st + 1 < nsteps) step(st + 1, SB);
         }
 #pragma unroll
         for (int b = 0; b < NCB; ++b)
@@ -662,7 +705,15 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         for (int ww = 0; ww < NW; ++ww) s += Dacc[(ww * NCC + c) * 2] + Dacc[(ww * NCC + c) * 2 + 1];
       a.dpart[(long)wi.slot * a.dstride + n] = s;
     }
+    if (tid0 == 0) s_item = claim;
     __syncthreads();
+    idx = -1;
+    if (home) {
+      const int j = qh0 + n_static(qi) + __builtin_amdgcn_readfirstlane(s_item);
+      if (j < qh1) idx = j;
+      else home = false;
+    }
+    __syncthreads();                              // s_item is read before the next item writes it
   }
 }
 
