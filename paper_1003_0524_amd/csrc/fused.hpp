@@ -133,7 +133,11 @@ struct FusedCfg {
   static constexpr int EPV = 16 / ESZ;                  // elements per 16 bytes
   static constexpr int LDK = KC + EPV;                  // A panel pitch (k contiguous per column)
   static constexpr int APL = NCC * LDK;
-  static constexpr int ABUF = NPL * APL;
+  // converted panel: pieces of Re, Im and, where it fits the LDS share, -Im (else the
+  // MFMA loop negates Im)
+  static constexpr bool NEGP = (size_t)(3 * NP * NCC * LDK * ESZ) + (NCC * KC * 16 + 4095) / 4096 * 4096 +
+                                   (size_t)NW * NCC * 2 * sizeof(double) + 16 * 64 + 32 <= (size_t)163840 / OCC;
+  static constexpr int ABUF = (NEGP ? 3 : 2) * NP * APL;
   static constexpr int LDR = GR + EPV;                  // Gram stage pitch (rows contiguous per column)
   static constexpr int YPL = NCC * LDR;
   static constexpr int YS = NPL * YPL;
@@ -152,13 +156,23 @@ struct FusedCfg {
   static constexpr int SP_CF = SP_MP + CB * MPC * 16;    // [MAXT][GR] coefficients,
   static constexpr int SP_ST = SP_CF + MAXT * GR * 16;   // then the Gram stage
   static constexpr int SPARSE_B = SP_ST + YS * ESZ;
-  static constexpr int RAW_B = (NCC * KC * 16 + 1023) / 1024 * 1024;   // raw panel in bytes (complex128 worst case)
+  static constexpr int RAW_B = (NCC * KC * 16 + 4095) / 4096 * 4096;   // raw panel (complex128 worst case), a whole
+                                                                       // number of 1 KB loads per wavefront
   static constexpr int PL_B = ABUF * ESZ;               // converted panel
-  static constexpr size_t DENSE_B = (size_t)(RAW_B + PL_B > YS * ESZ ? RAW_B + PL_B : YS * ESZ);
+  // two raw panel buffers where they fit the LDS share (with the other phases' needs)
+  static constexpr size_t FIXED_B = (size_t)NW * NCC * 2 * sizeof(double) + 16 * MAXCK + 16;
+  static constexpr size_t MAXSHARE = 163840 / OCC;
+  static constexpr size_t OTHER_B = (size_t)(SPARSE_B > YS * ESZ ? SPARSE_B : YS * ESZ);
+  static constexpr int NRAW = (2 * (size_t)RAW_B + PL_B <= MAXSHARE - FIXED_B - 16) ? 2 : 1;
+  static constexpr size_t DENSE_B = (size_t)(NRAW * RAW_B + PL_B > OTHER_B ? NRAW * RAW_B + PL_B : OTHER_B);
   static constexpr size_t MAIN_RAW = DENSE_B > (size_t)SPARSE_B ? DENSE_B : (size_t)SPARSE_B;
   static constexpr size_t MAIN_B = (MAIN_RAW + 15) / 16 * 16;
   // s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: expcnt and lgkmcnt at their maxima)
   static constexpr int WAIT_VM0 = 0x0F70;
+  // vmcnt(NIW): all but the last NIW vector-memory instructions of the wavefront
+  static constexpr int NIW_C = RAW_B / 1024 / NW;
+  static constexpr int WAIT_VM_NIW = (NIW_C & 0xF) | ((NIW_C >> 4) << 14) | 0x0F70;
+  static_assert(NIW_C < 64, "vmcnt is a 6-bit count");
   static constexpr size_t DACC_B = (size_t)NW * NCC * 2 * sizeof(double);
   static constexpr size_t LDS_B = MAIN_B + DACC_B;
   static_assert(MODE != M_F64, "the fused kernel serves the reduced-precision modes");
@@ -185,8 +199,8 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
   __shared__ __align__(16) unsigned char smem[C::LDS_B];
   __shared__ int s_item;
   __shared__ int4 s_chunk[C::MAXCK];
-  unsigned char* Raw = smem;                   // [NCC][KC] complex, as loaded   (K loop)
-  lds_t* Apl = (lds_t*)(smem + C::RAW_B);      // [NPL][NCC][LDK] pieces          (K loop)
+  unsigned char* Raw = smem;                   // NRAW x [NCC][KC] complex, as loaded (K loop)
+  lds_t* Apl = (lds_t*)(smem + C::NRAW * C::RAW_B);   // [3 NP][NCC][LDK] pieces (K loop)
   lds_t* Ys = (lds_t*)smem;                    // [NPL][NCC][LDR] (Gram stage; aliases the K panels)
   double* Dacc = (double*)(smem + C::MAIN_B);  // [NW][NCC][2]
 
@@ -537,7 +551,11 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 
         // ---- K panels of A_d: global -> LDS directly (buffer_load ... lds), then
         // converted in LDS into the mode's pieces. One wave instruction moves 1 KB:
-        // two columns of KC complex128 (or four of complex64), lanes in order.
+        // two columns of KC complex128 (or four of complex64), lanes in order. With
+        // NRAW = 2 raw buffers two panels are in flight: the factor pieces of the next
+        // panel are requested before the raw panel two ahead, so that waiting for them
+        // (vmcnt counts in order) leaves that panel in flight; every wavefront issues the
+        // same NIW raw instructions per panel (past the data's end they read zero).
         constexpr int NI = C::RAW_B / 1024;                // instructions per panel
         constexpr int NIW = (NI + NW - 1) / NW;            // per wavefront
         uint32_t r_off[NIW];
@@ -559,35 +577,33 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             r_off[t] = ok ? (uint32_t)((col * pi.nmb + a.n_s + k) * esz) : 0x80000000u;
           }
         }
-        const int ni = (NCC * KC * esz + 1023) / 1024;     // instructions this dtype needs
-        auto issue_raw = [&](int kc) {
+        auto issue_raw = [&](int kc, int buf) {
 #pragma unroll
-          for (int t = 0; t < NIW; ++t) {
-            const int idx = w + NW * t;
-            if (idx < ni)
-              lds_load16(mrs, Raw + idx * 1024, r_off[t], (uint32_t)(kc * esz));
-          }
+          for (int t = 0; t < NIW; ++t)
+            lds_load16(mrs, Raw + buf * C::RAW_B + (w + NW * t) * 1024, r_off[t], (uint32_t)(kc * esz));
         };
         // raw -> pieces: consecutive lanes take consecutive elements (a wavefront reads
         // 1 KB of contiguous LDS per instruction, free of bank conflicts) and write
         // their pieces as single elements of the planes
-        auto convert = [&](int kc) {
+        auto convert = [&](int kc, int buf) {
+          const unsigned char* Rw = Raw + buf * C::RAW_B;
           for (int e = tid; e < NCC * KC; e += NT) {
             const int c = e / KC, k = e % KC;
             double re = 0.0, im = 0.0;
             if (kc + k < nd) {
               if (a.m_c64) {
-                const float2 v = *(const float2*)(Raw + e * 8);
+                const float2 v = *(const float2*)(Rw + e * 8);
                 re = (double)v.x;
                 im = (double)v.y;
               } else {
-                const double2 v = *(const double2*)(Raw + e * 16);
+                const double2 v = *(const double2*)(Rw + e * 16);
                 re = v.x;
                 im = v.y;
               }
             }
             put_real<MODE>(Apl + c * LDK + k, APL, re);
             put_real<MODE>(Apl + NP * APL + c * LDK + k, APL, im);
+            if constexpr (C::NEGP) put_real<MODE>(Apl + 2 * NP * APL + c * LDK + k, APL, -im);
           }
         };
 
@@ -609,44 +625,61 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
                                                    (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ));
           }
         };
-        issue_raw(kc0);
+        const int np = (kend - kc0) / KC;                 // K panels of this row block
+        issue_raw(kc0, 0);
         load_u(kc0, ucur);
-        __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
+        if (C::NRAW == 2 && np > 1) {
+          issue_raw(kc0 + KC, 1);
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM_NIW);     // panel 0 and its factor have landed
+        } else {
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
+        }
         __syncthreads();
-        for (int kc = kc0; kc < kend; kc += KC) {
-          convert(kc);
-          __syncthreads();                            // pieces ready, raw panel free
-          const bool more = kc + KC < kend;
-          if (more) {                                 // next panel and its factor pieces in flight
-            issue_raw(kc + KC);
-            load_u(kc + KC, unext);
+        for (int pp = 0; pp < np; ++pp) {
+          const int kc = kc0 + pp * KC, buf = C::NRAW == 2 ? (pp & 1) : 0;
+          convert(kc, buf);
+          __syncthreads();                            // pieces ready, raw buffer free
+          const bool more = pp + 1 < np;
+          if (more) load_u(kc + KC, unext);           // next panel's factor pieces in flight
+          if (C::NRAW == 2) {
+            if (pp + 2 < np) issue_raw(kc + 2 * KC, buf);
+          } else if (more) {
+            issue_raw(kc + KC, 0);
           }
+          // [Yr|Yi] += Br [Ar|Ai] + Bi [-Ai|Ar]: the B operand of step (h, j) is plane
+          // part (h = 0) or, for h = 1, -Im (part 0) or Re (part 1); one step ahead
 #pragma unroll
           for (int ks = 0; ks < KC / KS; ++ks) {
             const int kofs = ks * KS + KPL * lq;
+            auto bload = [&](int hj, op_t (&b)[NP]) {
+              const int h = hj / NCT, j = hj % NCT;
+              const int pl = C::NEGP ? (h == 0 ? part : 2 * (1 - part)) : (part ^ h);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int bpart = part ^ h;
-              const bool neg = (h == 1) && (part == 0);
-#pragma unroll
-              for (int j = 0; j < NCT; ++j) {
-                op_t bop[NP];
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                  bop[p] = lds_operand<MODE>(Apl + (bpart * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
-                  if (neg) bop[p] = negate(bop[p]);
-                }
-                // products outer, tiles inner: consecutive MFMAs use different accumulators
-#pragma unroll
-                for (int pr = 0; pr < C::T::NPROD; ++pr)
-#pragma unroll
-                  for (int ii = 0; ii < RTW; ++ii)
-                    acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
-                                      bop[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
+              for (int p = 0; p < NP; ++p) {
+                b[p] = lds_operand<MODE>(Apl + (pl * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
+                if (!C::NEGP && h == 1 && part == 0) b[p] = negate(b[p]);
               }
+            };
+            op_t bA[NP], bB[NP];
+            bload(0, bA);
+#pragma unroll
+            for (int hj = 0; hj < 2 * NCT; ++hj) {
+              const int h = hj / NCT, j = hj % NCT;
+              op_t (&bc)[NP] = (hj & 1) ? bB : bA;
+              op_t (&bn)[NP] = (hj & 1) ? bA : bB;
+              if (hj + 1 < 2 * NCT) bload(hj + 1, bn);
+              // products outer, tiles inner: consecutive MFMAs use different accumulators
+#pragma unroll
+              for (int pr = 0; pr < C::T::NPROD; ++pr)
+#pragma unroll
+                for (int ii = 0; ii < RTW; ++ii)
+                  acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
+                                    bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
             }
           }
-          __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);    // this wave's part of the next panel has landed
+          // this wave's part of the next panel (and its factor pieces) has landed
+          if (C::NRAW == 2 && pp + 2 < np) __builtin_amdgcn_s_waitcnt(C::WAIT_VM_NIW);
+          else __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
           __syncthreads();
           if (more) {
 #pragma unroll
