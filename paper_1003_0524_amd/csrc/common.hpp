@@ -96,6 +96,26 @@ __device__ __forceinline__ void put_real(typename Traits<MODE>::lds_t* dst, long
     for (int p = 0; p < Traits<MODE>::NPIECE; ++p) dst[p * ps] = h[p];
   }
 }
+// Re, Im and -Im into their planes (-Im: the pieces of Im with the sign flipped, exact).
+template <int MODE>
+__device__ __forceinline__ void put_cplx3(typename Traits<MODE>::lds_t* dst, long ps, double re, double im) {
+  constexpr int NP = Traits<MODE>::NPIECE;
+  if constexpr (MODE == M_F64) {
+    dst[0] = re; dst[ps] = im; dst[2 * ps] = -im;
+  } else if constexpr (MODE == M_F32) {
+    dst[0] = (float)re; dst[ps] = (float)im; dst[2 * ps] = -(float)im;
+  } else {
+    uint16_t hr[NP], hi[NP];
+    split_d<NP>(re, hr);
+    split_d<NP>(im, hi);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      dst[p * ps] = hr[p];
+      dst[(NP + p) * ps] = hi[p];
+      dst[(2 * NP + p) * ps] = (uint16_t)(hi[p] ^ 0x8000u);
+    }
+  }
+}
 template <int MODE>
 __device__ __forceinline__ void put_realf(typename Traits<MODE>::lds_t* dst, long ps, float x) {
   if constexpr (MODE == M_F64) {

@@ -601,9 +601,12 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
                 im = v.y;
               }
             }
-            put_real<MODE>(Apl + c * LDK + k, APL, re);
-            put_real<MODE>(Apl + NP * APL + c * LDK + k, APL, im);
-            if constexpr (C::NEGP) put_real<MODE>(Apl + 2 * NP * APL + c * LDK + k, APL, -im);
+            if constexpr (C::NEGP) {
+              put_cplx3<MODE>(Apl + c * LDK + k, APL, re, im);
+            } else {
+              put_real<MODE>(Apl + c * LDK + k, APL, re);
+              put_real<MODE>(Apl + NP * APL + c * LDK + k, APL, im);
+            }
           }
         };
 
