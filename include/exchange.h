@@ -151,6 +151,21 @@ exc_status exchange_matrix_all(exc_ctx *ctx, const void *const *M_k, int32_t dty
 exc_status exchange_energy(exc_ctx *ctx, const double *w_k, const void *const *rho_k,
                            double *E_out);
 
+/*
+ * exchange_energy_device -- the same E_x as exchange_energy, left in device memory
+ * without synchronising: for loops that keep results on the GPU.
+ *   w_k, rho_k : as for exchange_energy (w_k host, rho_k device pointers); both
+ *                arrays are copied before the call returns
+ *   E_dev      : device pointer to one double, written on `stream` after the
+ *                last exchange_matrix[_all] work (NULL stream: that work's stream;
+ *                another stream is made to wait for it)
+ * The sum over k is taken on the device in the order of k. Errors of the
+ * enqueued kernels surface on the next synchronising call. EXC_ESTATE if some
+ * V(k) was never computed.
+ */
+exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *const *rho_k,
+                                  double *E_dev, void *stream);
+
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx == NULL,
  * the message of the last failed exchange_init on this thread. */
 const char *exchange_last_error(const exc_ctx *ctx);

@@ -30,6 +30,7 @@ DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
+                    "exchange_energy_device",
                     "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
                     "exchange_nn_init", "exchange_nn_params", "exchange_nn_train", "exchange_nn_grad",
                     "exchange_nn_predict", "exchange_nn_features", "exchange_eigh", "exchange_nn_project",
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp),
                                     ctypes.POINTER(ctypes.c_double)]
     lib.exchange_energy.restype = i32
+    lib.exchange_energy_device.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp), vp, vp]
+    lib.exchange_energy_device.restype = i32
     lib.exchange_last_error.argtypes = [vp]
     lib.exchange_last_error.restype = ctypes.c_char_p
     lib.exchange_destroy.argtypes = [vp]
@@ -230,6 +233,21 @@ class Exchange:
         e = ctypes.c_double()
         self._check(self.lib.exchange_energy(self.ctx, wk, rp, ctypes.byref(e)))
         return e.value
+
+    def energy_device(self, out, w_k: Optional[Sequence[float]] = None, rho: Optional[Sequence] = None,
+                      stream=None) -> None:
+        """E_x into out (a one-element float64 CUDA tensor) without synchronising."""
+        if str(out.dtype) != "torch.float64" or not out.is_cuda or out.numel() < 1:
+            raise ValueError("out must be a float64 CUDA tensor with at least one element")
+        wk = None
+        if w_k is not None:
+            wk_arr = np.ascontiguousarray(np.asarray(w_k, dtype=np.float64))
+            wk = wk_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rp = None
+        if rho is not None:
+            rp = (ctypes.c_void_p * self.n_k)(*[r.data_ptr() for r in rho])
+        st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        self._check(self.lib.exchange_energy_device(self.ctx, wk, rp, ctypes.c_void_p(out.data_ptr()), st))
 
     def query(self, what: int) -> float:
         v = ctypes.c_double()

@@ -243,6 +243,21 @@ __global__ __launch_bounds__(256) void energy_kernel(const double2* vres, const 
   if (threadIdx.x == 0) out[k] = red[0];
 }
 
+// E_x = 1/2 sum_k w_k e_k on the device, in the fixed order of k (one workgroup).
+__global__ __launch_bounds__(256) void energy_sum_kernel(const double* e_k, const double* w_k, int32_t n_k,
+                                                         double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n_k; k += 256) s += (w_k ? w_k[k] : 1.0 / n_k) * e_k[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 0.5 * red[0];
+}
+
 // ---------------------------------------------------------------------------
 // Per-channel factorisation (HERK form, q independent): D_c = L_c L_c^H,
 // l_c = L_c^{-1} C_c and the Schur update ||l_c||^2 of the channel's multipole

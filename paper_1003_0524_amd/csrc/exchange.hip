@@ -191,6 +191,8 @@ struct exc_ctx {
   void* d_mstage = nullptr;
   size_t mstage_bytes = 0;
   double* d_eout = nullptr;
+  double* d_ewk = nullptr;            // [n_k] weights of exchange_energy_device
+  void** d_erho = nullptr;            // [n_k] rho pointers of exchange_energy_device
   hipStream_t last_stream = nullptr;
   // accounting
   double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
@@ -275,7 +277,7 @@ void release(exc_ctx* c) {
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
                   c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
-                  c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout};
+                  c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
@@ -1139,6 +1141,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   IHIP(hipMemset(c->d_vtab, 0, c->n_k * sizeof(void*)));
   ITRY(dalloc(c, &c->d_counter, (size_t)NQ_MAX));
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
+  ITRY(dalloc(c, &c->d_ewk, (size_t)c->n_k));
+  ITRY(dalloc(c, &c->d_erho, (size_t)c->n_k));
 
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
@@ -1278,6 +1282,28 @@ exc_status exchange_energy(exc_ctx* c, const double* w_k, const void* const* rho
   double s = 0.0;
   for (int k = 0; k < c->n_k; ++k) s += (w_k ? w_k[k] : 1.0 / c->n_k) * e[k];
   *E_out = 0.5 * s;
+  return EXC_OK;
+}
+
+exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* const* rho_k, double* E_dev,
+                                  void* stream) {
+  TRY(check_ctx(c));
+  if (!E_dev) return fail(c, EXC_EINVAL, "E_dev is NULL");
+  for (int k = 0; k < c->n_k; ++k)
+    if (!c->v_valid[k]) return fail(c, EXC_ESTATE, "V(k=%d) has not been computed", k);
+  hipStream_t st = stream ? (hipStream_t)stream : c->last_stream;
+  if (st != c->last_stream) {                     // after the last V(k) on its stream
+    HIPCHK(c, hipEventRecord(c->ev_out, c->last_stream));
+    HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
+  }
+  // the host arrays are copied before this call returns (pageable source)
+  if (w_k) HIPCHK(c, hipMemcpyAsync(c->d_ewk, w_k, c->n_k * sizeof(double), hipMemcpyHostToDevice, st));
+  if (rho_k) HIPCHK(c, hipMemcpyAsync(c->d_erho, rho_k, c->n_k * sizeof(void*), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
+                     rho_k ? (const void* const*)c->d_erho : nullptr, c->n_occ, c->d_eout);
+  hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, st, c->d_eout, w_k ? c->d_ewk : nullptr,
+                     c->n_k, E_dev);
+  HIPCHK(c, hipGetLastError());
   return EXC_OK;
 }
 

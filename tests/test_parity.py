@@ -243,3 +243,24 @@ def test_autotuner_choice_and_cache(tmp_path, monkeypatch):
     assert ids[0] == ids[1]
     assert ids[0] in _fused_ids("bf16x3", 1) + [31, 30]
     assert cache.read_text().count("\t") == 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_energy_device_matches_host_energy(precision):
+    """exchange_energy_device leaves the same E_x in device memory, with and without
+    explicit weights and density matrices."""
+    name = "small"
+    cfg, E, D, C, v = _case(name)
+    _say(f"[parity] energy on the device {name} {precision}")
+    ex = _ex(name, precision, "herk", True)
+    ex.matrix_all([_m(cfg, k) for k in range(cfg.n_k)])
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ex.energy_device(out)
+    w = np.linspace(0.5, 1.5, cfg.n_k)
+    rho = [torch.from_numpy(vx.default_rho(nb, cfg.n_occ).T.ravel().copy()).cuda() for nb in cfg.n_bands]
+    ex.energy_device(out[1:], w_k=w, rho=rho)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert got[0] == pytest.approx(ex.energy(), rel=1e-14)
+    assert got[1] == pytest.approx(ex.energy(w_k=w), rel=1e-14)
+    ex.close()
