@@ -5,9 +5,11 @@ precision should show against the float64 oracle, so that a GPU parity test can
 demand "within a small factor of the predicted error" instead of an arbitrary
 tolerance. Modelled: rounding of the operands to the mode's storage, products
 of split pieces (exact in binary32, as on the matrix cores), accumulation in
-binary32 (NumPy float32 / complex64 GEMMs; the summation order differs from the
-hardware's but the error magnitude does not), rounding of Y = L^H A to binary32,
-and the float64 diagonal and q sum.
+binary32 sequentially over the contraction index in chunks of one matrix-core
+instruction's K (4 for fp32, 32 for the bf16 modes), the real and imaginary
+products of a chunk added in turn, as the kernels accumulate (a single blocked
+float32 GEMM would understate the growth of the rounding error with K),
+rounding of Y = L^H A to binary32, and the float64 diagonal and q sum.
 
 Modes
   fp32   -- operands rounded to IEEE binary32 (round to nearest even).
@@ -52,33 +54,6 @@ def split3_bf16(x: np.ndarray):
     return hi, mid, lo
 
 
-def _prod_bf16x6(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Complex a @ b with each real product done with the six leading split terms."""
-    def mm(x, y):
-        xh, xm, xl = split3_bf16(x)
-        yh, ym, yl = split3_bf16(y)
-        return xh @ yh + xh @ ym + xm @ yh + xh @ yl + xm @ ym + xl @ yh
-
-    re = mm(a.real, b.real) - mm(a.imag, b.imag)
-    im = mm(a.real, b.imag) + mm(a.imag, b.real)
-    return re + 1j * im
-
-
-def _prod_bf16x3(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Complex a @ b with each real product done as hi*hi + hi*lo + lo*hi."""
-    ar_h, ar_l = split_bf16(a.real)
-    ai_h, ai_l = split_bf16(a.imag)
-    br_h, br_l = split_bf16(b.real)
-    bi_h, bi_l = split_bf16(b.imag)
-
-    def mm(xh, xl, yh, yl):
-        return xh @ yh + xh @ yl + xl @ yh
-
-    re = mm(ar_h, ar_l, br_h, br_l) - mm(ai_h, ai_l, bi_h, bi_l)
-    im = mm(ar_h, ar_l, bi_h, bi_l) + mm(ai_h, ai_l, br_h, br_l)
-    return re + 1j * im
-
-
 def _pieces(x: np.ndarray, n: int):
     return split_bf16(x) if n == 2 else split3_bf16(x)
 
@@ -86,21 +61,37 @@ def _pieces(x: np.ndarray, n: int):
 _PAIRS = {2: ((0, 0), (0, 1), (1, 0)), 3: ((0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0))}
 
 
-def _real_split_mm32(x: np.ndarray, y: np.ndarray, n: int) -> np.ndarray:
-    """sum over leading piece pairs of x_i @ y_j, each GEMM accumulated in float32."""
-    px = [p.astype(np.float32) for p in _pieces(x, n)]
-    py = [p.astype(np.float32) for p in _pieces(y, n)]
-    acc = np.zeros((x.shape[0], y.shape[1]), dtype=np.float32)
-    for i, j in _PAIRS[n]:
-        acc = acc + px[i] @ py[j]
-    return acc.astype(np.float64)
+def _cmm32_seq(a: np.ndarray, b: np.ndarray, n: int, chunk: int) -> np.ndarray:
+    """Complex a @ b in binary32: K in chunks, each chunk's real products (the sum of
+    the leading piece pairs for n = 2, 3; the plain product for n = 1) added to the
+    real accumulator (ar br, then -ai bi) and the imaginary one (ar bi, then ai br)."""
+    def parts(x):
+        if n == 1:
+            return [x.astype(np.float32)]
+        return [p.astype(np.float32) for p in _pieces(x, n)]
+    pairs = ((0, 0),) if n == 1 else _PAIRS[n]
+    ar, ai = parts(a.real), parts(-a.imag)
+    ai_pos = parts(a.imag)
+    br, bi = parts(b.real), parts(b.imag)
+    acc_r = np.zeros((a.shape[0], b.shape[1]), dtype=np.float32)
+    acc_i = np.zeros_like(acc_r)
+
+    def chunk_mm(x, y, k0, k1):
+        t = np.zeros_like(acc_r)
+        for i, j in pairs:
+            t = t + x[i][:, k0:k1] @ y[j][k0:k1, :]
+        return t
+
+    for k0 in range(0, a.shape[1], chunk):
+        k1 = min(k0 + chunk, a.shape[1])
+        acc_r = acc_r + chunk_mm(ar, br, k0, k1)
+        acc_r = acc_r + chunk_mm(ai, bi, k0, k1)
+        acc_i = acc_i + chunk_mm(ar, bi, k0, k1)
+        acc_i = acc_i + chunk_mm(ai_pos, br, k0, k1)
+    return acc_r.astype(np.float64) + 1j * acc_i.astype(np.float64)
 
 
-def _prod_split32(a: np.ndarray, b: np.ndarray, n: int) -> np.ndarray:
-    """Complex a @ b as four real split products with float32 accumulation."""
-    re = _real_split_mm32(a.real, b.real, n) - _real_split_mm32(a.imag, b.imag, n)
-    im = _real_split_mm32(a.real, b.imag, n) + _real_split_mm32(a.imag, b.real, n)
-    return re + 1j * im
+_MODE_PIECES = {"fp32": (1, 4), "bf16x3": (2, 32), "bf16x6": (3, 32)}
 
 
 def vx_k_emulated(m_blocks, L_list, w_q, mode: str) -> np.ndarray:
@@ -112,24 +103,24 @@ def vx_k_emulated(m_blocks, L_list, w_q, mode: str) -> np.ndarray:
     V = np.zeros((nb, nb), dtype=np.complex128)
     for q, mq in enumerate(m_blocks):
         Uh = L_list[q].conj().T
+        # Y = L^H A for every n'' at once: the columns of a product are independent, so
+        # one product over [A_0 | A_1 | ...] gives each n'' its own Y
+        A = np.concatenate([mq[npp].T for npp in range(mq.shape[0])], axis=1)
+        if mode == "fp64":
+            Y = Uh @ A
+        elif mode in _MODE_PIECES:
+            n, ch = _MODE_PIECES[mode]
+            Y = round_fp32(_cmm32_seq(Uh, A, n, ch))
+        else:
+            raise ValueError(mode)
         for npp in range(mq.shape[0]):
-            A = mq[npp].T
+            Yn = Y[:, npp * nb:(npp + 1) * nb]
             if mode == "fp64":
-                Y = Uh @ A
-                P = Y.conj().T @ Y
-            elif mode == "fp32":
-                Y = (Uh.astype(np.complex64) @ A.astype(np.complex64)).astype(np.complex128)
-                Y32 = Y.astype(np.complex64)
-                P = (Y32.conj().T @ Y32).astype(np.complex128)
-            elif mode == "bf16x3":
-                Y = round_fp32(_prod_split32(Uh, A, 2))
-                P = _prod_split32(Y.conj().T, Y, 2)
-            elif mode == "bf16x6":
-                Y = round_fp32(_prod_split32(Uh, A, 3))
-                P = _prod_split32(Y.conj().T, Y, 3)
+                P = Yn.conj().T @ Yn
             else:
-                raise ValueError(mode)
-            d = np.sum(np.abs(Y) ** 2, axis=0)      # diagonal in float64 from the mode's Y
+                n, ch = _MODE_PIECES[mode]
+                P = _cmm32_seq(Yn.conj().T, Yn, n, ch)
+            d = np.sum(np.abs(Yn) ** 2, axis=0)     # diagonal in float64 from the mode's Y
             P[np.arange(nb), np.arange(nb)] = d
             V -= w_q[q] * P
     return V

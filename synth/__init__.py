@@ -118,6 +118,10 @@ class Config:
     w_k: Optional[np.ndarray] = None   # default 1/n_k
     m_dtype: str = "c128"          # dtype the caller hands to the library
     description: str = ""
+    # a slice of a larger workload: the parent's q index of each q (random streams and
+    # phases follow it) and the parent's largest dense block (size of the shared H0)
+    q_ids: Optional[List[int]] = None
+    h0_n: Optional[int] = None
 
     # -- derived sizes -------------------------------------------------------
     @property
@@ -275,6 +279,22 @@ def pw_set(cfg: Config, q: int) -> np.ndarray:
         nmax *= 2
 
 
+def q_slice(cfg: Config, q_ids: Sequence[int], n_k: int = 1) -> Config:
+    """The workload restricted to the q points q_ids and the first n_k irreducible k,
+    with the parent's per-pair inputs: M(k, q) and E(q) of a slice equal those of the
+    parent at the same (k, q). The q weights are 1/len(q_ids)."""
+    q_ids = [int(q) for q in q_ids]
+    return dataclasses.replace(
+        cfg, name=f"{cfg.name}[q={','.join(map(str, q_ids))};k<{n_k}]", q_frac=cfg.q_frac[q_ids],
+        n_k=n_k, n_bands=list(cfg.n_bands[:n_k]), n_pw=[cfg.n_pw[q] for q in q_ids],
+        w_q=None, w_k=None, q_ids=[_qid(cfg, q) for q in q_ids],
+        h0_n=cfg.h0_n or max(cfg.n_d(q) for q in range(cfg.n_q)))
+
+
+def _qid(cfg: Config, q: int) -> int:
+    return cfg.q_ids[q] if cfg.q_ids else q
+
+
 def _shared_hermitian(cfg: Config, n: int) -> np.ndarray:
     """Seeded random Hermitian matrix with spectral norm exactly 1."""
     rng = np.random.default_rng([cfg.seed, cfg.tag, 31337])
@@ -318,14 +338,14 @@ def coulomb_blocks(cfg: Config):
         cv *= math.sqrt(lmin * m_c[c] / 8.0) / np.linalg.norm(cv)
         D.append(d)
         C.append(cv)
-    nd_max = max(cfg.n_d(q) for q in range(cfg.n_q))
+    nd_max = cfg.h0_n or max(cfg.n_d(q) for q in range(cfg.n_q))
     h0 = _shared_hermitian(cfg, nd_max)
     E = []
     for q in range(cfg.n_q):
         nd = cfg.n_d(q)
         g = pw_set(cfg, q)
         s = np.concatenate([m_c, 4.0 * math.pi / g ** 2])
-        ph = np.exp(2j * math.pi * np.random.default_rng([cfg.seed, cfg.tag, 77, q]).uniform(size=nd))
+        ph = np.exp(2j * math.pi * np.random.default_rng([cfg.seed, cfg.tag, 77, _qid(cfg, q)]).uniform(size=nd))
         h = (ph[:, None] * h0[:nd, :nd]) * ph.conj()[None, :]
         rs = np.sqrt(s)
         e = rs[:, None] * (np.eye(nd) + 0.5 * h) * rs[None, :]
@@ -344,7 +364,7 @@ def m_block(cfg: Config, k: int, q: int, dtype=np.complex128) -> np.ndarray:
     (k, q) SplitMix64 substream.
     """
     nb, nmb, nocc = cfg.n_bands[k], cfg.n_mb(q), cfg.n_occ
-    s = stream_seed(cfg.seed, cfg.tag, k, q)
+    s = stream_seed(cfg.seed, cfg.tag, k, _qid(cfg, q))
     n = nocc * nb * nmb
     z0, z1 = normal_pairs(s, 0, n)
     decay = np.exp(-0.1 * np.arange(nmb) / nmb)
