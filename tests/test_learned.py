@@ -245,3 +245,36 @@ def test_outer_loop_falls_back_when_threshold_unreachable():
     first = [r for r in recs if r.judged][0]
     assert first.accepted is False
     assert all(r.exact for r in recs if r.t >= first.t)
+
+
+def test_outer_loop_at_zno_like_shapes():
+    """The outer-iteration scheme at the ZnO-like workload's per-pair shapes: 60 bands,
+    18 occupied, N_MB 827-1399 (its Gamma, smallest and largest mixed basis) on the
+    first 4 irreducible k, 30 iterations, 10 training pairs, judged every 5th. The
+    network must beat the stale V^x at every judgement and be accepted at 1e-4 Ha."""
+    import synth
+    import synth.scf as scf
+    from paper_1003_0524_amd import learned
+    import paper_1003_0524_amd as lib
+    full = synth.make_config("c3")
+    nmb = np.array([full.n_mb(q) for q in range(full.n_q)])
+    cfg = synth.q_slice(full, [0, int(nmb.argmin()), int(nmb.argmax())], n_k=4)
+    print(f"[learned] {cfg.name}: n_b={cfg.n_bands[0]} n_occ={cfg.n_occ} N_MB={[cfg.n_mb(q) for q in range(cfg.n_q)]}",
+          flush=True)
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision="fp64", form="herk", batched=True)
+    try:
+        feed = scf.make_feed(cfg, 30, torch.device("cuda"))
+        xp = learned.Extrapolator(ex, epochs=1500, epochs_ft=300)
+        recs, xp, V = learned.run_outer(ex, feed, n_iter=30, tau=1e-4, xp=xp)
+    finally:
+        ex.close()
+    for r in recs:
+        print(r, flush=True)
+    judged = [r for r in recs if r.judged]
+    assert [r.t for r in judged] == [15, 20, 25, 30]
+    for r in judged:
+        assert r.err_pred < r.err_stale, r
+    assert np.mean([r.err_pred / r.err_stale for r in judged]) < 0.5
+    assert all(r.accepted for r in judged)
