@@ -176,19 +176,35 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const int iri = gidx<ACC64>(tp, c, c2 + 8), iir = gidx<ACC64>(tp, c + 8, c2);
   double re = 0.0, im = 0.0, dg = 0.0;
   const bool diag = (n == n2) && n < nb;
-  for (int s = a.slot_begin[k] + sg; s < a.slot_begin[k + 1]; s += 4) {
-    const double wq = a.slot_w[s];
-    double grr, gii, gri, gir;
-    if (ACC64) {
-      const double* g = (const double*)a.gpart + (long)s * a.gstride;
-      grr = g[irr]; gii = g[iii]; gri = g[iri]; gir = g[iir];
-    } else {
-      const float* g = (const float*)a.gpart + (long)s * a.gstride;
-      grr = g[irr]; gii = g[iii]; gri = g[iri]; gir = g[iir];
+  // slots sg, sg + 4, ... in order; UN slots' loads are issued before their adds
+  constexpr int UN = 4;
+  const int s0 = a.slot_begin[k] + sg, s1 = a.slot_begin[k + 1];
+  for (int sb = s0; sb < s1; sb += 4 * UN) {
+    double wq[UN], grr[UN], gii[UN], gri[UN], gir[UN], dd[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int s = sb + 4 * u;
+      wq[u] = grr[u] = gii[u] = gri[u] = gir[u] = dd[u] = 0.0;
+      if (s < s1) {
+        wq[u] = a.slot_w[s];
+        if (ACC64) {
+          const double* g = (const double*)a.gpart + (long)s * a.gstride;
+          grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
+        } else {
+          const float* g = (const float*)a.gpart + (long)s * a.gstride;
+          grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
+        }
+        if (diag && a.use_d64) dd[u] = a.dpart[(long)s * a.dstride + n];
+      }
     }
-    re += wq * (grr + gii);
-    im += wq * (gri - gir);
-    if (diag && a.use_d64) dg += wq * a.dpart[(long)s * a.dstride + n];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      if (sb + 4 * u < s1) {
+        re += wq[u] * (grr[u] + gii[u]);
+        im += wq[u] * (gri[u] - gir[u]);
+        if (diag && a.use_d64) dg += wq[u] * dd[u];
+      }
+    }
   }
   red[sg][e][0] = re;
   red[sg][e][1] = im;
@@ -241,6 +257,27 @@ __global__ __launch_bounds__(256) void energy_kernel(const double2* vres, const 
     __syncthreads();
   }
   if (threadIdx.x == 0) out[k] = red[0];
+}
+
+// E_x for rho_k = diag(2 for n < n_occ): 1/2 sum_k w_k sum_{n < n_occ} 2 Re V_k[n][n], in one
+// workgroup: thread t takes the (k, n) pairs t, t + 256, ... and the partial sums are
+// combined by a fixed tree.
+__global__ __launch_bounds__(256) void energy_diag_kernel(const double2* vres, const int64_t* v_off,
+                                                          const int32_t* k_nb, int32_t n_k, int32_t n_occ,
+                                                          const double* w_k, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_k * n_occ; i += 256) {
+    const int k = i / n_occ, n = i - k * n_occ, nb = k_nb[k];
+    if (n < nb) s += (w_k ? w_k[k] : 1.0 / n_k) * 2.0 * vres[v_off[k] + n + (long)n * nb].x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 0.5 * red[0];
 }
 
 // E_x = 1/2 sum_k w_k e_k on the device, in the fixed order of k (one workgroup).

@@ -675,11 +675,11 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
     if (r == hipSuccess) { c->tnode[i] = n2; last = n2; }
     return r;
   };
-  e = add_ev(0);
   SparseArgs sa;
   KLaunch L;
   if (e == hipSuccess && cfg_sparse(c, dtype, 0, (int)c->pairs.size(), sa, L)) {
-    e = add_node(g, L, &last, &node);
+    e = add_ev(0);                      // (the fused path has no block-sparse kernel to time)
+    if (e == hipSuccess) e = add_node(g, L, &last, &node);
     last = node;
   }
   e = add_ev(1);
@@ -1238,20 +1238,15 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
       if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
       TRY(build_batched_graph(c, dtype));
     }
-    if (c->t_slots > 0 && c->tnode[0] && c->tnode[1] && c->tnode[2]) {
+    if (c->t_slots > 0 && c->tnode[1] && c->tnode[2]) {
       // rotate the event triple of this replay
       const int s = c->t_next;
       for (int i = 0; i < 3; ++i)
-        HIPCHK(c, hipGraphExecEventRecordNodeSetEvent(c->gexec, c->tnode[i], c->tpool[3 * s + i]));
+        if (c->tnode[i]) HIPCHK(c, hipGraphExecEventRecordNodeSetEvent(c->gexec, c->tnode[i], c->tpool[3 * s + i]));
       c->t_next = (c->t_next + 1) % c->t_slots;
       c->t_count = std::min(c->t_count + 1, c->t_slots);
     }
-    // order: caller's stream -> graph on the internal stream -> caller's stream
-    HIPCHK(c, hipEventRecord(c->ev_in, st));
-    HIPCHK(c, hipStreamWaitEvent(c->own, c->ev_in, 0));
-    HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
-    HIPCHK(c, hipEventRecord(c->ev_out, c->own));
-    HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
+    HIPCHK(c, hipGraphLaunch(c->gexec, st));     // in order with the caller's work on st
   }
   for (int k = 0; k < c->n_k; ++k) c->v_valid[k] = 1;
   return EXC_OK;
@@ -1299,10 +1294,15 @@ exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* con
   // the host arrays are copied before this call returns (pageable source)
   if (w_k) HIPCHK(c, hipMemcpyAsync(c->d_ewk, w_k, c->n_k * sizeof(double), hipMemcpyHostToDevice, st));
   if (rho_k) HIPCHK(c, hipMemcpyAsync(c->d_erho, rho_k, c->n_k * sizeof(void*), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
-                     rho_k ? (const void* const*)c->d_erho : nullptr, c->n_occ, c->d_eout);
-  hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, st, c->d_eout, w_k ? c->d_ewk : nullptr,
-                     c->n_k, E_dev);
+  if (rho_k) {
+    hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
+                       (const void* const*)c->d_erho, c->n_occ, c->d_eout);
+    hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, st, c->d_eout, w_k ? c->d_ewk : nullptr,
+                       c->n_k, E_dev);
+  } else {                                         // rho = 2 P_occ: one launch
+    hipLaunchKernelGGL(energy_diag_kernel, dim3(1), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
+                       c->n_k, c->n_occ, w_k ? c->d_ewk : nullptr, E_dev);
+  }
   HIPCHK(c, hipGetLastError());
   return EXC_OK;
 }
@@ -1334,7 +1334,7 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 5:
     case 7: {
       // mean duration (ms) of the tile (5) or sparse (7) kernel over the timed replays
-      if (c->t_count == 0) { *value = 0.0; return EXC_OK; }
+      if (c->t_count == 0 || (what == 7 && !c->tnode[0])) { *value = 0.0; return EXC_OK; }
       double sum = 0.0;
       for (int s = 0; s < c->t_count; ++s) {
         hipEvent_t* e = const_cast<hipEvent_t*>(&c->tpool[3 * s]);
