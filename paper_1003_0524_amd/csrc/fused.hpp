@@ -10,17 +10,18 @@
 // structure of the transformed Coulomb matrix (Fig. 1).
 //
 // Layout of the work in one workgroup (4 wavefronts, one per SIMD):
-//  * sparse rows, in chunks of GR = 64 rows: each lane computes one row of Y_s
-//    for the columns of its wavefront in FP64, writes its split pieces to LDS
-//    and adds |Y|^2 to the FP64 diagonal; then the Gram tiles are contracted
-//    over the chunk on MFMA;
+//  * multipole-free rows, in chunks of whole channels of at most GR = 64 rows
+//    (lane = row): each wavefront forms Y_s of its own columns in FP64 registers
+//    (the rows a coefficient run needs come from the lanes below by DPP shifts),
+//    writes the split pieces to LDS and keeps |Y|^2 for the FP64 diagonal in
+//    registers; then the Gram tiles are contracted over the chunk on MFMA;
 //  * dense rows, in row blocks of BM = 64 RTW rows: the accumulators of the
-//    whole row block live in registers (wavefront w owns row tiles w, w+4, ...),
-//    the K loop streams double-buffered LDS panels of A_d (converted from M to
-//    the mode's pieces on the way in) and reads the factor's pieces straight
-//    from global memory (L2: the factor of q is shared by every k); row tiles
-//    whose rows precede the chunk's k range are skipped (L22^H is upper
-//    triangular); then the rows go through LDS, GR at a time, into the Gram
+//    whole row block live in registers (wavefront w owns row tiles w, w+4, ...);
+//    the K loop starts at the block's first row (L22^H is upper triangular),
+//    streams raw K panels of A_d global -> LDS (two in flight where LDS allows),
+//    converts each into the mode's pieces of Re, Im and -Im, and reads the
+//    factor's pieces straight from global memory (L2: the factor of q is shared
+//    by every k); then the rows go through LDS, GR at a time, into the Gram
 //    contraction.
 // Partials: one slot per item (Gram tiles in accumulator order and the FP64
 // diagonal per band), summed per k in a fixed order by the reduction kernel.
@@ -144,7 +145,6 @@ struct FusedCfg {
   static constexpr int NPT = NB8M * (NB8M + 1) / 2;
   static constexpr int NPW = (NPT + NW - 1) / NW;
   static constexpr bool GSTREAM = NPW > 8;
-  static constexpr int NU = NCC * KC / EPV;             // A panel units (EPV consecutive k of one column)
   static constexpr int CB = CBX;                         // sparse step: columns (CB / NW per wavefront)
   static constexpr int CPW = CB / NW;
   static constexpr int NCB = (NCC + CB - 1) / CB;        // column blocks of a sparse chunk (at most)
