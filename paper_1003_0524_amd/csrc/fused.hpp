@@ -552,10 +552,10 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         // ---- K panels of A_d: global -> LDS directly (buffer_load ... lds), then
         // converted in LDS into the mode's pieces. One wave instruction moves 1 KB:
         // two columns of KC complex128 (or four of complex64), lanes in order. With
-        // NRAW = 2 raw buffers two panels are in flight: the factor pieces of the next
-        // panel are requested before the raw panel two ahead, so that waiting for them
-        // (vmcnt counts in order) leaves that panel in flight; every wavefront issues the
-        // same NIW raw instructions per panel (past the data's end they read zero).
+        // NRAW = 2 raw buffers two panels are in flight; the factor pieces of a panel are
+        // requested before its raw panel two ahead, so that waiting for them (vmcnt counts
+        // in order) leaves that panel in flight; every wavefront issues the same NIW raw
+        // instructions per panel (past the data's end they read zero).
         constexpr int NI = C::RAW_B / 1024;                // instructions per panel
         constexpr int NIW = (NI + NW - 1) / NW;            // per wavefront
         uint32_t r_off[NIW];
@@ -611,9 +611,9 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         };
 
         __syncthreads();                              // the stage is free
-        // factor pieces of this wave's tiles, one K panel ahead in registers (L2 latency
-        // hides behind the current panel's MFMAs)
-        op_t ucur[RTW][KC / KS][2][NP], unext[RTW][KC / KS][2][NP];
+        // factor pieces of this wave's tiles for the current K panel, requested before the
+        // panel's conversion (L2 latency hides behind it and the barrier that follows)
+        op_t ucur[RTW][KC / KS][2][NP];
         auto load_u = [&](int kc, op_t (&u)[RTW][KC / KS][2][NP]) {
 #pragma unroll
           for (int ii = 0; ii < RTW; ++ii) {
@@ -630,20 +630,19 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         };
         const int np = (kend - kc0) / KC;                 // K panels of this row block
         issue_raw(kc0, 0);
-        load_u(kc0, ucur);
         if (C::NRAW == 2 && np > 1) {
           issue_raw(kc0 + KC, 1);
-          __builtin_amdgcn_s_waitcnt(C::WAIT_VM_NIW);     // panel 0 and its factor have landed
+          __builtin_amdgcn_s_waitcnt(C::WAIT_VM_NIW);     // panel 0 has landed
         } else {
           __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
         }
         __syncthreads();
         for (int pp = 0; pp < np; ++pp) {
           const int kc = kc0 + pp * KC, buf = C::NRAW == 2 ? (pp & 1) : 0;
+          load_u(kc, ucur);                           // this panel's factor pieces in flight
           convert(kc, buf);
           __syncthreads();                            // pieces ready, raw buffer free
           const bool more = pp + 1 < np;
-          if (more) load_u(kc + KC, unext);           // next panel's factor pieces in flight
           if (C::NRAW == 2) {
             if (pp + 2 < np) issue_raw(kc + 2 * KC, buf);
           } else if (more) {
@@ -680,20 +679,10 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
                                     bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
             }
           }
-          // this wave's part of the next panel (and its factor pieces) has landed
+          // this wave's part of the next panel has landed
           if (C::NRAW == 2 && pp + 2 < np) __builtin_amdgcn_s_waitcnt(C::WAIT_VM_NIW);
           else __builtin_amdgcn_s_waitcnt(C::WAIT_VM0);
           __syncthreads();
-          if (more) {
-#pragma unroll
-            for (int ii = 0; ii < RTW; ++ii)
-#pragma unroll
-              for (int ks = 0; ks < KC / KS; ++ks)
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                  for (int p = 0; p < NP; ++p) ucur[ii][ks][h][p] = unext[ii][ks][h][p];
-          }
         }
 
         // ---- the row block's rows through LDS into the Gram tiles, GR rows at a time ----
