@@ -614,9 +614,21 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         // factor pieces of this wave's tiles for the current K panel, requested before the
         // panel's conversion (L2 latency hides behind it and the barrier that follows)
         op_t ucur[RTW][KC / KS][2][NP];
+        // row tiles of this wavefront with a nonzero factor block in the K panel at kc:
+        // L22^H is upper triangular, so tiles whose rows start past the panel's last k
+        // (or past N_d) meet zeros only; the active tiles are a prefix in ii
+        auto n_active = [&](int kc) {
+          int n = 0;
+#pragma unroll
+          for (int ii = 0; ii < RTW; ++ii)
+            if (r0 + 16 * (w + 4 * ii) < min(kc + KC, nd)) n = ii + 1;
+          return n;
+        };
         auto load_u = [&](int kc, op_t (&u)[RTW][KC / KS][2][NP]) {
+          const int na = n_active(kc);
 #pragma unroll
           for (int ii = 0; ii < RTW; ++ii) {
+            if (ii >= na) break;
             const long row0 = (long)(r0 + 16 * (w + 4 * ii)) * pi.ldu + kc;
 #pragma unroll
             for (int ks = 0; ks < KC / KS; ++ks)
@@ -648,6 +660,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
           } else if (more) {
             issue_raw(kc + KC, 0);
           }
+          const int na = n_active(kc);                // uniform
           // [Yr|Yi] += Br [Ar|Ai] + Bi [-Ai|Ar]: the B operand of step (h, j) is plane
           // part (h = 0) or, for h = 1, -Im (part 0) or Re (part 1); one step ahead
 #pragma unroll
@@ -675,8 +688,9 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
               for (int pr = 0; pr < C::T::NPROD; ++pr)
 #pragma unroll
                 for (int ii = 0; ii < RTW; ++ii)
-                  acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
-                                    bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
+                  if (ii < na)
+                    acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
+                                      bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
             }
           }
           // this wave's part of the next panel has landed
