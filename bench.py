@@ -19,6 +19,10 @@ Forms measured on the same resident inputs:
 The headline ("value") is the fastest batched mixed-precision mode whose
 eigenvalue error against the FP64 oracle, normalised to a 1 Ha spectral radius,
 is <= 1e-6 Ha. Prints one JSON line.
+
+Also timed, outside the step (it is computed once per self-consistency cycle):
+the Gamma-point term's lattice sum (exchange_gamma_term, beta = 0.005, on the
+workload's q mesh), reported under "gamma_term".
 """
 from __future__ import annotations
 
@@ -75,6 +79,7 @@ def main() -> int:
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--modes", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-gamma", action="store_true", help="skip timing the Gamma-point lattice sum")
     ap.add_argument("--only", default=None, help="run a single batched mode (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scales HBM byte counters)")
@@ -149,6 +154,12 @@ def main() -> int:
         kt = ex.kernel_ms() if kernel_timing else None
         return ms, energy, kt
 
+    # the q-mesh divisions (a Gamma-centred mesh has n_i distinct fractions on axis i)
+    mesh = tuple(len(np.unique(np.round(cfg.q_frac[:, i], 12))) for i in range(3))
+    if int(np.prod(mesh)) != cfg.n_q:
+        mesh = None
+    gamma = None
+
     results = {}
     modes = [args.only] if args.only else ["plain", "fp64"] + [m for m in args.modes.split(",") if m]
     for mode in modes:
@@ -168,6 +179,18 @@ def main() -> int:
         log(f"[bench] {mode}: {ms:.4f} ms/step, E_x = {energy:.8f}"
             + (f", main kernel {kt[0]:.4f} ms, sparse kernel {kt[1]:.4f} ms" if kt else "")
             + f", config {results[mode]['cfg']}{' (autotuned)' if results[mode]['tuned'] else ''}")
+        if gamma is None and mesh is not None and not args.no_gamma:
+            # Gamma-point term (computed once per self-consistency cycle): lattice-sum kernel, HIP events
+            c_gamma = ex.gamma_term(cfg.recip(), mesh, 0.005, apply=False)
+            kms = []
+            for _ in range(5):
+                ex.gamma_term(cfg.recip(), mesh, 0.005, apply=False)
+                kms.append(ex.gamma_kernel_ms()[0])
+            n_terms = ex.gamma_kernel_ms()[1]
+            gamma = {"C": c_gamma, "beta": 0.005, "mesh": list(mesh), "terms": n_terms,
+                     "kernel_ms": round(float(np.mean(kms)), 5),
+                     "terms_per_s": round(n_terms / (float(np.mean(kms)) * 1e-3), 1)}
+            log(f"[bench] gamma term: C = {c_gamma:.12f}, {n_terms} terms, lattice-sum kernel {gamma['kernel_ms']:.4f} ms")
         ex.close()
 
     # errors against the float64 oracle (all k)
@@ -268,7 +291,7 @@ def main() -> int:
         "gflops_executed": round(H["flops_exec"] / (H["ms"] * 1e-3) / 1e9, 3),
         "err_eig_ha": H["err_eig_ha"], "err_normwise": H["err_norm"],
         "init_ms": round(H["init_ms"], 2),
-        "roofline": roof, "cpu_baseline": cpu, "sparse_rows": sparse,
+        "roofline": roof, "cpu_baseline": cpu, "sparse_rows": sparse, "gamma_term": gamma,
         "modes": {m: {"ms_per_step": round(r["ms"], 5),
                       "gflops": round(r["flops_nom"] / (r["ms"] * 1e-3) / 1e9, 3),
                       "err_eig_ha": r["err_eig_ha"], "err_normwise": r["err_norm"],

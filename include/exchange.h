@@ -166,6 +166,33 @@ exc_status exchange_energy(exc_ctx *ctx, const double *w_k, const void *const *r
 exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *const *rho_k,
                                   double *E_dev, void *stream);
 
+/*
+ * exchange_gamma_term -- the q -> 0 term of the exchange matrix (Sec. II.D,
+ * eqs. "F(q)", "divergence" and "div final"). The divergent 1/q^2 part of the
+ * Coulomb matrix, damped by exp(-beta q^2), is integrated analytically and the
+ * part of that integral the q-mesh sum already holds is subtracted:
+ *   C = erf(sqrt(beta) q0) / sqrt(pi beta)
+ *       - 4 pi / (N Omega) * sum_{p, 0 < |p| <= q0} exp(-beta |p|^2) / |p|^2
+ * with exp(-beta q0^2) = beta, p over every point q + G of the mesh (every G),
+ * N = mesh[0] mesh[1] mesh[2] and Omega = (2 pi)^3 / |det B|. The prefactor
+ * 4 pi / (N Omega) is the Riemann-sum weight that makes the bracket vanish as
+ * the mesh is refined (the printed equation shows 1/(N Omega)). V_nn gains -C
+ * for n < n_occ (occupation 1 per spin); off-diagonal elements are unchanged.
+ *   recip : [9] host, row-major, rows = reciprocal lattice vectors b_i (bohr^-1)
+ *   mesh  : [3] host, divisions of the Gamma-centred mesh (>= 1); its points are
+ *           sum_i (j_i / mesh_i) b_i for integer j_i
+ *   beta  : damping parameter, 0 < beta < 1 (the paper's choice is 0.005)
+ *   apply : 1 -> every later exchange_matrix[_all] adds -C to the occupied diagonal
+ *           of V(k) (and so to exchange_energy); 0 -> C is computed, no shift is applied
+ *   C_out : host, receives C (may be NULL)
+ * The lattice sum runs on the GPU in FP64 in a fixed order (the same inputs give
+ * the same bits). The call waits for earlier exchange_matrix[_all] work, runs on
+ * `stream` and synchronises it. EXC_EINVAL for NULL arrays, mesh < 1, beta outside
+ * (0, 1), linearly dependent b_i, or more than 2^40 candidate lattice points.
+ */
+exc_status exchange_gamma_term(exc_ctx *ctx, const double *recip, const int32_t *mesh, double beta,
+                               int32_t apply, double *C_out, void *stream);
+
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx == NULL,
  * the message of the last failed exchange_init on this thread. */
 const char *exchange_last_error(const exc_ctx *ctx);
@@ -189,6 +216,8 @@ void exchange_destroy(exc_ctx *ctx);
  *   what = 10: 1 if the fused kernel serves the batched path, else 0
  *   what = 4: algorithmic HBM bytes of one exchange_matrix_all
  *             (M read once, v(q) read once, Vx written once)
+ *   what = 11: duration (ms, HIP events) of the lattice-sum kernel of the last
+ *              exchange_gamma_term; what = 12: its number of terms
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);

@@ -30,7 +30,7 @@ DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
-                    "exchange_energy_device",
+                    "exchange_energy_device", "exchange_gamma_term",
                     "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
                     "exchange_nn_init", "exchange_nn_params", "exchange_nn_train", "exchange_nn_grad",
                     "exchange_nn_predict", "exchange_nn_features", "exchange_eigh", "exchange_nn_project",
@@ -79,6 +79,9 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.POINTER(ctypes.c_double)]
     lib.exchange_energy.restype = i32
     lib.exchange_energy_device.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp), vp, vp]
+    lib.exchange_gamma_term.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
+                                        ctypes.c_double, i32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.exchange_gamma_term.restype = i32
     lib.exchange_energy_device.restype = i32
     lib.exchange_last_error.argtypes = [vp]
     lib.exchange_last_error.restype = ctypes.c_char_p
@@ -248,6 +251,23 @@ class Exchange:
             rp = (ctypes.c_void_p * self.n_k)(*[r.data_ptr() for r in rho])
         st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
         self._check(self.lib.exchange_energy_device(self.ctx, wk, rp, ctypes.c_void_p(out.data_ptr()), st))
+
+    def gamma_term(self, recip, mesh: Sequence[int], beta: float = 0.005, apply: bool = True,
+                   stream=None) -> float:
+        """C of the q -> 0 term (exchange_gamma_term); with apply, later V(k) carry -C on the occupied diagonal."""
+        b = np.ascontiguousarray(np.asarray(recip, dtype=np.float64).reshape(9))
+        m = np.ascontiguousarray(np.asarray(mesh, dtype=np.int32).reshape(3))
+        out = ctypes.c_double()
+        st = (ctypes.c_void_p(stream.cuda_stream) if stream is not None
+              else _stream_handle(self._torch, self.device))
+        self._check(self.lib.exchange_gamma_term(self.ctx, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(beta),
+                                                 int(bool(apply)), ctypes.byref(out), st))
+        return out.value
+
+    def gamma_kernel_ms(self):
+        """(lattice-sum kernel ms, number of terms) of the last gamma_term call."""
+        return self.query(11), int(self.query(12))
 
     def query(self, what: int) -> float:
         v = ctypes.c_double()

@@ -149,6 +149,8 @@ struct ReduceArgs {
   double2* vres;
   const int64_t* v_off;        // [n_k]
   void* const* vout;           // [n_k] device pointers or nullptr
+  const double* gshift;        // Gamma-point term added to -V_nn for n < n_occ (0 when unset)
+  int32_t n_occ;
 };
 
 // Position of G[row][col] of Gram tile tp in a partial slot written as
@@ -216,6 +218,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   if (n == n2) {
     im = 0.0;
     if (a.use_d64) re = ((red[0][e][2] + red[1][e][2]) + red[2][e][2]) + red[3][e][2];
+    if (n < a.n_occ) re += *a.gshift;
   }
   const double2 v = make_double2(-re, -im);
   double2* V = a.vres + a.v_off[k];

@@ -19,6 +19,7 @@
 #include "aux.hpp"
 #include "tile.hpp"
 #include "fused.hpp"
+#include "gamma.hpp"
 
 using namespace exc;
 
@@ -193,6 +194,11 @@ struct exc_ctx {
   double* d_eout = nullptr;
   double* d_ewk = nullptr;            // [n_k] weights of exchange_energy_device
   void** d_erho = nullptr;            // [n_k] rho pointers of exchange_energy_device
+  double* d_gamma = nullptr;          // [4] Gamma-point term: C, lattice sum, terms, diagonal shift
+  double* d_gpartial = nullptr;       // [2 * kGammaGrid] per-workgroup partials of the lattice sum
+  hipEvent_t ev_g[2] = {nullptr, nullptr};
+  float gamma_ms = 0.f;               // lattice-sum kernel of the last exchange_gamma_term
+  double gamma_terms = 0.0;           // its number of terms
   hipStream_t last_stream = nullptr;
   // accounting
   double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
@@ -272,12 +278,15 @@ void release(exc_ctx* c) {
   if (c->ev_in) hipEventDestroy(c->ev_in);
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own) hipStreamDestroy(c->own);
+  for (hipEvent_t& e : c->ev_g) if (e) hipEventDestroy(e);
+  c->ev_g[0] = c->ev_g[1] = nullptr;
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
                   c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
-                  c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho};
+                  c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
+                  c->d_gamma, c->d_gpartial};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
@@ -573,6 +582,8 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   r.vres = c->d_vres;
   r.v_off = c->d_voff + k0;
   r.vout = c->d_vtab + k0;
+  r.gshift = c->d_gamma + 3;
+  r.n_occ = c->n_occ;
   L.grid = dim3(c->nbt_max * (c->nbt_max + 1) / 2, nk);
   L.block = dim3(256);
   L.shmem = 0;
@@ -1143,6 +1154,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_ewk, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_erho, (size_t)c->n_k));
+  ITRY(dalloc(c, &c->d_gamma, (size_t)4));
+  IHIP(hipMemset(c->d_gamma, 0, 4 * sizeof(double)));   // no Gamma-point shift until requested
 
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
@@ -1307,6 +1320,73 @@ exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* con
   return EXC_OK;
 }
 
+exc_status exchange_gamma_term(exc_ctx* c, const double* recip, const int32_t* mesh, double beta,
+                               int32_t apply, double* C_out, void* stream) {
+  TRY(check_ctx(c));
+  if (!recip || !mesh) return fail(c, EXC_EINVAL, "recip and mesh must not be NULL");
+  if (!(beta > 0.0 && beta < 1.0)) return fail(c, EXC_EINVAL, "beta = %g is outside (0, 1)", beta);
+  for (int i = 0; i < 3; ++i)
+    if (mesh[i] < 1) return fail(c, EXC_EINVAL, "mesh[%d] = %d < 1", i, mesh[i]);
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(recip[i])) return fail(c, EXC_EINVAL, "recip[%d] is not finite", i);
+  // cofactor rows of B: a_i = 2 pi cof_i / det B are the real-space vectors
+  const double(*B)[3] = (const double(*)[3])recip;
+  double cof[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      cof[i][j] = B[i1][j1] * B[i2][j2] - B[i1][j2] * B[i2][j1];
+    }
+  const double det = B[0][0] * cof[0][0] + B[0][1] * cof[0][1] + B[0][2] * cof[0][2];
+  double bmax = 0.0;
+  for (int i = 0; i < 9; ++i) bmax = std::max(bmax, std::fabs(recip[i]));
+  if (!(std::fabs(det) > 1e-12 * bmax * bmax * bmax))
+    return fail(c, EXC_EINVAL, "the reciprocal lattice vectors are linearly dependent");
+  const double q0 = std::sqrt(-std::log(beta) / beta);   // exp(-beta q0^2) = beta
+  GammaArgs ga{};
+  double boxes = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    const double an = std::sqrt(cof[i][0] * cof[i][0] + cof[i][1] * cof[i][1] + cof[i][2] * cof[i][2]);
+    // |j_i| = mesh_i |p . a_i| / (2 pi) <= mesh_i q0 |a_i| / (2 pi); one more for rounding
+    const double jm = std::floor(mesh[i] * q0 * an / std::fabs(det)) + 1.0;
+    if (jm > 1e9) return fail(c, EXC_EINVAL, "the lattice sum is too large (beta too small for this mesh)");
+    ga.J[i] = (int32_t)jm;
+    boxes *= 2.0 * jm + 1.0;
+    for (int d = 0; d < 3; ++d) ga.g[i][d] = recip[3 * i + d] / mesh[i];
+  }
+  if (boxes > 1099511627776.0)   // 2^40 candidate points
+    return fail(c, EXC_EINVAL, "the lattice sum is too large (%.3g candidate points)", boxes);
+  ga.beta = beta;
+  ga.q0sq = q0 * q0;
+  if (!c->d_gpartial) TRY(dalloc(c, &c->d_gpartial, (size_t)2 * kGammaGrid));
+  ga.part = c->d_gpartial;
+  if (!c->ev_g[0]) {
+    HIPCHK(c, hipEventCreate(&c->ev_g[0]));
+    HIPCHK(c, hipEventCreate(&c->ev_g[1]));
+  }
+  const double pi = 3.14159265358979323846;
+  const double omega = 8.0 * pi * pi * pi / std::fabs(det);
+  const double pref = 4.0 * pi / ((double)mesh[0] * mesh[1] * mesh[2] * omega);
+  hipStream_t st = (hipStream_t)stream;
+  if (c->last_stream && st != c->last_stream) {   // the shift changes after earlier q-sums
+    HIPCHK(c, hipEventRecord(c->ev_out, c->last_stream));
+    HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
+  }
+  HIPCHK(c, hipEventRecord(c->ev_g[0], st));
+  hipLaunchKernelGGL(gamma_sum_kernel, dim3(kGammaGrid), dim3(kGammaBlock), 0, st, ga);
+  HIPCHK(c, hipEventRecord(c->ev_g[1], st));
+  hipLaunchKernelGGL(gamma_finish_kernel, dim3(1), dim3(kGammaBlock), 0, st, (const double*)c->d_gpartial,
+                     kGammaGrid, beta, q0, pref, (int)(apply != 0), c->d_gamma);
+  HIPCHK(c, hipGetLastError());
+  double h[4];
+  HIPCHK(c, hipMemcpyAsync(h, c->d_gamma, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  HIPCHK(c, hipEventElapsedTime(&c->gamma_ms, c->ev_g[0], c->ev_g[1]));
+  c->gamma_terms = h[2];
+  if (C_out) *C_out = h[0];
+  return EXC_OK;
+}
+
 const char* exchange_last_error(const exc_ctx* c) {
   if (!c) return g_init_err.c_str();
   if (c->magic != kAlive) return "context is not alive";
@@ -1350,6 +1430,8 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 8: *value = c->tuned; return EXC_OK;
     case 9: *value = (double)c->ws_bytes; return EXC_OK;
     case 10: *value = c->fused ? 1.0 : 0.0; return EXC_OK;
+    case 11: *value = c->gamma_ms; return EXC_OK;
+    case 12: *value = c->gamma_terms; return EXC_OK;
     default: return EXC_EINVAL;
   }
 }
