@@ -151,7 +151,13 @@ struct ReduceArgs {
   void* const* vout;           // [n_k] device pointers or nullptr
   const double* gshift;        // Gamma-point term added to -V_nn for n < n_occ (0 when unset)
   int32_t n_occ;
+  int32_t* counter;            // work counters of the persistent launch before this one, cleared
+  int32_t n_counter;           // here for the next launch (nullptr / 0: none)
 };
+
+// Slot groups per q-sum workgroup: group sg sums slots sg, sg + RED_SG, ... of its k
+// (one round of loads for up to 4 RED_SG slots), the groups are added in order.
+constexpr int RED_SG = 16;
 
 // Position of G[row][col] of Gram tile tp in a partial slot written as
 // [tile][element i][lane] (see acc_row for the two accumulator layouts).
@@ -162,8 +168,9 @@ __device__ __forceinline__ int gidx(int tp, int row, int col) {
 }
 
 template <int ACC64>
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
-  __shared__ double red[4][64][3];
+__global__ __launch_bounds__(64 * RED_SG) void reduce_kernel(ReduceArgs a) {
+  __shared__ double red[RED_SG][64][3];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < a.n_counter) a.counter[threadIdx.x] = 0;
   const int k = blockIdx.y;
   const int nb = a.k_nb[k];
   const int nbt = (nb + 7) >> 3;
@@ -178,14 +185,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const int iri = gidx<ACC64>(tp, c, c2 + 8), iir = gidx<ACC64>(tp, c + 8, c2);
   double re = 0.0, im = 0.0, dg = 0.0;
   const bool diag = (n == n2) && n < nb;
-  // slots sg, sg + 4, ... in order; UN slots' loads are issued before their adds
+  // slots sg, sg + RED_SG, ... in order; UN slots' loads are issued before their adds
   constexpr int UN = 4;
   const int s0 = a.slot_begin[k] + sg, s1 = a.slot_begin[k + 1];
-  for (int sb = s0; sb < s1; sb += 4 * UN) {
+  for (int sb = s0; sb < s1; sb += RED_SG * UN) {
     double wq[UN], grr[UN], gii[UN], gri[UN], gir[UN], dd[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int s = sb + 4 * u;
+      const int s = sb + RED_SG * u;
       wq[u] = grr[u] = gii[u] = gri[u] = gir[u] = dd[u] = 0.0;
       if (s < s1) {
         wq[u] = a.slot_w[s];
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      if (sb + 4 * u < s1) {
+      if (sb + RED_SG * u < s1) {
         re += wq[u] * (grr[u] + gii[u]);
         im += wq[u] * (gri[u] - gir[u]);
         if (diag && a.use_d64) dg += wq[u] * dd[u];
@@ -213,11 +220,18 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   red[sg][e][2] = dg;
   __syncthreads();
   if (sg != 0 || n >= nb || n2 >= nb || n > n2) return;
-  re = ((red[0][e][0] + red[1][e][0]) + red[2][e][0]) + red[3][e][0];
-  im = ((red[0][e][1] + red[1][e][1]) + red[2][e][1]) + red[3][e][1];
+  re = red[0][e][0];
+  im = red[0][e][1];
+  double dsum = red[0][e][2];
+#pragma unroll
+  for (int g = 1; g < RED_SG; ++g) {
+    re += red[g][e][0];
+    im += red[g][e][1];
+    dsum += red[g][e][2];
+  }
   if (n == n2) {
     im = 0.0;
-    if (a.use_d64) re = ((red[0][e][2] + red[1][e][2]) + red[2][e][2]) + red[3][e][2];
+    if (a.use_d64) re = dsum;
     if (n < a.n_occ) re += *a.gshift;
   }
   const double2 v = make_double2(-re, -im);
@@ -517,11 +531,6 @@ __global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, cons
     if (t < ri.y) v = coef[ri.x + t];
   }
   out[e] = v;
-}
-
-__global__ void zero_int_kernel(int32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
 }
 
 }  // namespace exc

@@ -585,7 +585,7 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   r.gshift = c->d_gamma + 3;
   r.n_occ = c->n_occ;
   L.grid = dim3(c->nbt_max * (c->nbt_max + 1) / 2, nk);
-  L.block = dim3(256);
+  L.block = dim3(64 * RED_SG);
   L.shmem = 0;
   L.fn = r.acc64 ? (const void*)reduce_kernel<1> : (const void*)reduce_kernel<0>;
   L.arg = &r;
@@ -659,8 +659,9 @@ void run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
 }
 
 // The batched path as an explicit graph:
-//   zero work counter -> [ev0] -> block-sparse rows -> [ev1] -> persistent tile
-//   kernel -> [ev2] -> FP64 reduction.
+//   [ev0] -> block-sparse rows -> [ev1] -> persistent tile (or fused) kernel ->
+//   [ev2] -> FP64 reduction, which also clears the persistent kernel's work
+//   counters for the next replay (they start at zero from init).
 // The event-record nodes exist only while kernel timing is on; their events are
 // swapped per replay (hipGraphExecEventRecordNodeSetEvent).
 exc_status build_batched_graph(exc_ctx* c, int dtype) {
@@ -668,21 +669,12 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   HIPCHK(c, hipGraphCreate(&g, 0));
   const bool timed = c->t_slots > 0;
   for (auto& t : c->tnode) t = nullptr;
-  int32_t one = NQ_MAX;                 // work counters to clear (one per queue)
-  int32_t* ctr = c->d_counter;
-  void* zargs[2] = {&ctr, &one};
-  hipKernelNodeParams zp{};
-  zp.func = (void*)zero_int_kernel;
-  zp.gridDim = dim3(1);
-  zp.blockDim = dim3(64);
-  zp.kernelParams = zargs;
   hipGraphNode_t last = nullptr, node = nullptr;
-  hipError_t e = hipGraphAddKernelNode(&node, g, nullptr, 0, &zp);
-  last = node;
+  hipError_t e = hipSuccess;
   auto add_ev = [&](int i) -> hipError_t {
     if (!timed || e != hipSuccess) return e;
     hipGraphNode_t n2 = nullptr;
-    hipError_t r = hipGraphAddEventRecordNode(&n2, g, &last, 1, c->tpool[i]);
+    hipError_t r = hipGraphAddEventRecordNode(&n2, g, last ? &last : nullptr, last ? 1 : 0, c->tpool[i]);
     if (r == hipSuccess) { c->tnode[i] = n2; last = n2; }
     return r;
   };
@@ -690,20 +682,22 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   KLaunch L;
   if (e == hipSuccess && cfg_sparse(c, dtype, 0, (int)c->pairs.size(), sa, L)) {
     e = add_ev(0);                      // (the fused path has no block-sparse kernel to time)
-    if (e == hipSuccess) e = add_node(g, L, &last, &node);
+    if (e == hipSuccess) e = add_node(g, L, last ? &last : nullptr, &node);
     last = node;
   }
   e = add_ev(1);
   MainArgs ta;
   if (e == hipSuccess) {
     cfg_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
-    e = add_node(g, L, &last, &node);
+    e = add_node(g, L, last ? &last : nullptr, &node);
     last = node;
   }
   e = add_ev(2);
   ReduceArgs ra;
   if (e == hipSuccess) {
     cfg_reduce(c, c->bat, 0, c->n_k, ra, L);
+    ra.counter = c->d_counter;
+    ra.n_counter = NQ_MAX;
     e = add_node(g, L, &last, &node);
   }
   const char* where = e == hipSuccess ? "instantiate" : "add node";
@@ -1151,6 +1145,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   IHIP(hipMemset(c->d_mtab, 0, c->n_k * sizeof(void*)));
   IHIP(hipMemset(c->d_vtab, 0, c->n_k * sizeof(void*)));
   ITRY(dalloc(c, &c->d_counter, (size_t)NQ_MAX));
+  IHIP(hipMemset(c->d_counter, 0, NQ_MAX * sizeof(int32_t)));   // each q-sum clears them again
   ITRY(dalloc(c, &c->d_eout, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_ewk, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_erho, (size_t)c->n_k));
