@@ -80,6 +80,7 @@ def main() -> int:
     ap.add_argument("--modes", default="fp32,bf16x3,bf16x6")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gamma", action="store_true", help="skip timing the Gamma-point lattice sum")
+    ap.add_argument("--no-inversion", action="store_true", help="skip the inversion-symmetric variant")
     ap.add_argument("--only", default=None, help="run a single batched mode (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scales HBM byte counters)")
@@ -118,32 +119,35 @@ def main() -> int:
     log(f"[bench] workload {args.workload}: n_k={cfg.n_k} n_q={cfg.n_q} N_MB={cfg.n_mb(0)} "
         f"n_b={cfg.n_bands[0]} n_occ={cfg.n_occ}")
 
-    def make(precision, form, batched):
+    def make(precision, form, batched, inversion=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C,
-                          w_q=cfg.weights_q(), precision=precision, form=form, batched=batched)
+        blocks = synth.coulomb_blocks_real(cfg) if inversion else (E, D, C)
+        ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, *blocks,
+                          w_q=cfg.weights_q(), precision=precision, form=form, batched=batched,
+                          inversion=inversion)
         torch.cuda.synchronize()
         return ex, (time.perf_counter() - t0) * 1e3
 
     outs = [torch.empty(nb * nb, dtype=torch.complex128, device=dev) for nb in cfg.n_bands]
     e_dev = torch.zeros(1, dtype=torch.float64, device=dev)
 
-    def step(ex):
+    def step(ex, m_in):
         # V(k) for every k and E_x, both left in device memory: no host round trip per step
-        ex.matrix_all(Ms, outs)
+        ex.matrix_all(m_in, outs)
         ex.energy_device(e_dev)
 
-    def timed(ex, steps, warmup, kernel_timing=False):
+    def timed(ex, steps, warmup, kernel_timing=False, m_in=None):
+        m_in = Ms if m_in is None else m_in
         if kernel_timing:
             ex.timing(steps)          # re-captures the graph: before the warm-up
         for _ in range(max(1, warmup)):
-            step(ex)
+            step(ex, m_in)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            step(ex)
+            step(ex, m_in)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -209,6 +213,30 @@ def main() -> int:
     head = min(mixed, key=lambda m: results[m]["ms"]) if mixed else ("fp64" if "fp64" in results else modes[0])
     H = results[head]
     value = H["flops_nom"] / (H["ms"] * 1e-3) / 1e9
+
+    # inversion-symmetric variant (real v and real projections, bands packed in pairs) in the
+    # headline's precision on the same workload shapes
+    inv = None
+    if not args.no_inversion and head not in ("plain",):
+        Mr = [torch.from_numpy(synth.m_all_real_packed(cfg, k, mdt)).to(dev) for k in range(cfg.n_k)]
+        exr, init_r = make(head, "herk", True, inversion=True)
+        ms_r, e_r, kt_r = timed(exr, args.steps, args.warmup, kernel_timing=True, m_in=Mr)
+        Vr = [o.view(nb, nb).T.cpu().numpy() for o, nb in zip(outs, cfg.n_bands)]
+        nom_r, cfg_r = exr.query(1), int(exr.query(3))
+        exr.close()
+        Er, Dr, Cr = synth.coulomb_blocks_real(cfg)
+        vr = [vx.assemble_v(Er[q], Dr, Cr) for q in range(cfg.n_q)]
+        refs_r = [vx.vx_k([synth.m_block_real(cfg, k, q) for q in range(cfg.n_q)], vr, cfg.weights_q())
+                  for k in range(cfg.n_k)]
+        rho_r = max(np.abs(np.linalg.eigvalsh(r.real)).max() for r in refs_r)
+        inv = {"mode": head, "ms_per_step": round(ms_r, 5), "main_kernel_ms": round(kt_r[0], 5),
+               "gflops_nominal_real": round(nom_r / (ms_r * 1e-3) / 1e9, 3),
+               "kpoints_per_s": round(cfg.n_k / (ms_r * 1e-3), 1),
+               "speedup_vs_complex": round(H["ms"] / ms_r, 3), "config": cfg_r,
+               "err_normwise": max(pr.normwise_error(a, b) for a, b in zip(Vr, refs_r)),
+               "err_eig_ha": max(pr.normalised_eig_error(a, b, rho_r) for a, b in zip(Vr, refs_r))}
+        log(f"[bench] inversion variant ({head}): {ms_r:.4f} ms/step, main kernel {kt_r[0]:.4f} ms, "
+            f"{H['ms'] / ms_r:.2f}x the complex step, eigenvalue error {inv['err_eig_ha']:.3e} Ha")
 
     # roofline of the dominant kernel, timed live with graph event nodes. Its bound
     # follows from its arithmetic intensity (algorithmic flops / algorithmic HBM
@@ -292,6 +320,7 @@ def main() -> int:
         "err_eig_ha": H["err_eig_ha"], "err_normwise": H["err_norm"],
         "init_ms": round(H["init_ms"], 2),
         "roofline": roof, "cpu_baseline": cpu, "sparse_rows": sparse, "gamma_term": gamma,
+        "inversion_variant": inv,
         "modes": {m: {"ms_per_step": round(r["ms"], 5),
                       "gflops": round(r["flops_nom"] / (r["ms"] * 1e-3) / 1e9, 3),
                       "err_eig_ha": r["err_eig_ha"], "err_normwise": r["err_norm"],

@@ -95,6 +95,16 @@ typedef struct {
                                (k,q) work captured in a HIP graph; 0 = one launch per
                                (k,q) pair, no graph                                      */
   int32_t device;           /* HIP device ordinal                                        */
+  int32_t inversion;        /* 1: inversion-symmetric system (Sec. II.D, symmetrized MT
+                               functions): v(q) and the projections are real. Only the
+                               real parts of E, D and C are read. M holds the n_occ real
+                               bands in pairs: column j of a q block is the complex number
+                               M_{2j} + i M_{2j+1} (M_{n_occ} = 0 when n_occ is odd), so a
+                               q block is [ceil(n_occ/2)][n_b][N_MB] in the element type of
+                               `dtype`. V(k) is real symmetric (stored complex128, Im = 0).
+                               Since v is real, Re(Y^H Y) of a packed column is the sum of
+                               the two bands' Y^T Y: half the columns, half the bytes.
+                               0: general complex system                                 */
 } exc_desc;
 
 typedef struct {

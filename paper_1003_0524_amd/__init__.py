@@ -49,7 +49,7 @@ class _Desc(ctypes.Structure):
                 ("n_bands", ctypes.POINTER(ctypes.c_int32)), ("n_pw", ctypes.POINTER(ctypes.c_int32)),
                 ("ch_nrad", ctypes.POINTER(ctypes.c_int32)), ("w_q", ctypes.POINTER(ctypes.c_double)),
                 ("precision", ctypes.c_int32), ("form", ctypes.c_int32), ("batched", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("inversion", ctypes.c_int32)]
 
 
 class _Coulomb(ctypes.Structure):
@@ -128,7 +128,9 @@ class Exchange:
     def __init__(self, n_bands: Sequence[int], n_pw: Sequence[int], ch_nrad: Sequence[int],
                  n_occ: int, E: Sequence[np.ndarray], D: Sequence[np.ndarray], C: Sequence[np.ndarray],
                  w_q: Optional[Sequence[float]] = None, precision: str = "fp64", form: str = "herk",
-                 batched: bool = True, device: int = 0):
+                 batched: bool = True, device: int = 0, inversion: bool = False):
+        """inversion=True: real v and real bands; M packs bands 2j, 2j+1 as the real and imaginary
+        parts of column j (``synth.pack_real_pairs``) and V(k) comes back real (Im = 0)."""
         import torch
         if not torch.cuda.is_available():
             raise ExchangeError(-5, "no GPU visible: the exchange library runs only on a HIP device")
@@ -138,6 +140,8 @@ class Exchange:
         self.n_k, self.n_q = len(n_bands), len(n_pw)
         self.n_bands = [int(x) for x in n_bands]
         self.n_occ = int(n_occ)
+        self.inversion = bool(inversion)
+        self.n_cols = (self.n_occ + 1) // 2 if self.inversion else self.n_occ   # columns n'' of M
         self.precision, self.form, self.batched = precision, form, bool(batched)
         nb_arr, nb_p = _i32(n_bands)
         pw_arr, pw_p = _i32(n_pw)
@@ -148,7 +152,8 @@ class Exchange:
         desc = _Desc(self.n_k, self.n_q, self.n_occ, len(ch_nrad), nb_p, pw_p,
                      ch_p if len(ch_nrad) else None,
                      wq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wq_arr is not None else None,
-                     PRECISIONS[precision], FORMS[form], 1 if batched else 0, device)
+                     PRECISIONS[precision], FORMS[form], 1 if batched else 0, device,
+                     1 if self.inversion else 0)
         e_host = [np.ascontiguousarray(np.asarray(e, dtype=np.complex128).T) for e in E]  # column-major
         e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.ctypes.data for e in e_host])
         d_cat = np.concatenate([np.asarray(d, np.complex128).T.ravel() for d in D] + [np.zeros(0, np.complex128)])
@@ -180,7 +185,7 @@ class Exchange:
         raise ExchangeError(-1, f"M must be complex64 or complex128, got {M.dtype}")
 
     def m_elems(self, k: int, n_mb: Sequence[int]) -> int:
-        return int(sum(self.n_occ * self.n_bands[k] * int(n) for n in n_mb))
+        return int(sum(self.n_cols * self.n_bands[k] * int(n) for n in n_mb))
 
     # -- API ---------------------------------------------------------------
     def matrix(self, k: int, M, out=None):

@@ -151,6 +151,7 @@ struct ReduceArgs {
   void* const* vout;           // [n_k] device pointers or nullptr
   const double* gshift;        // Gamma-point term added to -V_nn for n < n_occ (0 when unset)
   int32_t n_occ;
+  int32_t real_v;              // 1: V = Re of the result (inversion symmetry, packed real bands)
   int32_t* counter;            // work counters of the persistent launch before this one, cleared
   int32_t n_counter;           // here for the next launch (nullptr / 0: none)
 };
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(64 * RED_SG) void reduce_kernel(ReduceArgs a) {
     im += red[g][e][1];
     dsum += red[g][e][2];
   }
+  if (a.real_v) im = 0.0;
   if (n == n2) {
     im = 0.0;
     if (a.use_d64) re = dsum;

@@ -126,6 +126,11 @@ struct exc_ctx {
   uint32_t magic = kAlive;
   std::string err;
   int n_k = 0, n_q = 0, n_occ = 0, n_ch = 0, precision = 0, form = 0, batched = 0, device = 0;
+  // n_occ: columns n'' of M per band n (the kernels' view). With inversion symmetry two real
+  // occupied bands share one complex column, so n_occ_v (occupied bands of V, for the
+  // energy and the Gamma-point shift) is 2 n_occ or 2 n_occ - 1; otherwise n_occ_v = n_occ.
+  int n_occ_v = 0;
+  bool real_v = false;                // inversion symmetry: V = Re of the packed product
   std::vector<int> nb, npw, nrad, nd, nmb;
   std::vector<double> wq;
   int n_s = 0, nb_max = 0, nbt_max = 0, ns_pad = 0;
@@ -583,7 +588,8 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   r.v_off = c->d_voff + k0;
   r.vout = c->d_vtab + k0;
   r.gshift = c->d_gamma + 3;
-  r.n_occ = c->n_occ;
+  r.n_occ = c->n_occ_v;
+  r.real_v = c->real_v ? 1 : 0;
   L.grid = dim3(c->nbt_max * (c->nbt_max + 1) / 2, nk);
   L.block = dim3(64 * RED_SG);
   L.shmem = 0;
@@ -877,6 +883,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     return fail(nullptr, EXC_EINVAL, "bad form %d", d->form);
   if (d->form == EXC_FORM_GEMM && d->precision != EXC_FP64)
     return fail(nullptr, EXC_EUNSUPPORTED, "the GEMM form runs in FP64 only");
+  if (d->inversion != 0 && d->inversion != 1) return fail(nullptr, EXC_EINVAL, "inversion must be 0 or 1");
   if (!cv->E) return fail(nullptr, EXC_EINVAL, "coulomb.E is NULL");
   for (int k = 0; k < d->n_k; ++k)
     if (d->n_bands[k] < 1 || d->n_bands[k] > 128)
@@ -914,6 +921,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   } while (0)
 
   c->n_k = d->n_k; c->n_q = d->n_q; c->n_occ = d->n_occ; c->n_ch = d->n_channels;
+  c->n_occ_v = d->n_occ;
+  c->real_v = d->inversion != 0;
+  if (c->real_v) c->n_occ = (d->n_occ + 1) / 2;
   c->precision = d->precision; c->form = d->form; c->batched = d->batched; c->device = d->device;
   c->nb.assign(d->n_bands, d->n_bands + d->n_k);
   c->npw.assign(d->n_pw, d->n_pw + d->n_q);
@@ -974,6 +984,10 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       if (!cv->C) { fail(c, EXC_EINVAL, "coulomb.C is NULL"); return bail(EXC_EINVAL); }
       IHIP(hipMemcpy(c->d_cvec, cv->C, (size_t)c->n_s * 16, kind));
     }
+    if (c->real_v) {                  // only the real parts of v are read
+      if (c->coef_total) IHIP(hipMemset2D((char*)c->d_coef + 8, 16, 0, 8, (size_t)c->coef_total));
+      if (c->n_s) IHIP(hipMemset2D((char*)c->d_cvec + 8, 16, 0, 8, (size_t)c->n_s));
+    }
     ITRY(upload(c, &c->d_row_chan, row_chan));
     {
       // per multipole-free row r (entry i of channel ch, b = ch_len): the coefficient
@@ -1011,6 +1025,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       if (!cv->E[q] && c->nd[q] > 0) { cleanup(); fail(c, EXC_EINVAL, "coulomb.E[%d] is NULL", q); return bail(EXC_EINVAL); }
       if (c->nd[q] > 0) {
         hipError_t e = hipMemcpy(d_E + e_off[q], cv->E[q], (size_t)c->nd[q] * c->nd[q] * 16, kind);
+        if (e == hipSuccess && c->real_v)
+          e = hipMemset2D((char*)(d_E + e_off[q]) + 8, 16, 0, 8, (size_t)c->nd[q] * c->nd[q]);
         if (e != hipSuccess) { cleanup(); fail(c, EXC_EHIP, "copy of E[%d]: %s", q, hipGetErrorString(e)); return bail(EXC_EHIP); }
       }
     }
@@ -1111,6 +1127,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     m_max = std::max(m_max, moff);
     c->k_pair.push_back((int)c->pairs.size());
   }
+  // with inversion symmetry the method works in real arithmetic (2 flops per multiply-add
+  // instead of 8) on n_occ_v real bands
+  if (c->real_v) c->flops_nominal *= (double)c->n_occ_v / c->n_occ / 4.0;
   {
     double mb = 0, vb = 0, ub = 0;
     for (int k = 0; k < c->n_k; ++k) {
@@ -1275,7 +1294,7 @@ exc_status exchange_energy(exc_ctx* c, const double* w_k, const void* const* rho
     }
   }
   hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
-                     (const void* const*)d_rho, c->n_occ, c->d_eout);
+                     (const void* const*)d_rho, c->n_occ_v, c->d_eout);
   std::vector<double> e(c->n_k);
   hipError_t e1 = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
@@ -1304,12 +1323,12 @@ exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* con
   if (rho_k) HIPCHK(c, hipMemcpyAsync(c->d_erho, rho_k, c->n_k * sizeof(void*), hipMemcpyHostToDevice, st));
   if (rho_k) {
     hipLaunchKernelGGL(energy_kernel, dim3(c->n_k), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
-                       (const void* const*)c->d_erho, c->n_occ, c->d_eout);
+                       (const void* const*)c->d_erho, c->n_occ_v, c->d_eout);
     hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, st, c->d_eout, w_k ? c->d_ewk : nullptr,
                        c->n_k, E_dev);
   } else {                                         // rho = 2 P_occ: one launch
     hipLaunchKernelGGL(energy_diag_kernel, dim3(1), dim3(256), 0, st, c->d_vres, c->d_voff, c->d_knb,
-                       c->n_k, c->n_occ, w_k ? c->d_ewk : nullptr, E_dev);
+                       c->n_k, c->n_occ_v, w_k ? c->d_ewk : nullptr, E_dev);
   }
   HIPCHK(c, hipGetLastError());
   return EXC_OK;

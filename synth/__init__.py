@@ -382,3 +382,35 @@ def m_offsets(cfg: Config, k: int) -> np.ndarray:
     nb = cfg.n_bands[k]
     sizes = [cfg.n_occ * nb * cfg.n_mb(q) for q in range(cfg.n_q)]
     return np.concatenate([[0], np.cumsum(sizes)])[:-1].astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Inversion-symmetric stand-ins: real v(q) and real projections
+# ---------------------------------------------------------------------------
+def coulomb_blocks_real(cfg: Config):
+    """The real parts of ``coulomb_blocks(cfg)``: real symmetric positive definite
+    blocks (the real part of a Hermitian positive definite matrix is one), standing
+    in for the Coulomb matrix of a system with inversion symmetry."""
+    E, D, C = coulomb_blocks(cfg)
+    return ([np.ascontiguousarray(e.real) for e in E], [np.ascontiguousarray(d.real) for d in D],
+            [np.ascontiguousarray(c.real) for c in C])
+
+
+def m_block_real(cfg: Config, k: int, q: int) -> np.ndarray:
+    """Real projections [n_occ][n_b(k)][N_MB(q)]: the real part of ``m_block``."""
+    return np.ascontiguousarray(m_block(cfg, k, q).real)
+
+
+def pack_real_pairs(m_real: np.ndarray, dtype=np.complex128) -> np.ndarray:
+    """Layout of real bands for the inversion-symmetric entry points: column j is
+    the complex number M[2j] + i M[2j+1] (a zero band completes an odd count)."""
+    n = m_real.shape[0]
+    out = np.zeros(((n + 1) // 2,) + m_real.shape[1:], dtype=dtype)
+    out.real = m_real[0::2]
+    out.imag[: n // 2] = m_real[1::2]
+    return out
+
+
+def m_all_real_packed(cfg: Config, k: int, dtype=np.complex128) -> np.ndarray:
+    """``pack_real_pairs`` of every q block of k, concatenated in mesh order (flat)."""
+    return np.concatenate([pack_real_pairs(m_block_real(cfg, k, q), dtype).ravel() for q in range(cfg.n_q)])
