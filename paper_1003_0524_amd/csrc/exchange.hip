@@ -73,6 +73,7 @@ struct FusedKCfg {
   void (*fn)(FusedArgs);
   size_t lds;
   int id;
+  bool realf = false;               // real factor only (inversion-symmetric contexts)
 };
 
 #define FCFG(MODE, RTW, NCT, NB8M, KC, ID)                                                       \
@@ -82,6 +83,12 @@ struct FusedKCfg {
 #define FCFG2(MODE, RTW, NCT, NB8M, ID)                                                          \
   FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2>,       \
             FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID}
+
+// real-factor instances (inversion symmetry): the same kernels without the
+// products with the factor's zero imaginary parts
+#define FCFG2R(MODE, RTW, NCT, NB8M, ID)                                                         \
+  FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2, true>, \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID, true}
 
 // Listed in order of preference among equal band-tile capacity (the two-per-CU
 // instances first: they hide more memory latency).
@@ -99,6 +106,9 @@ const FusedKCfg kFused[] = {
     FCFG(M_BF16X6, 3, 12, 3, 32, 140), FCFG(M_BF16X6, 5, 6, 3, 32, 144),
     FCFG(M_BF16X6, 4, 8, 8, 32, 141),  FCFG(M_BF16X6, 2, 13, 13, 32, 143),
     FCFG(M_BF16X6, 2, 16, 16, 32, 142),
+    FCFG2R(M_F32, 2, 6, 3, 250),       FCFG2R(M_F32, 3, 6, 3, 251),
+    FCFG2R(M_BF16X3, 2, 6, 3, 260),    FCFG2R(M_BF16X3, 3, 6, 3, 261),
+    FCFG2R(M_BF16X6, 2, 6, 3, 270),    FCFG2R(M_BF16X6, 3, 6, 3, 271),
 };
 
 struct Plan {
@@ -426,16 +436,22 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
   return EXC_OK;
 }
 
-const FusedKCfg* pick_fused(int mode, int nbt_max) {
+// Real-factor instances serve only contexts with a real factor; there they are
+// preferred over the general ones of the same capacity.
+bool fused_fits(const FusedKCfg& k, int mode, int nbt_max, bool real) {
+  return k.mode == mode && k.NB8M >= nbt_max && k.NCT >= nbt_max && (real || !k.realf);
+}
+
+const FusedKCfg* pick_fused(int mode, int nbt_max, bool real) {
   const FusedKCfg* best = nullptr;
   if (const char* ev = getenv("EXC_FUSED_CFG")) {      // a fixed configuration id (tuning runs)
     const int id = atoi(ev);
     for (const auto& k : kFused)
-      if (k.id == id && k.mode == mode && k.NB8M >= nbt_max && k.NCT >= nbt_max) return &k;
+      if (k.id == id && fused_fits(k, mode, nbt_max, real)) return &k;
   }
   for (const auto& k : kFused) {
-    if (k.mode != mode || k.NB8M < nbt_max || k.NCT < nbt_max) continue;
-    if (!best || k.NB8M < best->NB8M) best = &k;
+    if (!fused_fits(k, mode, nbt_max, real)) continue;
+    if (!best || k.NB8M < best->NB8M || (k.NB8M == best->NB8M && k.realf && !best->realf)) best = &k;
   }
   return best;
 }
@@ -783,9 +799,9 @@ std::string tune_key(const exc_ctx* c, int dtype) {
   for (int q = 0; q < c->n_q; ++q) nmb += c->nmb[q];
   for (int k = 0; k < c->n_k; ++k) nbs += c->nb[k];
   char buf[256];
-  snprintf(buf, sizeof buf, "v1 prec=%d form=%d dtype=%d nk=%d nq=%d nocc=%d nbt=%d nmb_avg=%ld nb_avg=%ld ns=%d",
+  snprintf(buf, sizeof buf, "v1 prec=%d form=%d dtype=%d nk=%d nq=%d nocc=%d nbt=%d nmb_avg=%ld nb_avg=%ld ns=%d%s",
            c->precision, c->form, dtype, c->n_k, c->n_q, c->n_occ, c->nbt_max, nmb / std::max(1, c->n_q),
-           nbs / std::max(1, c->n_k), c->n_s);
+           nbs / std::max(1, c->n_k), c->n_s, c->real_v ? " real" : "");
   return buf;
 }
 
@@ -796,7 +812,7 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
   std::vector<const FusedKCfg*> cands;
   if (c->fused_ok)
     for (const auto& k : kFused)
-      if (k.mode == c->precision && k.NB8M >= c->nbt_max && k.NCT >= c->nbt_max) cands.push_back(&k);
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v)) cands.push_back(&k);
   cands.push_back(nullptr);                      // block-sparse + tile kernels
   const std::string key = tune_key(c, dtype);
   const char* cache = getenv("EXC_TUNE_CACHE");
@@ -952,7 +968,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (!c->cfg) { fail(c, EXC_EUNSUPPORTED, "no tile configuration for n_b = %d", c->nb_max); return bail(EXC_EUNSUPPORTED); }
   if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
     const char* ev = getenv("EXC_FUSED");
-    c->fcfg = pick_fused(c->precision, c->nbt_max);
+    c->fcfg = pick_fused(c->precision, c->nbt_max, c->real_v);
     c->fused_ok = c->fcfg && sparse_chunks(c, row_chan, c->h_schunk);
     if (!c->fused_ok) c->h_schunk.clear();
     c->fused = c->fused_ok && !(ev && ev[0] == '0');

@@ -185,7 +185,9 @@ struct FusedCfg {
   static_assert(CPW * MPC == 64, "one multipole block load per wavefront and sparse step");
 };
 
-template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
+// REALF: the factor and the channel couplings are real (inversion symmetry): the
+// products with their imaginary parts, which are zero, are left out.
+template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1, bool REALF = false>
 __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
   using C = FusedCfg<MODE, RTW, NCT, NB8M, KC, CBX, OCC>;
   using lds_t = typename C::lds_t;
@@ -473,8 +475,13 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
             const double2 xm = Mp[j * MPC + rd.mloc];
-            y[j].x = rd.lc.x * xm.x - rd.lc.y * xm.y;
-            y[j].y = rd.lc.x * xm.y + rd.lc.y * xm.x;
+            if constexpr (REALF) {
+              y[j].x = rd.lc.x * xm.x;
+              y[j].y = rd.lc.x * xm.y;
+            } else {
+              y[j].x = rd.lc.x * xm.x - rd.lc.y * xm.y;
+              y[j].y = rd.lc.x * xm.y + rd.lc.y * xm.x;
+            }
           }
           // Term t: coefficient L_c[i+t][i] (zero past the row's run, in the table) times
           // the value of row r + t, which xs holds after t shifts (zero past the chunk:
@@ -484,9 +491,11 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
               y[j].x = fma(l.x, xs[j].x, y[j].x);
-              y[j].x = fma(l.y, xs[j].y, y[j].x);
               y[j].y = fma(l.x, xs[j].y, y[j].y);
-              y[j].y = fma(-l.y, xs[j].x, y[j].y);
+              if constexpr (!REALF) {
+                y[j].x = fma(l.y, xs[j].y, y[j].x);
+                y[j].y = fma(-l.y, xs[j].x, y[j].y);
+              }
               xs[j] = shift_down1(xs[j]);
             }
           };
@@ -633,7 +642,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
             for (int ks = 0; ks < KC / KS; ++ks)
 #pragma unroll
-              for (int h = 0; h < 2; ++h)
+              for (int h = 0; h < (REALF ? 1 : 2); ++h)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
                   u[ii][ks][h][p] = buf_load<op_t>(urs, u_lane,
@@ -677,12 +686,13 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             };
             op_t bA[NP], bB[NP];
             bload(0, bA);
+            constexpr int NHJ = (REALF ? 1 : 2) * NCT;      // a real factor has no Bi products
 #pragma unroll
-            for (int hj = 0; hj < 2 * NCT; ++hj) {
+            for (int hj = 0; hj < NHJ; ++hj) {
               const int h = hj / NCT, j = hj % NCT;
               op_t (&bc)[NP] = (hj & 1) ? bB : bA;
               op_t (&bn)[NP] = (hj & 1) ? bA : bB;
-              if (hj + 1 < 2 * NCT) bload(hj + 1, bn);
+              if (hj + 1 < NHJ) bload(hj + 1, bn);
               // products outer, tiles inner: consecutive MFMAs use different accumulators
 #pragma unroll
               for (int pr = 0; pr < C::T::NPROD; ++pr)

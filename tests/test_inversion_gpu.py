@@ -105,3 +105,45 @@ def test_real_variant_energy_and_accounting():
                        precision="fp64", form="herk", batched=True)
     assert nominal == pytest.approx(exc.query(1) / 4.0, rel=1e-12)
     exc.close()
+
+
+REAL_IDS = {"fp32": (250, 251), "bf16x3": (260, 261), "bf16x6": (270, 271)}
+COMPLEX_TWIN = {250: 150, 251: 151, 260: 160, 261: 161, 270: 170, 271: 171}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("name", ["small", "c1"])          # (the real-factor instances hold <= 3 band tiles)
+def test_real_factor_instances(name, precision, monkeypatch):
+    """Each real-factor instance (products with the zero imaginary parts of the factor left
+    out) gives bitwise the result of its general twin on the same real inputs."""
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_TUNE_CACHE", raising=False)
+    cfg = _case(name)[0]
+    for cid in REAL_IDS[precision]:
+        out = {}
+        for use in (cid, COMPLEX_TWIN[cid]):
+            monkeypatch.setenv("EXC_FUSED_CFG", str(use))
+            _, ex, Vs = _run(name, precision)
+            assert int(ex.query(3)) == use
+            ex.close()
+            out[use] = Vs
+        for k in range(cfg.n_k):
+            assert np.array_equal(out[cid][k], out[COMPLEX_TWIN[cid]][k]), (name, precision, cid, k)
+
+
+def test_autotuner_prefers_real_factor_instances(monkeypatch):
+    monkeypatch.delenv("EXC_FUSED_CFG", raising=False)
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_TUNE_CACHE", raising=False)
+    _, ex, _ = _run("small", "bf16x3")
+    chosen = int(ex.query(3))
+    ex.close()
+    # a real context may run any fused instance that fits (all are exact for a real factor);
+    # the default choice before tuning is a real-factor one
+    import paper_1003_0524_amd as lib
+    cfg, E, D, C, v = _case("small")
+    ex2 = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                       precision="bf16x3", form="herk", batched=True, inversion=True)
+    assert int(ex2.query(3)) in REAL_IDS["bf16x3"]
+    ex2.close()
+    assert chosen > 0
