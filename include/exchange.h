@@ -105,6 +105,15 @@ typedef struct {
                                Since v is real, Re(Y^H Y) of a packed column is the sum of
                                the two bands' Y^T Y: half the columns, half the bytes.
                                0: general complex system                                 */
+  const double *w_kq;       /* [n_k * n_q] (k-major) weight of each (k, q) pair, host
+                               memory, or NULL for w_q of every k. A zero weight leaves
+                               the pair out: its q block is then absent from M(k) (the
+                               remaining blocks keep mesh order). For the q sum over the
+                               extended irreducible wedge EIBZ(k) (Sec. II.D, eq. "rotate
+                               APW"): w_q / N_{k,q} on the wedge, 0 elsewhere; summing the
+                               result rotated by the operations of the little group of k
+                               gives the full sum. Every k needs one nonzero weight
+                               (EXC_EINVAL otherwise).                                   */
 } exc_desc;
 
 typedef struct {

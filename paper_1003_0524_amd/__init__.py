@@ -49,7 +49,8 @@ class _Desc(ctypes.Structure):
                 ("n_bands", ctypes.POINTER(ctypes.c_int32)), ("n_pw", ctypes.POINTER(ctypes.c_int32)),
                 ("ch_nrad", ctypes.POINTER(ctypes.c_int32)), ("w_q", ctypes.POINTER(ctypes.c_double)),
                 ("precision", ctypes.c_int32), ("form", ctypes.c_int32), ("batched", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("inversion", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("inversion", ctypes.c_int32),
+                ("w_kq", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Coulomb(ctypes.Structure):
@@ -128,9 +129,10 @@ class Exchange:
     def __init__(self, n_bands: Sequence[int], n_pw: Sequence[int], ch_nrad: Sequence[int],
                  n_occ: int, E: Sequence[np.ndarray], D: Sequence[np.ndarray], C: Sequence[np.ndarray],
                  w_q: Optional[Sequence[float]] = None, precision: str = "fp64", form: str = "herk",
-                 batched: bool = True, device: int = 0, inversion: bool = False):
+                 batched: bool = True, device: int = 0, inversion: bool = False, w_kq=None):
         """inversion=True: real v and real bands; M packs bands 2j, 2j+1 as the real and imaginary
-        parts of column j (``synth.pack_real_pairs``) and V(k) comes back real (Im = 0)."""
+        parts of column j (``synth.pack_real_pairs``) and V(k) comes back real (Im = 0).
+        w_kq: [n_k][n_q] pair weights (0 leaves the pair out and its q block out of M(k))."""
         import torch
         if not torch.cuda.is_available():
             raise ExchangeError(-5, "no GPU visible: the exchange library runs only on a HIP device")
@@ -149,11 +151,16 @@ class Exchange:
         wq_arr = None
         if w_q is not None:
             wq_arr = np.ascontiguousarray(np.asarray(w_q, dtype=np.float64))
+        wkq_arr = None
+        if w_kq is not None:
+            wkq_arr = np.ascontiguousarray(np.asarray(w_kq, dtype=np.float64).reshape(self.n_k, self.n_q))
+        self.pair_used = (np.ones((self.n_k, self.n_q), dtype=bool) if wkq_arr is None else wkq_arr != 0.0)
         desc = _Desc(self.n_k, self.n_q, self.n_occ, len(ch_nrad), nb_p, pw_p,
                      ch_p if len(ch_nrad) else None,
                      wq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wq_arr is not None else None,
                      PRECISIONS[precision], FORMS[form], 1 if batched else 0, device,
-                     1 if self.inversion else 0)
+                     1 if self.inversion else 0,
+                     wkq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wkq_arr is not None else None)
         e_host = [np.ascontiguousarray(np.asarray(e, dtype=np.complex128).T) for e in E]  # column-major
         e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.ctypes.data for e in e_host])
         d_cat = np.concatenate([np.asarray(d, np.complex128).T.ravel() for d in D] + [np.zeros(0, np.complex128)])
@@ -169,7 +176,7 @@ class Exchange:
         if st != 0:
             raise ExchangeError(st, self.lib.exchange_last_error(None).decode())
         self.ctx = ctx
-        self._keep = (nb_arr, pw_arr, ch_arr, wq_arr)
+        self._keep = (nb_arr, pw_arr, ch_arr, wq_arr, wkq_arr)
 
     # -- helpers -----------------------------------------------------------
     def _check(self, st):
@@ -185,7 +192,7 @@ class Exchange:
         raise ExchangeError(-1, f"M must be complex64 or complex128, got {M.dtype}")
 
     def m_elems(self, k: int, n_mb: Sequence[int]) -> int:
-        return int(sum(self.n_cols * self.n_bands[k] * int(n) for n in n_mb))
+        return int(sum(self.n_cols * self.n_bands[k] * int(n) for q, n in enumerate(n_mb) if self.pair_used[k, q]))
 
     # -- API ---------------------------------------------------------------
     def matrix(self, k: int, M, out=None):

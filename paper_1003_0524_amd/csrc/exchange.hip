@@ -143,6 +143,7 @@ struct exc_ctx {
   bool real_v = false;                // inversion symmetry: V = Re of the packed product
   std::vector<int> nb, npw, nrad, nd, nmb;
   std::vector<double> wq;
+  std::vector<double> wkq;            // [n_k * n_q] weight of pair (k, q); 0: pair not computed
   int n_s = 0, nb_max = 0, nbt_max = 0, ns_pad = 0;
   std::vector<int> ch_off, ch_len;
   std::vector<int64_t> ch_coef;
@@ -165,6 +166,7 @@ struct exc_ctx {
   std::vector<PairInfo> pairs;
   PairInfo* d_pairs = nullptr;
   std::vector<int> k_pair;            // [n_k + 1]
+  std::vector<int64_t> m_len;         // [n_k] elements of M(k) (the blocks of its pairs)
   std::vector<double> pair_w;
   double* d_pair_w = nullptr;
   int32_t* d_pair_begin = nullptr;
@@ -377,7 +379,7 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
           for (int rb = rb0; rb < rb1; ++rb) cs += block_cost(c, p, rb, std::min(ngc, g1 - g) * p.nb8);
         }
         P.items.push_back(w);
-        P.slot_w.push_back(c->wq[p.q]);
+        P.slot_w.push_back(c->pair_w[pidx]);     // the pair's weight (w_kq, else w_q)
         cost.push_back(cs);
       };
       if (!split_rows) {
@@ -912,6 +914,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (d->w_q)
     for (int q = 0; q < d->n_q; ++q)
       if (!std::isfinite(d->w_q[q])) return fail(nullptr, EXC_EINVAL, "w_q[%d] not finite", q);
+  if (d->w_kq)
+    for (long i = 0; i < (long)d->n_k * d->n_q; ++i)
+      if (!std::isfinite(d->w_kq[i])) return fail(nullptr, EXC_EINVAL, "w_kq[%ld] not finite", i);
 
   exc_ctx* c = new (std::nothrow) exc_ctx();
   if (!c) return fail(nullptr, EXC_ENOMEM, "host allocation failed");
@@ -946,6 +951,10 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (c->n_ch) c->nrad.assign(d->ch_nrad, d->ch_nrad + c->n_ch);
   c->wq.resize(c->n_q);
   for (int q = 0; q < c->n_q; ++q) c->wq[q] = d->w_q ? d->w_q[q] : 1.0 / c->n_q;
+  c->wkq.resize((size_t)c->n_k * c->n_q);
+  for (int k = 0; k < c->n_k; ++k)
+    for (int q = 0; q < c->n_q; ++q)
+      c->wkq[(size_t)k * c->n_q + q] = d->w_kq ? d->w_kq[(size_t)k * c->n_q + q] : c->wq[q];
 
   IHIP(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
@@ -1118,6 +1127,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   for (int k = 0; k < c->n_k; ++k) {
     int64_t moff = 0;
     for (int q = 0; q < c->n_q; ++q) {
+      const double wpair = c->wkq[(size_t)k * c->n_q + q];
+      if (wpair == 0.0) continue;       // not computed; its block is absent from M
       PairInfo p{};
       p.k = k; p.q = q; p.nb = c->nb[k]; p.nmb = c->nmb[q]; p.nd = c->nd[q];
       p.nsb = (c->n_s + BM - 1) / BM; p.ndb = (c->nd[q] + BM - 1) / BM;
@@ -1128,7 +1139,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       moff += (int64_t)c->n_occ * p.nb * p.nmb;
       ws_total += (int64_t)c->n_occ * p.nb * ldw * ws_cols;
       c->pairs.push_back(p);
-      c->pair_w.push_back(c->wq[q]);
+      c->pair_w.push_back(wpair);
       // accounting (nominal: sparse-aware method, Hermitian upper triangle)
       const double R = (double)c->n_occ * p.nb;
       double sp = 0;
@@ -1141,8 +1152,14 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         c->flops_exec += 8.0 * p.nd * (double)p.nd * R + 4.0 * p.nb * (p.nb + 1.0) * p.nmb * c->n_occ;
     }
     m_max = std::max(m_max, moff);
+    c->m_len.push_back(moff);
     c->k_pair.push_back((int)c->pairs.size());
   }
+  for (int k = 0; k < c->n_k; ++k)
+    if (c->k_pair[k + 1] == c->k_pair[k]) {
+      fail(c, EXC_EINVAL, "w_kq leaves no q for k = %d", k);
+      return bail(EXC_EINVAL);
+    }
   // with inversion symmetry the method works in real arithmetic (2 flops per multiply-add
   // instead of 8) on n_occ_v real bands
   if (c->real_v) c->flops_nominal *= (double)c->n_occ_v / c->n_occ / 4.0;
@@ -1150,11 +1167,16 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     double mb = 0, vb = 0, ub = 0;
     for (int k = 0; k < c->n_k; ++k) {
       int64_t e = 0;
-      for (int q = 0; q < c->n_q; ++q) e += (int64_t)c->n_occ * c->nb[k] * c->nmb[q];
+      for (int q = 0; q < c->n_q; ++q)
+        if (c->wkq[(size_t)k * c->n_q + q] != 0.0) e += (int64_t)c->n_occ * c->nb[k] * c->nmb[q];
       mb += (double)e;
       vb += (double)c->nb[k] * c->nb[k] * 16.0;
     }
-    for (int q = 0; q < c->n_q; ++q) ub += (double)c->nd[q] * c->nd[q] * 16.0;   // v(q) dense block once
+    for (int q = 0; q < c->n_q; ++q) {                // v(q) dense block once, if some k uses q
+      bool used = false;
+      for (int k = 0; k < c->n_k; ++k) used = used || c->wkq[(size_t)k * c->n_q + q] != 0.0;
+      if (used) ub += (double)c->nd[q] * c->nd[q] * 16.0;
+    }
     c->bytes_alg = mb * 16.0 + ub + vb;   // per complex128 M; the binding rescales for complex64
   }
   c->mstage_bytes = (size_t)m_max * 16;
@@ -1215,13 +1237,12 @@ exc_status exchange_matrix(exc_ctx* c, int32_t k, const void* M, int32_t dtype, 
   c->last_stream = st;
   HIPCHK(c, hipSetDevice(c->device));
   const size_t esz = dtype == EXC_C64 ? 8 : 16;
-  const size_t mbytes = (size_t)(c->pairs[c->k_pair[k + 1] - 1].m_off +
-                                 (int64_t)c->n_occ * c->nb[k] * c->nmb[c->n_q - 1]) * esz;
+  const size_t mbytes = (size_t)c->m_len[k] * esz;
   const void* Md = M;
   void* Vd = Vx;
   if (!on_device) {
     TRY(ensure_stage(c));
-    HIPCHK(c, hipMemcpyAsync(c->d_mstage, M, mbytes, hipMemcpyHostToDevice, st));
+    if (mbytes) HIPCHK(c, hipMemcpyAsync(c->d_mstage, M, mbytes, hipMemcpyHostToDevice, st));
     Md = c->d_mstage;
     Vd = nullptr;
   }
