@@ -84,6 +84,7 @@ def main() -> int:
     ap.add_argument("--no-gamma", action="store_true", help="skip timing the Gamma-point lattice sum")
     ap.add_argument("--no-inversion", action="store_true", help="skip the inversion-symmetric variant")
     ap.add_argument("--no-eibz", action="store_true", help="skip the EIBZ-restricted q sum")
+    ap.add_argument("--no-backx", action="store_true", help="skip timing the back-transform to the LAPW basis")
     ap.add_argument("--only", default=None, help="run a single batched mode (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scales HBM byte counters)")
@@ -166,6 +167,7 @@ def main() -> int:
     if int(np.prod(mesh)) != cfg.n_q:
         mesh = None
     gamma = None
+    btx = None
 
     results = {}
     modes = [args.only] if args.only else ["plain", "fp64"] + [m for m in args.modes.split(",") if m]
@@ -198,6 +200,31 @@ def main() -> int:
                      "kernel_ms": round(float(np.mean(kms)), 5),
                      "terms_per_s": round(n_terms / (float(np.mean(kms)) * 1e-3), 1)}
             log(f"[bench] gamma term: C = {c_gamma:.12f}, {n_terms} terms, lattice-sum kernel {gamma['kernel_ms']:.4f} ms")
+        if btx is None and mode == "fp64" and not args.no_backx:
+            # back-transform of V(k=0) to an LAPW basis of n_G functions (synthetic Z = S c)
+            btx = []
+            rng = np.random.default_rng(20)
+            for nG in (400, 2000):
+                nb0 = cfg.n_bands[0]
+                Zh = rng.standard_normal((nG, nb0)) + 1j * rng.standard_normal((nG, nb0))
+                Zd = torch.from_numpy(np.ascontiguousarray(Zh.T)).to(dev).T
+                VG = torch.empty(nG * nG, dtype=torch.complex128, device=dev)
+                ex.back_transform(0, Zd, VG)
+                kms = []
+                for _ in range(5):
+                    ex.back_transform(0, Zd, VG)
+                    kms.append(ex.query(13))
+                t_k = float(np.mean(kms))
+                fl, by = 8.0 * nG * nG * nb0, 16.0 * nG * nG + 2 * 16.0 * nG * nb0
+                ridge = PEAK_TFLOPS["fp64"] * 1e12 / (HBM_PEAK_GBS * 1e9)
+                bound = "mfma" if fl / by >= ridge else "hbm"
+                frac = (fl / (t_k * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"] if bound == "mfma"
+                        else by / (t_k * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                btx.append({"n_G": nG, "n_b": nb0, "kernel_ms": round(t_k, 5), "bound": bound,
+                            "tflops": round(fl / (t_k * 1e-3) / 1e12, 3),
+                            "gbps": round(by / (t_k * 1e-3) / 1e9, 1), "frac": round(frac, 4)})
+                log(f"[bench] back-transform n_G={nG}: product kernel {t_k:.4f} ms, "
+                    f"{btx[-1]['tflops']} TFLOP/s, {btx[-1]['gbps']} GB/s ({bound}-bound, {frac:.2%})")
         ex.close()
 
     # errors against the float64 oracle (all k)
@@ -354,7 +381,7 @@ def main() -> int:
         "err_eig_ha": H["err_eig_ha"], "err_normwise": H["err_norm"],
         "init_ms": round(H["init_ms"], 2),
         "roofline": roof, "cpu_baseline": cpu, "sparse_rows": sparse, "gamma_term": gamma,
-        "inversion_variant": inv, "eibz_q_sum": eibz,
+        "inversion_variant": inv, "eibz_q_sum": eibz, "back_transform": btx,
         "modes": {m: {"ms_per_step": round(r["ms"], 5),
                       "gflops": round(r["flops_nom"] / (r["ms"] * 1e-3) / 1e9, 3),
                       "err_eig_ha": r["err_eig_ha"], "err_normwise": r["err_norm"],

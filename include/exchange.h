@@ -7,12 +7,12 @@
  *
  *   V_{nn'}(k) = - sum_q w_q sum_{n'' occ} sum_{IJ} conj(M^{n n''}_I(k,q)) v_IJ(q) M^{n' n''}_J(k,q)
  *
- * (Sec. II.C, eq. "vec-mat-vec"; the q sum is the Brillouin-zone integration
- * on the k mesh of Sec. I; v is the Coulomb matrix of the mixed product basis,
+ * (Sec. III.C, eq. "vec-mat-vec"; the q sum is the Brillouin-zone integration
+ * on the k mesh of Sec. II; v is the Coulomb matrix of the mixed product basis,
  * eq. "coulomb matrix").
  *
  * Coulomb matrix layout (the transformed, sparse mixed product basis of
- * Sec. II.C and its Fig. 1): the basis index I runs over
+ * Sec. III.C and its Fig. 1): the basis index I runs over
  *   [ multipole-free MT functions, channel 0, channel 1, ... ]   N_s = sum_c (nrad_c - 1)
  *   [ one multipole-carrying MT function per channel ]            n_channels
  *   [ interstitial plane waves of q ]                            n_pw[q]
@@ -95,7 +95,7 @@ typedef struct {
                                (k,q) work captured in a HIP graph; 0 = one launch per
                                (k,q) pair, no graph                                      */
   int32_t device;           /* HIP device ordinal                                        */
-  int32_t inversion;        /* 1: inversion-symmetric system (Sec. II.D, symmetrized MT
+  int32_t inversion;        /* 1: inversion-symmetric system (Sec. III.D, symmetrized MT
                                functions): v(q) and the projections are real. Only the
                                real parts of E, D and C are read. M holds the n_occ real
                                bands in pairs: column j of a q block is the complex number
@@ -109,7 +109,7 @@ typedef struct {
                                memory, or NULL for w_q of every k. A zero weight leaves
                                the pair out: its q block is then absent from M(k) (the
                                remaining blocks keep mesh order). For the q sum over the
-                               extended irreducible wedge EIBZ(k) (Sec. II.D, eq. "rotate
+                               extended irreducible wedge EIBZ(k) (Sec. III.D, eq. "rotate
                                APW"): w_q / N_{k,q} on the wedge, 0 elsewhere; summing the
                                result rotated by the operations of the little group of k
                                gives the full sum. Every k needs one nonzero weight
@@ -126,7 +126,7 @@ typedef struct {
 /*
  * exchange_init -- validate sizes, copy v(q) to device memory and prepare it.
  * The Coulomb matrix is independent of the wavefunctions and is prepared once
- * per self-consistency cycle (Sec. II.C, after eq. "coulomb matrix"). With
+ * per self-consistency cycle (Sec. III.C, after eq. "coulomb matrix"). With
  * form = EXC_FORM_CHOL_HERK it is Cholesky-factored in FP64 on the GPU here;
  * a non-positive pivot returns EXC_ENOTPD (the message names q). The caller's
  * buffers may be freed after return. *out receives the new context (NULL on
@@ -137,7 +137,7 @@ exc_status exchange_init(const exc_desc *desc, const exc_coulomb *coulomb, void 
 
 /*
  * exchange_matrix -- V^x(k) for one irreducible k, summed over every q of the
- * mesh (eq. "vec-mat-vec" with the band cutoff n, n' < n_b(k), Sec. II).
+ * mesh (eq. "vec-mat-vec" with the band cutoff n, n' < n_b(k), Sec. III).
  *   M  : the q blocks of k concatenated in mesh order; block q is
  *        [n''< n_occ][n < n_b(k)][I < N_MB(q)] (I fastest), element type `dtype`,
  *        holding M^{n n''}_I(k,q) = <M_I^q phi_{n'' k-q} | phi_{n k}>.
@@ -186,7 +186,7 @@ exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *c
                                   double *E_dev, void *stream);
 
 /*
- * exchange_gamma_term -- the q -> 0 term of the exchange matrix (Sec. II.D,
+ * exchange_gamma_term -- the q -> 0 term of the exchange matrix (Sec. III.E,
  * eqs. "F(q)", "divergence" and "div final"). The divergent 1/q^2 part of the
  * Coulomb matrix, damped by exp(-beta q^2), is integrated analytically and the
  * part of that integral the q-mesh sum already holds is subtracted:
@@ -211,6 +211,24 @@ exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *c
  */
 exc_status exchange_gamma_term(exc_ctx *ctx, const double *recip, const int32_t *mesh, double beta,
                                int32_t apply, double *C_out, void *stream);
+
+/*
+ * exchange_back_transform -- V^x(k) in the LAPW basis (Sec. III.A, eq. "APW trafo"):
+ *   VGG = Z V(k) Z^H,   Z = S(k) c(k),
+ * S the overlap matrix and c the (generalized orthonormal, c^H S c = 1) eigenvectors of
+ * the n_b(k) bands, so that Z V Z^H multiplies V by the inverse of c and its adjoint.
+ * (The printed left factor carries S* with S's indices; for the Hermitian S its
+ * adjoint's elements are read, which keeps VGG Hermitian.)
+ *   Z   : device, n_G x n_b(k) complex128, column-major (leading dimension n_G)
+ *   VGG : device, n_G x n_G complex128, column-major, every element written
+ * V(k) is the resident result of the last exchange_matrix[_all]. Asynchronous on
+ * `stream` (ordered after that work); Z and VGG must stay valid until it completes.
+ * A workspace of n_G x n_b(k) complex128 is kept by the context and grown when a
+ * larger one is needed (the growth synchronises the device). EXC_EINVAL for a bad k,
+ * NULL pointers or n_G outside [1, 2^22]; EXC_ESTATE if V(k) was never computed.
+ */
+exc_status exchange_back_transform(exc_ctx *ctx, int32_t k, const void *Z, int32_t n_G, void *VGG,
+                                   void *stream);
 
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx == NULL,
  * the message of the last failed exchange_init on this thread. */
@@ -237,6 +255,8 @@ void exchange_destroy(exc_ctx *ctx);
  *             (M read once, v(q) read once, Vx written once)
  *   what = 11: duration (ms, HIP events) of the lattice-sum kernel of the last
  *              exchange_gamma_term; what = 12: its number of terms
+ *   what = 13: duration (ms, HIP events) of the product kernel of the last
+ *              exchange_back_transform (waits for it)
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);

@@ -13,11 +13,11 @@ arithmetic).
 Modules
 -------
 vx         -- the exchange matrix as defined by the vector-matrix-vector form
-              (Sec. II.C, eq. "vec-mat-vec") with a dense Coulomb matrix, and the
-              exchange energy (Sec. I/II, eq. "HF exchange energy").
+              (Sec. III.C, eq. "vec-mat-vec") with a dense Coulomb matrix, and the
+              exchange energy (Sec. II, eq. "HF exchange energy").
 brute      -- the same definition as literal nested loops for tiny sizes.
 transform  -- the multipole-moment rotation that makes the Coulomb matrix sparse
-              (Sec. II.C, the two-function unitary transformation).
+              (Sec. III.C, the two-function unitary transformation).
 chol       -- Cholesky factor of v(q) and V = -sum Y^H Y (exact re-arrangement).
 precision  -- input-rounding emulation of the FP32 / split-BF16 product modes.
 mlp        -- float64 reference of the small MLP (forward, backward, Adam).

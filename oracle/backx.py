@@ -1,6 +1,6 @@
 """Back-transform of the exchange matrix to the LAPW basis (test infrastructure only).
 
-Sec. II.B, eq. "APW trafo": V^x in the basis functions G is the band-space V^x
+Sec. III.A, eq. "APW trafo": V^x in the basis functions G is the band-space V^x
 multiplied on the left by the inverse of the eigenvector matrix's adjoint and on
 the right by the inverse of the eigenvectors. With generalized orthonormal
 eigenvectors (c^H S c = 1) that inverse is c^H S, so

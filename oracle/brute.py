@@ -1,6 +1,6 @@
 """Brute-force exchange matrix: the literal nested sum (test infrastructure only).
 
-Writes out eq. "vec-mat-vec" (Sec. II.C) term by term in pure Python:
+Writes out eq. "vec-mat-vec" (Sec. III.C) term by term in pure Python:
 
     V_{nn'}(k) = - sum_q w_q sum_{n''} sum_I sum_J conj(M[q][n''][n][I]) v[q][I][J] M[q][n''][n'][J]
 

@@ -1,6 +1,6 @@
 """Gamma-point term of the exchange matrix (test infrastructure only).
 
-The Coulomb matrix diverges like 1/q^2 at q = 0 (Sec. II.D, "Singularity of the
+The Coulomb matrix diverges like 1/q^2 at q = 0 (Sec. III.E, "Singularity of the
 Coulomb matrix"). Its divergent part, taken in the plane-wave representation
 exp(iq.r) and with the overlaps reduced to Kronecker deltas near q = 0, adds to
 the occupied diagonal of V^x a term that is integrated analytically once 1/q^2
@@ -31,7 +31,7 @@ import numpy as np
 
 
 def q0_of_beta(beta: float) -> float:
-    """Cutoff with exp(-beta q0^2) = beta (Sec. II.D, after eq. "div final")."""
+    """Cutoff with exp(-beta q0^2) = beta (Sec. III.E, after eq. "div final")."""
     if not 0.0 < beta < 1.0:
         raise ValueError("beta must lie in (0, 1)")
     return math.sqrt(-math.log(beta) / beta)

@@ -1,6 +1,6 @@
 """Float64 reference of the learned extrapolator's encoding -- TEST INFRASTRUCTURE ONLY.
 
-Between exact evaluations of V^x (Sec. II.C) the extension predicts the change
+Between exact evaluations of V^x (Sec. III.C) the extension predicts the change
 of V^x(k) caused by a change of the density matrix. V^x is linear in the
 density matrix for fixed product-basis projections, so the map to learn is
 dV = L(dP). The network sees a fixed-size encoding of dP and returns a

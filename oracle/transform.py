@@ -1,6 +1,6 @@
 """Multipole-moment rotation of the MT functions (test infrastructure only).
 
-Sec. II.C ("Sparsity of the Coulomb matrix"): within one atom and LM channel,
+Sec. III.C ("Sparsity of the Coulomb matrix"): within one atom and LM channel,
 the radial MT functions M_{aLP}(r) have multipole moments
 mu_{aLP} = int_0^S M_{aLP}(r) r^{L+2} dr. A real orthogonal change of basis of
 the functions of a channel can leave only one function with a nonzero moment;

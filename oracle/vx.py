@@ -1,13 +1,13 @@
 """Oracle: the exchange matrix V^x(k) from its definition (test infrastructure only).
 
-Definition (Sec. II.C, eq. "vec-mat-vec"):
+Definition (Sec. III.C, eq. "vec-mat-vec"):
 
     V_{nn'}(k) = - sum_q w_q sum_{n'' occ} sum_{IJ} conj(M^{n n''}_I(k,q)) v_IJ(q) M^{n' n''}_J(k,q)
 
 where M^{n n''}_I(k,q) is the MPB projection of the wavefunction product
 (M_I^q phi_{n'' k-q} | phi_{n k}) and v(q) the Coulomb matrix of the MPB
 (eq. "coulomb matrix"). The q sum is the Brillouin-zone integration on the mesh
-(Sec. I, the sentence following eq. "HF exchange energy"), i.e. a weighted sum
+(Sec. II, the sentence following eq. "HF exchange energy"), i.e. a weighted sum
 with weights w_q (1/N_q on an equidistant mesh).
 
 Readings taken here (each listed in the design doc):
@@ -15,7 +15,7 @@ Readings taken here (each listed in the design doc):
     A_{n''} = M(k,q)[n''] viewed as an N_MB x n_b matrix, V = -sum w_q A^H v A;
   * the occupied set is the same n_occ bands at every k-q, unit occupation per
     spin channel, one spin channel;
-  * the band cutoff n_max (Sec. II) is the column count n_b(k) of M.
+  * the band cutoff n_max (Sec. III) is the column count n_b(k) of M.
 
 Layout of the inputs: ``M`` for one (k,q) is [n_occ][n_b][N_MB] (I fastest).
 The Coulomb matrix is given in the paper's transformed MPB order (Fig. 1):
@@ -31,7 +31,7 @@ __all__ = ["assemble_v", "vx_k", "vx_all", "energy_trace", "energy_direct",
 
 
 def assemble_v(E_q: np.ndarray, D: list, C: list) -> np.ndarray:
-    """Dense v(q) from the sparse block form (Sec. II.C and the Fig. 1 caption).
+    """Dense v(q) from the sparse block form (Sec. III.C and the Fig. 1 caption).
 
     Index order: [mu=0 functions of channel 0, channel 1, ...] (N_s rows), then
     the dense block [multipole function of channel 0..N_ch-1, plane waves].

@@ -30,7 +30,7 @@ DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
-                    "exchange_energy_device", "exchange_gamma_term",
+                    "exchange_energy_device", "exchange_gamma_term", "exchange_back_transform",
                     "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
                     "exchange_nn_init", "exchange_nn_params", "exchange_nn_train", "exchange_nn_grad",
                     "exchange_nn_predict", "exchange_nn_features", "exchange_eigh", "exchange_nn_project",
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_gamma_term.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
                                         ctypes.c_double, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.exchange_gamma_term.restype = i32
+    lib.exchange_back_transform.argtypes = [vp, i32, vp, i32, vp, vp]
+    lib.exchange_back_transform.restype = i32
     lib.exchange_energy_device.restype = i32
     lib.exchange_last_error.argtypes = [vp]
     lib.exchange_last_error.restype = ctypes.c_char_p
@@ -276,6 +278,24 @@ class Exchange:
                                                  m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(beta),
                                                  int(bool(apply)), ctypes.byref(out), st))
         return out.value
+
+    def back_transform(self, k: int, Z, out=None, stream=None):
+        """V^x(k) in the LAPW basis, Z V(k) Z^H (Z = S c: an n_G x n_b(k) complex128 CUDA tensor,
+        row-major [G][n] views are taken as given: pass Z laid out column-major, i.e. Z.T.contiguous().T)."""
+        t = self._torch
+        nG = int(Z.shape[0])
+        if Z.dtype != t.complex128 or not Z.is_cuda or tuple(Z.shape) != (nG, self.n_bands[k]):
+            raise ExchangeError(-1, "Z must be an n_G x n_b(k) complex128 CUDA tensor")
+        nb = self.n_bands[k]
+        if not ((nG == 1 or Z.stride(0) == 1) and (nb == 1 or Z.stride(1) == nG)):
+            raise ExchangeError(-1, "Z must be column-major (strides (1, n_G))")
+        if out is None:
+            out = t.empty(nG * nG, dtype=t.complex128, device=Z.device)
+        st = (ctypes.c_void_p(stream.cuda_stream) if stream is not None
+              else _stream_handle(t, self.device))
+        self._check(self.lib.exchange_back_transform(self.ctx, int(k), ctypes.c_void_p(Z.data_ptr()), nG,
+                                                     ctypes.c_void_p(out.data_ptr()), st))
+        return out.view(nG, nG).T      # column-major -> [G][G'] view
 
     def gamma_kernel_ms(self):
         """(lattice-sum kernel ms, number of terms) of the last gamma_term call."""

@@ -1,7 +1,7 @@
 // C ABI and host runtime of the MI355X nonlocal-exchange library.
 //
 // Computes V^x_{nn'}(k) = - sum_q w_q sum_{n''} A^H v(q) A (the vector-matrix-
-// vector form of Sec. II.C) on one gfx950 GPU. See include/exchange.h for the
+// vector form of Sec. III.C) on one gfx950 GPU. See include/exchange.h for the
 // contract of every entry point.
 #include <hip/hip_runtime.h>
 
@@ -20,6 +20,7 @@
 #include "tile.hpp"
 #include "fused.hpp"
 #include "gamma.hpp"
+#include "backx.hpp"
 
 using namespace exc;
 
@@ -216,6 +217,10 @@ struct exc_ctx {
   hipEvent_t ev_g[2] = {nullptr, nullptr};
   float gamma_ms = 0.f;               // lattice-sum kernel of the last exchange_gamma_term
   double gamma_terms = 0.0;           // its number of terms
+  double2* d_bt = nullptr;            // back-transform workspace T = Z V (grown on demand)
+  size_t bt_cap = 0;
+  hipEvent_t ev_bt[2] = {nullptr, nullptr};
+  bool bt_timed = false;
   hipStream_t last_stream = nullptr;
   // accounting
   double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
@@ -297,13 +302,15 @@ void release(exc_ctx* c) {
   if (c->own) hipStreamDestroy(c->own);
   for (hipEvent_t& e : c->ev_g) if (e) hipEventDestroy(e);
   c->ev_g[0] = c->ev_g[1] = nullptr;
+  for (hipEvent_t& e : c->ev_bt) if (e) hipEventDestroy(e);
+  c->ev_bt[0] = c->ev_bt[1] = nullptr;
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
                   c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
-                  c->d_gamma, c->d_gpartial};
+                  c->d_gamma, c->d_gpartial, c->d_bt};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
@@ -1438,6 +1445,47 @@ exc_status exchange_gamma_term(exc_ctx* c, const double* recip, const int32_t* m
   return EXC_OK;
 }
 
+exc_status exchange_back_transform(exc_ctx* c, int32_t k, const void* Z, int32_t n_G, void* VGG, void* stream) {
+  TRY(check_ctx(c));
+  if (k < 0 || k >= c->n_k) return fail(c, EXC_EINVAL, "k = %d outside [0, %d)", k, c->n_k);
+  if (!Z || !VGG) return fail(c, EXC_EINVAL, "Z or VGG is NULL");
+  if (n_G < 1 || n_G > (1 << 22)) return fail(c, EXC_EINVAL, "n_G = %d outside [1, 2^22]", n_G);
+  if (!c->v_valid[k]) return fail(c, EXC_ESTATE, "V(k=%d) has not been computed", k);
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nb = c->nb[k];
+  const size_t need = (size_t)n_G * nb;
+  if (need > c->bt_cap) {                         // earlier back-transforms may still read the old one
+    if (c->d_bt) {
+      HIPCHK(c, hipDeviceSynchronize());
+      hipFree(c->d_bt);
+      c->d_bt = nullptr;
+      c->bt_cap = 0;
+    }
+    TRY(dalloc(c, &c->d_bt, need));
+    c->bt_cap = need;
+  }
+  if (!c->ev_bt[0]) {
+    HIPCHK(c, hipEventCreate(&c->ev_bt[0]));
+    HIPCHK(c, hipEventCreate(&c->ev_bt[1]));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (c->last_stream && st != c->last_stream) {   // after the work that wrote V(k)
+    HIPCHK(c, hipEventRecord(c->ev_out, c->last_stream));
+    HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
+  }
+  const double2* V = c->d_vres + c->v_off[k];
+  hipLaunchKernelGGL(bt_left_kernel, dim3((unsigned)((n_G + 255) / 256), (unsigned)nb), dim3(256), 0, st,
+                     (const double2*)Z, V, n_G, nb, c->d_bt);
+  const unsigned nt = (unsigned)((n_G + 63) / 64);
+  HIPCHK(c, hipEventRecord(c->ev_bt[0], st));
+  hipLaunchKernelGGL(bt_gram_kernel, dim3(nt, nt), dim3(256), 0, st, (const double2*)c->d_bt,
+                     (const double2*)Z, n_G, nb, (double2*)VGG);
+  HIPCHK(c, hipEventRecord(c->ev_bt[1], st));
+  HIPCHK(c, hipGetLastError());
+  c->bt_timed = true;
+  return EXC_OK;
+}
+
 const char* exchange_last_error(const exc_ctx* c) {
   if (!c) return g_init_err.c_str();
   if (c->magic != kAlive) return "context is not alive";
@@ -1483,6 +1531,14 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 10: *value = c->fused ? 1.0 : 0.0; return EXC_OK;
     case 11: *value = c->gamma_ms; return EXC_OK;
     case 12: *value = c->gamma_terms; return EXC_OK;
+    case 13: {                                    // the last back-transform's product kernel
+      if (!c->bt_timed) { *value = 0.0; return EXC_OK; }
+      if (hipEventSynchronize(c->ev_bt[1]) != hipSuccess) return EXC_EHIP;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev_bt[0], c->ev_bt[1]) != hipSuccess) return EXC_EHIP;
+      *value = ms;
+      return EXC_OK;
+    }
     default: return EXC_EINVAL;
   }
 }

@@ -6,7 +6,7 @@
 //   Y_s = L_c^H A_c + l_c a_{j(c)}   (block-sparse multipole-free rows, FP64 VALU)
 //   Y_d = L22^H A_d                  (dense rows, MFMA in the mode's pieces)
 //
-// the vector-matrix-vector form of Sec. II.C with v = L L^H and the sparse
+// the vector-matrix-vector form of Sec. III.C with v = L L^H and the sparse
 // structure of the transformed Coulomb matrix (Fig. 1).
 //
 // Layout of the work in one workgroup (4 wavefronts, one per SIMD):

@@ -1,4 +1,4 @@
-// Gamma-point term of the exchange matrix (Sec. II.D, eqs. "F(q)", "divergence",
+// Gamma-point term of the exchange matrix (Sec. III.E, eqs. "F(q)", "divergence",
 // "div final"). The 1/q^2 part of the Coulomb matrix, damped by exp(-beta q^2),
 // is integrated analytically; what the q-mesh sum already holds is subtracted:
 //

@@ -6,7 +6,7 @@
 //   GEMM form:              B = E(q) (full), Right = W = E A_d + X, Left = A_d.
 //
 // The product with v(q) and the band contraction are the two stages of the
-// vector-matrix-vector form (Sec. II.C, eq. "vec-mat-vec"); the dense block is
+// vector-matrix-vector form (Sec. III.C, eq. "vec-mat-vec"); the dense block is
 // the "one big block" of multipole functions and plane waves of Fig. 1.
 //
 // Complex arithmetic on real MFMA: the 16 real columns of one MFMA tile hold

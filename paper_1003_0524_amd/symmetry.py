@@ -1,6 +1,6 @@
 """Point-group symmetry of a Gamma-centred q mesh (host-side set-up, no GPU work).
 
-Sec. II.D ("rotate APW" equation): only the operations that leave k invariant
+Sec. III.D ("rotate APW" equation): only the operations that leave k invariant
 modulo a reciprocal lattice vector (the little group LG(k)) may be used to
 reduce the q sum of V^x(k). They split the mesh into orbits; one representative
 per orbit forms the extended irreducible wedge EIBZ(k), and a representative q

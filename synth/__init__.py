@@ -19,7 +19,7 @@ wavefunctions and Coulomb matrices are not available):
   N_MB(q) ~ U{2000..2600}, 5 atoms x 36 channels (l<=5) with 0.6 * mean N_MB MT
   functions, 100 bands, 20 occupied.
 
-Index order inside the MPB follows the paper's Fig. 1 ordering (Sec. II.C
+Index order inside the MPB follows the paper's Fig. 1 ordering (Sec. III.C
 "Sparsity of the Coulomb matrix"): all multipole-free MT functions grouped by
 (atom, L, M) channel, then one multipole-carrying MT function per channel, then
 the interstitial plane waves.

@@ -1,4 +1,4 @@
-"""Pins of the back-transform oracle (Sec. II.B, eq. "APW trafo").
+"""Pins of the back-transform oracle (Sec. III.A, eq. "APW trafo").
 
   * element-by-element loops on tiny sizes;
   * the back-transform inverts the band projection: with overlap S (Hermitian

@@ -1,5 +1,5 @@
 """GPU parity of the q sum restricted to the extended irreducible wedge EIBZ(k)
-(exc_desc.w_kq; Sec. II.D, eq. "rotate APW").
+(exc_desc.w_kq; Sec. III.D, eq. "rotate APW").
 
 Data that respect the symmetry are built by copying: v(q) = v(rep_G(q)) (G the
 lattice's point group) and M(k,q) = M(k, rep_k(q)) (rep_k under the little group

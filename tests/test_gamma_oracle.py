@@ -1,4 +1,4 @@
-"""Pins of the oracle's Gamma-point term (Sec. II.D, eqs. "F(q)", "divergence", "div final").
+"""Pins of the oracle's Gamma-point term (Sec. III.E, eqs. "F(q)", "divergence", "div final").
 
 Each pin comes from outside the oracle's own formula:
   * the cutoff relation exp(-beta q0^2) = beta, as stated after eq. "div final";

@@ -1,6 +1,6 @@
 """The inversion-symmetric (real) variant, checked on the CPU with the oracle.
 
-With real v(q) (inversion symmetry, Sec. II.D) and real projections, the exchange
+With real v(q) (inversion symmetry, Sec. III.D) and real projections, the exchange
 matrix is real symmetric. The library computes it from bands packed in pairs as
 complex columns (column j = M_{2j} + i M_{2j+1}); since v is real,
 Re(A^H v A) of a packed column is the sum of the two bands' A^T v A. This file

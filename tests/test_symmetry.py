@@ -1,4 +1,4 @@
-"""Host-side symmetry set-up of the q sum (Sec. II.D): point groups, irreducible
+"""Host-side symmetry set-up of the q sum (Sec. III.D): point groups, irreducible
 meshes, little groups and the extended irreducible wedge EIBZ(k).
 
 Pins: the orders of the cubic and hexagonal holohedries (48, 24); the numbers of
