@@ -1,0 +1,49 @@
+"""The descriptor options together on one context: inversion symmetry (real v,
+packed real bands), per-pair weights with pairs left out, and the Gamma-point
+shift, in FP64 and bf16x3, against the oracle's restricted real sum minus C on
+the occupied diagonal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chol, gamma as og, precision as pr, vx
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_inversion_weights_and_gamma_together(precision):
+    import paper_1003_0524_amd as lib
+    cfg = synth.make_config("small")
+    print(f"[combined] small {precision}", flush=True)
+    E, D, C = synth.coulomb_blocks_real(cfg)
+    rng = np.random.default_rng(21)
+    w_kq = np.where(rng.random((cfg.n_k, cfg.n_q)) < 0.4, 0.0, rng.uniform(0.05, 0.2, (cfg.n_k, cfg.n_q)))
+    w_kq[:, 3] = 0.125
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True, inversion=True, w_kq=w_kq)
+    Cg = ex.gamma_term(cfg.recip(), (2, 2, 2), 0.05, apply=True)
+    Ms = [torch.from_numpy(np.concatenate([synth.pack_real_pairs(synth.m_block_real(cfg, k, q)).ravel()
+                                           for q in range(cfg.n_q) if w_kq[k, q] != 0])).cuda()
+          for k in range(cfg.n_k)]
+    Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    L = [chol.cholesky(a) for a in v]
+    assert Cg == pytest.approx(og.gamma_term(cfg.recip(), (2, 2, 2), 0.05), abs=1e-12)
+    for k in range(cfg.n_k):
+        keep = [q for q in range(cfg.n_q) if w_kq[k, q] != 0]
+        mr = [synth.m_block_real(cfg, k, q) for q in keep]
+        ref = og.apply_gamma(vx.vx_k(mr, [v[q] for q in keep], w_kq[k, keep]), cfg.n_occ, Cg)
+        assert not np.any(Vs[k].imag)
+        if precision == "fp64":
+            assert pr.normwise_error(Vs[k], ref) <= 1e-10, k
+        else:
+            emu = pr.vx_k_emulated([synth.pack_real_pairs(m) for m in mr], [L[q] for q in keep],
+                                   w_kq[k, keep], precision).real
+            emu = og.apply_gamma(emu, cfg.n_occ, Cg)
+            assert pr.normwise_error(Vs[k], ref) <= 4.0 * pr.normwise_error(emu, ref) + 1e-12, k
