@@ -225,7 +225,7 @@ exc_status exchange_gamma_term(exc_ctx *ctx, const double *recip, const int32_t 
  * `stream` (ordered after that work); Z and VGG must stay valid until it completes.
  * A workspace of n_G x n_b(k) complex128 is kept by the context and grown when a
  * larger one is needed (the growth synchronises the device). EXC_EINVAL for a bad k,
- * NULL pointers or n_G outside [1, 2^22]; EXC_ESTATE if V(k) was never computed.
+ * NULL pointers or n_G outside [1, 2^20]; EXC_ESTATE if V(k) was never computed.
  */
 exc_status exchange_back_transform(exc_ctx *ctx, int32_t k, const void *Z, int32_t n_G, void *VGG,
                                    void *stream);

@@ -808,9 +808,9 @@ std::string tune_key(const exc_ctx* c, int dtype) {
   for (int q = 0; q < c->n_q; ++q) nmb += c->nmb[q];
   for (int k = 0; k < c->n_k; ++k) nbs += c->nb[k];
   char buf[256];
-  snprintf(buf, sizeof buf, "v1 prec=%d form=%d dtype=%d nk=%d nq=%d nocc=%d nbt=%d nmb_avg=%ld nb_avg=%ld ns=%d%s",
+  snprintf(buf, sizeof buf, "v1 prec=%d form=%d dtype=%d nk=%d nq=%d nocc=%d nbt=%d nmb_avg=%ld nb_avg=%ld ns=%d pairs=%d%s",
            c->precision, c->form, dtype, c->n_k, c->n_q, c->n_occ, c->nbt_max, nmb / std::max(1, c->n_q),
-           nbs / std::max(1, c->n_k), c->n_s, c->real_v ? " real" : "");
+           nbs / std::max(1, c->n_k), c->n_s, (int)c->pairs.size(), c->real_v ? " real" : "");
   return buf;
 }
 
@@ -1449,7 +1449,7 @@ exc_status exchange_back_transform(exc_ctx* c, int32_t k, const void* Z, int32_t
   TRY(check_ctx(c));
   if (k < 0 || k >= c->n_k) return fail(c, EXC_EINVAL, "k = %d outside [0, %d)", k, c->n_k);
   if (!Z || !VGG) return fail(c, EXC_EINVAL, "Z or VGG is NULL");
-  if (n_G < 1 || n_G > (1 << 22)) return fail(c, EXC_EINVAL, "n_G = %d outside [1, 2^22]", n_G);
+  if (n_G < 1 || n_G > (1 << 20)) return fail(c, EXC_EINVAL, "n_G = %d outside [1, 2^20]", n_G);
   if (!c->v_valid[k]) return fail(c, EXC_ESTATE, "V(k=%d) has not been computed", k);
   HIPCHK(c, hipSetDevice(c->device));
   const int nb = c->nb[k];

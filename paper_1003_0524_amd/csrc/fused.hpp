@@ -610,7 +610,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
                 im = v.y;
               }
             }
-            if constexpr (C::NEGP) {
+            if constexpr (C::NEGP && !REALF) {      // (a real factor never reads the -Im plane)
               put_cplx3<MODE>(Apl + c * LDK + k, APL, re, im);
             } else {
               put_real<MODE>(Apl + c * LDK + k, APL, re);
