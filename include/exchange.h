@@ -230,6 +230,20 @@ exc_status exchange_gamma_term(exc_ctx *ctx, const double *recip, const int32_t 
 exc_status exchange_back_transform(exc_ctx *ctx, int32_t k, const void *Z, int32_t n_G, void *VGG,
                                    void *stream);
 
+/*
+ * exchange_band_mask -- band pairs (n, n') of V(k) to compute (Sec. III.D, eq. "MT
+ * stepfuntion"): an element of V^x between bands of different irreducible
+ * representations is zero, which the caller detects from the matrix elements of
+ * Theta^MT = 1 - Theta between groups of degenerate bands and passes here.
+ *   keep : host, n_b(k) x n_b(k) bytes, row-major (element (n, n') at keep[n n_b + n']),
+ *          nonzero = compute; NULL = compute every pair (the default)
+ * The work is skipped per 8 x 8 tile of band pairs: a tile (with its mirror) is left
+ * out only if every element of both is 0, and then its elements of V(k) are 0; the
+ * diagonal tiles (which hold V_nn) are always computed. Takes effect for later
+ * exchange_matrix[_all] calls; it synchronises the device first.
+ */
+exc_status exchange_band_mask(exc_ctx *ctx, int32_t k, const uint8_t *keep);
+
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx == NULL,
  * the message of the last failed exchange_init on this thread. */
 const char *exchange_last_error(const exc_ctx *ctx);

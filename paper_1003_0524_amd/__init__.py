@@ -31,6 +31,7 @@ STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4:
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
 EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
                     "exchange_energy_device", "exchange_gamma_term", "exchange_back_transform",
+                    "exchange_band_mask",
                     "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
                     "exchange_nn_init", "exchange_nn_params", "exchange_nn_train", "exchange_nn_grad",
                     "exchange_nn_predict", "exchange_nn_features", "exchange_eigh", "exchange_nn_project",
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_gamma_term.restype = i32
     lib.exchange_back_transform.argtypes = [vp, i32, vp, i32, vp, vp]
     lib.exchange_back_transform.restype = i32
+    lib.exchange_band_mask.argtypes = [vp, i32, vp]
+    lib.exchange_band_mask.restype = i32
     lib.exchange_energy_device.restype = i32
     lib.exchange_last_error.argtypes = [vp]
     lib.exchange_last_error.restype = ctypes.c_char_p
@@ -296,6 +299,15 @@ class Exchange:
         self._check(self.lib.exchange_back_transform(self.ctx, int(k), ctypes.c_void_p(Z.data_ptr()), nG,
                                                      ctypes.c_void_p(out.data_ptr()), st))
         return out.view(nG, nG).T      # column-major -> [G][G'] view
+
+    def band_mask(self, k: int, keep=None) -> None:
+        """Band pairs of V(k) to compute (n_b x n_b booleans; None: all). Tiles of 8 x 8 pairs
+        whose elements (and mirror) are all False are skipped and come back as zeros."""
+        if keep is None:
+            self._check(self.lib.exchange_band_mask(self.ctx, int(k), None))
+            return
+        m = np.ascontiguousarray(np.asarray(keep, dtype=np.uint8).reshape(self.n_bands[k], self.n_bands[k]))
+        self._check(self.lib.exchange_band_mask(self.ctx, int(k), ctypes.c_void_p(m.ctypes.data)))
 
     def gamma_kernel_ms(self):
         """(lattice-sum kernel ms, number of terms) of the last gamma_term call."""

@@ -218,6 +218,7 @@ struct exc_ctx {
   float gamma_ms = 0.f;               // lattice-sum kernel of the last exchange_gamma_term
   double gamma_terms = 0.0;           // its number of terms
   double2* d_bt = nullptr;            // back-transform workspace T = Z V (grown on demand)
+  uint64_t* d_tmask = nullptr;        // [n_k][3] band-tile pairs (I, J) to compute, bit J(J+1)/2 + I
   size_t bt_cap = 0;
   hipEvent_t ev_bt[2] = {nullptr, nullptr};
   bool bt_timed = false;
@@ -310,7 +311,7 @@ void release(exc_ctx* c) {
                   c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
-                  c->d_gamma, c->d_gpartial, c->d_bt};
+                  c->d_gamma, c->d_gpartial, c->d_bt, c->d_tmask};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
@@ -507,6 +508,7 @@ TileArgs tile_args(exc_ctx* c, int dtype) {
   a.gpart = c->d_gpart;
   a.dpart = c->d_dpart;
   a.gstride = c->gstride;
+  a.tmask = c->d_tmask;
   a.dstride = c->dstride;
   return a;
 }
@@ -535,6 +537,7 @@ FusedArgs fused_args(exc_ctx* c, int dtype) {
   f.schunk = c->d_schunk; f.n_schunk = c->n_schunk;
   f.gpart = c->d_gpart; f.dpart = c->d_dpart;
   f.gstride = c->gstride; f.dstride = c->dstride;
+  f.tmask = c->d_tmask;
   return f;
 }
 
@@ -1214,6 +1217,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(dalloc(c, &c->d_ewk, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_erho, (size_t)c->n_k));
   ITRY(dalloc(c, &c->d_gamma, (size_t)4));
+  ITRY(dalloc(c, &c->d_tmask, (size_t)3 * c->n_k));
+  IHIP(hipMemset(c->d_tmask, 0xFF, (size_t)3 * c->n_k * sizeof(uint64_t)));   // every tile pair
   IHIP(hipMemset(c->d_gamma, 0, 4 * sizeof(double)));   // no Gamma-point shift until requested
 
   if (sparse_lds_bytes(c) > 65536)
@@ -1483,6 +1488,29 @@ exc_status exchange_back_transform(exc_ctx* c, int32_t k, const void* Z, int32_t
   HIPCHK(c, hipEventRecord(c->ev_bt[1], st));
   HIPCHK(c, hipGetLastError());
   c->bt_timed = true;
+  return EXC_OK;
+}
+
+exc_status exchange_band_mask(exc_ctx* c, int32_t k, const uint8_t* keep) {
+  TRY(check_ctx(c));
+  if (k < 0 || k >= c->n_k) return fail(c, EXC_EINVAL, "k = %d outside [0, %d)", k, c->n_k);
+  const int nb = c->nb[k], nbt = (nb + 7) / 8;
+  uint64_t bits[3] = {~0ull, ~0ull, ~0ull};
+  if (keep) {
+    bits[0] = bits[1] = bits[2] = 0;
+    for (int J = 0; J < nbt; ++J)
+      for (int I = 0; I <= J; ++I) {
+        bool any = I == J;                        // diagonal tiles carry V_nn: always computed
+        for (int n = 8 * I; n < std::min(nb, 8 * I + 8) && !any; ++n)
+          for (int m = 8 * J; m < std::min(nb, 8 * J + 8) && !any; ++m)
+            any = keep[(size_t)n * nb + m] || keep[(size_t)m * nb + n];
+        const int tp = J * (J + 1) / 2 + I;
+        if (any) bits[tp >> 6] |= 1ull << (tp & 63);
+      }
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());              // no launch in flight reads the old mask
+  HIPCHK(c, hipMemcpy(c->d_tmask + 3 * k, bits, sizeof(bits), hipMemcpyHostToDevice));
   return EXC_OK;
 }
 

@@ -117,6 +117,7 @@ struct FusedArgs {
   void* gpart;
   double* dpart;
   int32_t gstride, dstride;
+  const uint64_t* tmask;          // [n_k][3] band-tile pairs to compute (bit tp), nullptr: all
 };
 
 template <int MODE, int RTW, int NCT, int NB8M, int KC, int CBX = 16, int OCC = 1>
@@ -294,6 +295,8 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
       }
     }
     for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
+    // this wavefront's tiles (bit s: tile w + NW s) that the band mask of k keeps
+    const uint64_t wkeep = tile_keep_bits(a.tmask, pi.k, w, NW, C::NPW);
 
     // ---- contraction of the staged GR rows into this wave's Gram tiles ----
     // rows_c: rows of the stage (GR), pitch: its row pitch
@@ -327,6 +330,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
         for (int s = 0; s < C::NPW; ++s) {
           const int tp = w + NW * s;
           if (tp >= npt) break;
+          if (!((wkeep >> s) & 1)) continue;
           const accv_t acc = one(tp, accv_t{0, 0, 0, 0});
 #pragma unroll
           for (int i = 0; i < 4; ++i) gp[(tp * 4 + i) * 64 + lane] += acc[i];
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
         for (int s = 0; s < NPWR; ++s) {
           const int tp = w + NW * s;
-          if (tp < npt) gacc[s] = one(tp, gacc[s]);
+          if (tp < npt && ((wkeep >> s) & 1)) gacc[s] = one(tp, gacc[s]);
         }
       }
     };

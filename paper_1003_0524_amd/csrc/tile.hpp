@@ -64,7 +64,22 @@ struct TileArgs {
   void* gpart;                   // Gram-tile partials, acc_t
   double* dpart;                 // FP64 diagonal partials
   int32_t gstride, dstride;      // elements per slot
+  const uint64_t* tmask;         // [n_k][3] band-tile pairs to compute (bit tp), nullptr: all
 };
+
+// Bit s of the result: the band mask of k keeps tile tp = w + nw s (s < ns <= 64).
+// A tile pair (I, J) that is left out contributes zero to its partial slot.
+__device__ __forceinline__ uint64_t tile_keep_bits(const uint64_t* tmask, int k, int w, int nw, int ns) {
+  if (!tmask) return ~0ull;
+  const uint64_t m0 = tmask[3 * k], m1 = tmask[3 * k + 1], m2 = tmask[3 * k + 2];
+  uint64_t r = 0;
+  for (int s = 0; s < ns && s < 64; ++s) {
+    const int tp = w + nw * s;
+    const uint64_t word = tp < 64 ? m0 : (tp < 128 ? m1 : m2);
+    if (tp < 192 && ((word >> (tp & 63)) & 1)) r |= 1ull << s;
+  }
+  return r;
+}
 
 // tile pair index tp <-> (I, J), I <= J, column-wise upper triangle: tp = J(J+1)/2 + I
 __device__ __forceinline__ void tp_to_ij(int tp, int& I, int& J) {
@@ -198,6 +213,7 @@ __global__ __launch_bounds__(64 * NWR * NWC, 1) void tile_kernel(TileArgs a) {
     if constexpr (DIAG64) {
       for (int e = tid; e < NW * C::NCC * 2; e += NT) Dacc[e] = 0.0;
     }
+    const uint64_t wkeep = tile_keep_bits(a.tmask, pi.k, w, NW, C::NPW);
 
     for (int gbase = wi.g0; gbase < wi.g1; gbase += wi.ngc) {
       const int ng = min(wi.ngc, wi.g1 - gbase);
@@ -523,6 +539,7 @@ __global__ __launch_bounds__(64 * NWR * NWC, 1) void tile_kernel(TileArgs a) {
           for (int s = 0; s < C::NPW; ++s) {
             const int tp = w + NW * s;
             if (tp >= npt) break;
+            if (!((wkeep >> s) & 1)) continue;
             accv_t acc = accv_t{0, 0, 0, 0};
             for (int g = 0; g < ng; ++g) acc = contract(tp, g, acc);
 #pragma unroll
@@ -532,7 +549,7 @@ __global__ __launch_bounds__(64 * NWR * NWC, 1) void tile_kernel(TileArgs a) {
 #pragma unroll
           for (int s = 0; s < NPWR; ++s) {
             const int tp = w + NW * s;
-            if (tp < npt)
+            if (tp < npt && ((wkeep >> s) & 1))
               for (int g = 0; g < ng; ++g) gacc[s] = contract(tp, g, gacc[s]);
           }
         }

@@ -105,3 +105,30 @@ def eibz_weights(k_frac: np.ndarray, q_points: np.ndarray, ops: list, w_q=None):
         if rep[q] == q:
             w[q] = w_q[q] / stab[q]                 # stab[q] = N_{k,q}
     return w, len(lg), rep
+
+
+def theta_mask(theta: np.ndarray, energies, deg_tol: float = 1e-6, zero_tol: float = 1e-8) -> np.ndarray:
+    """Band pairs to compute from the matrix elements of Theta^MT (Sec. III.D, eq. "MT
+    stepfuntion"): bands are grouped by degenerate energies (|e_n - e_m| <= deg_tol,
+    chained over sorted energies); a pair (n, n') is kept unless the block of theta between
+    the group of n and the group of n' is numerically zero (max |.| <= zero_tol times the
+    largest |theta|), which marks different irreducible representations."""
+    theta = np.asarray(theta)
+    e = np.asarray(energies, dtype=np.float64)
+    nb = e.size
+    order = np.argsort(e, kind="stable")
+    group = np.empty(nb, dtype=np.int64)
+    g = 0
+    for i, n in enumerate(order):
+        if i > 0 and e[n] - e[order[i - 1]] > deg_tol:
+            g += 1
+        group[n] = g
+    scale = float(np.abs(theta).max()) if theta.size else 0.0
+    ng = g + 1
+    nonzero = np.zeros((ng, ng), dtype=bool)
+    for a in range(ng):
+        ia = np.flatnonzero(group == a)
+        for b in range(ng):
+            ib = np.flatnonzero(group == b)
+            nonzero[a, b] = np.abs(theta[np.ix_(ia, ib)]).max() > zero_tol * scale
+    return nonzero[group][:, group]

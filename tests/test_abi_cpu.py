@@ -71,6 +71,7 @@ def test_null_context_calls(lib):
     assert lib.exchange_energy(None, None, None, ctypes.byref(v)) == -1
     assert lib.exchange_gamma_term(None, None, None, 0.005, 1, ctypes.byref(v), None) == -1
     assert lib.exchange_back_transform(None, 0, None, 1, None, None) == -1
+    assert lib.exchange_band_mask(None, 0, None) == -1
     lib.exchange_destroy(None)
 
 
