@@ -39,6 +39,14 @@
  * outputs must not be read until the stream has reached that point. With
  * on_device = 0 the call copies from / to host memory and returns when the
  * result is on the host.
+ *
+ * Around the exchange matrix: exchange_energy[_device] (eq. "HF exchange
+ * energy"); exchange_gamma_term (the q -> 0 term, Sec. III.E); the symmetry
+ * reductions of Sec. III.D -- exc_desc.inversion (real v and bands),
+ * exc_desc.w_kq (q sum over the extended irreducible wedge) and
+ * exchange_band_mask (band pairs from the Theta^MT criterion);
+ * exchange_back_transform (V in the LAPW basis, Sec. III.A); and the learned
+ * extrapolator of V between exact evaluations (exchange_nn_*).
  */
 #ifndef EXCHANGE_H
 #define EXCHANGE_H
