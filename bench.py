@@ -283,7 +283,7 @@ def main() -> int:
             exe, _ = make(head, "herk", True, w_kq=w_kq)
             ms_e, _, kt_e = timed(exe, args.steps, args.warmup, kernel_timing=True, m_in=Me)
             Ve = [o.view(nb, nb).T.cpu().numpy() for o, nb in zip(outs, cfg.n_bands)]
-            cfg_e, fused_e = int(exe.query(3)), bool(exe.query(10))
+            cfg_e, fused_e, split_e = int(exe.query(3)), bool(exe.query(10)), int(exe.query(14))
             exe.close()
             refs_e = []
             for k in range(cfg.n_k):
@@ -293,11 +293,13 @@ def main() -> int:
             eibz = {"mode": head, "pairs": n_pairs, "pairs_full_mesh": cfg.n_k * cfg.n_q,
                     "ms_per_step": round(ms_e, 5), "main_kernel_ms": round(kt_e[0], 5),
                     "sparse_kernel_ms": round(kt_e[1], 5), "config": cfg_e, "fused": fused_e,
+                    "items_per_band_chunk": split_e,
                     "kpoints_per_s": round(cfg.n_k / (ms_e * 1e-3), 1),
                     "speedup_vs_full_mesh": round(H["ms"] / ms_e, 3),
                     "err_normwise": max(pr.normwise_error(a, b) for a, b in zip(Ve, refs_e))}
             log(f"[bench] EIBZ q sum ({head}): {n_pairs} of {cfg.n_k * cfg.n_q} pairs, {ms_e:.4f} ms/step, "
-                f"main kernel {kt_e[0]:.4f} ms, {H['ms'] / ms_e:.2f}x the full-mesh step")
+                f"main kernel {kt_e[0]:.4f} ms, {H['ms'] / ms_e:.2f}x the full-mesh step, config {cfg_e}"
+                f"{' (an item per band chunk)' if split_e else ''}")
 
     # roofline of the dominant kernel, timed live with graph event nodes. Its bound
     # follows from its arithmetic intensity (algorithmic flops / algorithmic HBM

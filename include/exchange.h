@@ -279,6 +279,9 @@ void exchange_destroy(exc_ctx *ctx);
  *              exchange_gamma_term; what = 12: its number of terms
  *   what = 13: duration (ms, HIP events) of the product kernel of the last
  *              exchange_back_transform (waits for it)
+ *   what = 14: 1 if the fused kernel's work items are (pair, n'' chunk) instead of
+ *              pairs (chosen by the autotuner when few (k, q) pairs leave the GPU
+ *              short of work), else 0
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
@@ -287,10 +290,12 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
  * Autotuning (reduced-precision Cholesky/HERK contexts, batched path): the first
  * exchange_matrix_all times every main-kernel configuration that can serve the
  * context (fused instances with enough band tiles; the block-sparse + tile
- * kernels) on the caller's own inputs, one untimed and five timed runs each,
- * and keeps the fastest (later candidates must win by more than 3 %). Environment: EXC_TUNE=0 keeps the default choice;
- * EXC_TUNE_CACHE=<file> looks the choice up / appends it under a key of the
- * problem's sizes; EXC_FUSED_CFG=<id> fixes a fused instance and EXC_FUSED=0 the
+ * kernels; then the fused instances again with a work item per n'' chunk) on the
+ * caller's own inputs, one untimed and five timed runs each, and keeps the
+ * fastest (later candidates must win by more than 3 %). Environment: EXC_TUNE=0
+ * keeps the default choice; EXC_TUNE_CACHE=<file> looks the choice up / appends
+ * it under a key of the problem's sizes; EXC_FUSED_CFG=<id> fixes a fused
+ * instance (EXC_FUSED_SPLIT=1: an item per n'' chunk) and EXC_FUSED=0 the
  * block-sparse + tile path (neither is then tuned).
  */
 

@@ -176,6 +176,7 @@ struct exc_ctx {
   const FusedKCfg* fcfg = nullptr;    // non-null: reduced-precision HERK through the fused kernel
   bool fused = false;
   bool fused_ok = false;              // the fused kernel can serve this context
+  int fsplit = 0;                     // fused batched items: 1 = one per n'' chunk (more, smaller items)
   int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
   bool tune_done = false;
   size_t ws_bytes = 0;                // block-sparse workspace the unfused path needs
@@ -390,7 +391,7 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
         P.slot_w.push_back(c->pair_w[pidx]);     // the pair's weight (w_kq, else w_q)
         cost.push_back(cs);
       };
-      if (!split_rows) {
+      if (!split_rows && !(c->fused && c->fsplit)) {
         push(0, c->n_occ, 0, nrb);
       } else if (c->fused) {
         // the fused kernel runs every row of a column chunk: one item per n'' chunk
@@ -821,11 +822,18 @@ int cfg_id(const exc_ctx* c) { return c->fused ? c->fcfg->id : c->cfg->id; }
 
 exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
   c->tuned = 0;
-  std::vector<const FusedKCfg*> cands;
+  // candidates: (fused instance, one work item per n'' chunk instead of per pair), in
+  // order of preference; the split items come last: they pay when few pairs leave the
+  // CUs short of work
+  std::vector<std::pair<const FusedKCfg*, int>> cands;
   if (c->fused_ok)
     for (const auto& k : kFused)
-      if (fused_fits(k, c->precision, c->nbt_max, c->real_v)) cands.push_back(&k);
-  cands.push_back(nullptr);                      // block-sparse + tile kernels
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v)) cands.push_back({&k, 0});
+  cands.push_back({nullptr, 0});                 // block-sparse + tile kernels
+  if (c->fused_ok && c->n_occ > 1)
+    for (const auto& k : kFused)
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v) &&
+          std::min(c->n_occ, k.NCT / c->nbt_max) < c->n_occ) cands.push_back({&k, 1});
   const std::string key = tune_key(c, dtype);
   const char* cache = getenv("EXC_TUNE_CACHE");
   if (cache) {
@@ -839,10 +847,11 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
         if (key == line) found = atoi(tab + 1);
       }
       fclose(fp);
-      for (const FusedKCfg* f : cands) {
-        const int id = f ? f->id : c->cfg->id;
+      for (const auto& cd : cands) {
+        const int id = (cd.first ? cd.first->id : c->cfg->id) + 10000 * cd.second;
         if (id == found) {
-          TRY(configure(c, f, st));
+          c->fsplit = cd.second;
+          TRY(configure(c, cd.first, st));
           c->tuned = 2;
           return EXC_OK;
         }
@@ -853,9 +862,12 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   const FusedKCfg* best = c->fcfg;
+  int best_split = 0;
   float best_ms = 1e30f;
   bool any = false;
-  for (const FusedKCfg* f : cands) {
+  for (const auto& cd : cands) {
+    const FusedKCfg* f = cd.first;
+    c->fsplit = cd.second;
     exc_status s2 = configure(c, f, st);
     if (s2 == EXC_ENOMEM) { c->err.clear(); continue; }   // e.g. no room for the block-sparse workspace
     if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
@@ -868,16 +880,17 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
     // candidates come in order of preference: a later one must be clearly faster
-    if (!any || ms < 0.97f * best_ms) { best_ms = ms; best = f; any = true; }
+    if (!any || ms < 0.97f * best_ms) { best_ms = ms; best = f; best_split = cd.second; any = true; }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (!any) return fail(c, EXC_ENOMEM, "no main-kernel configuration fits in device memory");
+  c->fsplit = best_split;
   TRY(configure(c, best, st));
   c->tuned = 1;
   if (cache) {
     if (FILE* fp = fopen(cache, "a")) {
-      fprintf(fp, "%s\t%d\n", key.c_str(), cfg_id(c));
+      fprintf(fp, "%s\t%d\n", key.c_str(), cfg_id(c) + 10000 * c->fsplit);
       fclose(fp);
     }
   }
@@ -1223,6 +1236,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
 
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
+  if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = ev[0] == '1';   // (fixed-configuration runs)
   ITRY(configure(c, c->fused ? c->fcfg : nullptr, st));
   IHIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   IHIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
@@ -1559,6 +1573,7 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 10: *value = c->fused ? 1.0 : 0.0; return EXC_OK;
     case 11: *value = c->gamma_ms; return EXC_OK;
     case 12: *value = c->gamma_terms; return EXC_OK;
+    case 14: *value = c->fsplit; return EXC_OK;
     case 13: {                                    // the last back-transform's product kernel
       if (!c->bt_timed) { *value = 0.0; return EXC_OK; }
       if (hipEventSynchronize(c->ev_bt[1]) != hipSuccess) return EXC_EHIP;

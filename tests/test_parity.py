@@ -220,6 +220,26 @@ def test_every_tuner_candidate_matches_oracle(name, precision, monkeypatch):
             assert err <= 4.0 * pred + 1e-12, (name, precision, kind, cid, k, err, pred)
 
 
+@pytest.mark.parametrize("precision,cid", [("fp32", 150), ("bf16x3", 161), ("bf16x6", 170)])
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_split_items_match_oracle(name, precision, cid, monkeypatch):
+    """Fused work items per (pair, n'' chunk) (the autotuner's candidates for few pairs)."""
+    cfg = synth.make_config(name)
+    nbt = max((nb + 7) // 8 for nb in cfg.n_bands)
+    if nbt > 3:
+        cid = {"fp32": 121, "bf16x3": 131, "bf16x6": 141}[precision]   # 8 band tiles
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
+    monkeypatch.setenv("EXC_FUSED_SPLIT", "1")
+    cfg_, Vs = _run_all(name, precision, "herk", True)
+    for k in range(cfg.n_k):
+        ref = _oracle(name, k)
+        pred = pr.normwise_error(_emulated(name, k, precision), ref)
+        err = pr.normwise_error(Vs[k], ref)
+        assert err <= 4.0 * pred + 1e-12, (name, precision, k, err, pred)
+        _assert_hermitian_exact(Vs[k])
+
+
 def test_autotuner_choice_and_cache(tmp_path, monkeypatch):
     import paper_1003_0524_amd as lib
     monkeypatch.delenv("EXC_FUSED_CFG", raising=False)
