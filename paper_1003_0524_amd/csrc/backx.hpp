@@ -25,7 +25,8 @@ __global__ __launch_bounds__(256) void bt_left_kernel(const double2* __restrict_
   const int g = blockIdx.x * 256 + threadIdx.x, n = blockIdx.y;
   if (g >= nG) return;
   double re = 0.0, im = 0.0;
-  for (int m = 0; m < nb; ++m) {
+#pragma unroll 8
+  for (int m = 0; m < nb; ++m) {                  // (eight loads of Z in flight)
     const double2 z = Z[g + (long)m * nG], v = V[m + (long)n * nb];
     re = fma(z.x, v.x, re);
     re = fma(-z.y, v.y, re);
