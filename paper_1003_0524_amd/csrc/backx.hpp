@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256) void bt_left_kernel(const double2* __restrict_
   T[g + (long)n * nG] = make_double2(re, im);
 }
 
-// C[b + a * nG] = sum_n T[b + n * nG] conj(Z[a + n * nG]) for a 64 x 64 tile:
-// rows b in blockIdx.x * 64 + [0, 64), columns a in blockIdx.y * 64 + [0, 64).
+// C[b + a * nG] = sum_n T[b + n * nG] conj(Z[a + n * nG]) over 64 x 64 tiles: tile t
+// has rows b in (t % nt) * 64 + [0, 64) and columns a in (t / nt) * 64 + [0, 64).
 // As an MFMA product D[a][b] = sum_n conj(Z)[a][n] T[b][n]: the A operand is a
 // 16 x 4 block of conj(Z) (lane l: column a = l % 16, n = l / 16), the B operand a
 // 4 x 16 block of T^T (lane l: row b = l % 16, same n), and lane l holds
@@ -46,44 +46,52 @@ __global__ __launch_bounds__(256) void bt_gram_kernel(const double2* __restrict_
                                                       int nG, int nb, double2* __restrict__ C) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int a0 = blockIdx.y * 64 + 16 * w;          // this wavefront's 16 columns of C
-  const int bt0 = blockIdx.x * 64;                   // the tile's 64 rows of C
-  const int a_l = a0 + r16;
-  d4_t accr[4], acci[4];
+  const int nt = (nG + 63) / 64;
+  // tiles in turn (grid-stride): the stores of one tile drain while the next one's
+  // operands load and its MFMAs run
+  for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+    const int a0 = (tile / nt) * 64 + 16 * w;       // this wavefront's 16 columns of C
+    const int bt0 = (tile % nt) * 64;                // the tile's 64 rows of C
+    const int a_l = a0 + r16;
+    d4_t accr[4], acci[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) accr[j] = acci[j] = d4_t{0.0, 0.0, 0.0, 0.0};
-  // K in chunks of 16: the chunk's operands (4 of Z, 16 of T per lane) are requested
-  // before its 64 MFMAs, one memory latency per chunk
-  for (int n0 = 0; n0 < nb; n0 += 16) {
-    double2 z[4], t[4][4];
+    for (int j = 0; j < 4; ++j) accr[j] = acci[j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    // K in chunks of 16: the chunk's operands (4 of Z, 16 of T per lane) are requested
+    // before its 64 MFMAs, one memory latency per chunk
+    for (int n0 = 0; n0 < nb; n0 += 16) {
+      const int ns = min(4, (nb - n0 + 3) >> 2);     // MFMA steps of 4 in this chunk (uniform)
+      double2 z[4], t[4][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int n = n0 + 4 * s + kq;
-      z[s] = (a_l < nG && n < nb) ? Z[a_l + (long)n * nG] : make_double2(0.0, 0.0);
+      for (int s = 0; s < 4; ++s) {
+        const int n = n0 + 4 * s + kq;
+        z[s] = (a_l < nG && n < nb) ? Z[a_l + (long)n * nG] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int b_l = bt0 + 16 * j + r16;
-        t[s][j] = (b_l < nG && n < nb) ? T[b_l + (long)n * nG] : make_double2(0.0, 0.0);
+        for (int j = 0; j < 4; ++j) {
+          const int b_l = bt0 + 16 * j + r16;
+          t[s][j] = (b_l < nG && n < nb) ? T[b_l + (long)n * nG] : make_double2(0.0, 0.0);
+        }
+      }
+      // conj(z) t = (zr tr + zi ti) + i (zr ti - zi tr)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (s >= ns) break;                            // (no MFMAs on the zero tail of n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          accr[j] = mfma(z[s].x, t[s][j].x, accr[j]);
+          accr[j] = mfma(z[s].y, t[s][j].y, accr[j]);
+          acci[j] = mfma(z[s].x, t[s][j].y, acci[j]);
+          acci[j] = mfma(-z[s].y, t[s][j].x, acci[j]);
+        }
       }
     }
-    // conj(z) t = (zr tr + zi ti) + i (zr ti - zi tr)
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int j = 0; j < 4; ++j) {
+      const int b = bt0 + 16 * j + r16;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        accr[j] = mfma(z[s].x, t[s][j].x, accr[j]);
-        accr[j] = mfma(z[s].y, t[s][j].y, accr[j]);
-        acci[j] = mfma(z[s].x, t[s][j].y, acci[j]);
-        acci[j] = mfma(-z[s].y, t[s][j].x, acci[j]);
+      for (int i = 0; i < 4; ++i) {
+        const int a = a0 + kq + 4 * i;
+        if (a < nG && b < nG) C[b + (long)a * nG] = make_double2(accr[j][i], acci[j][i]);
       }
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int b = bt0 + 16 * j + r16;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int a = a0 + kq + 4 * i;
-      if (a < nG && b < nG) C[b + (long)a * nG] = make_double2(accr[j][i], acci[j][i]);
     }
   }
 }

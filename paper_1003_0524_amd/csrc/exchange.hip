@@ -1495,9 +1495,10 @@ exc_status exchange_back_transform(exc_ctx* c, int32_t k, const void* Z, int32_t
   const double2* V = c->d_vres + c->v_off[k];
   hipLaunchKernelGGL(bt_left_kernel, dim3((unsigned)((n_G + 255) / 256), (unsigned)nb), dim3(256), 0, st,
                      (const double2*)Z, V, n_G, nb, c->d_bt);
-  const unsigned nt = (unsigned)((n_G + 63) / 64);
+  const long nt = (n_G + 63) / 64;
+  const unsigned ngrid = (unsigned)std::min<long>(nt * nt, 512);   // two workgroups per CU, tiles in turn
   HIPCHK(c, hipEventRecord(c->ev_bt[0], st));
-  hipLaunchKernelGGL(bt_gram_kernel, dim3(nt, nt), dim3(256), 0, st, (const double2*)c->d_bt,
+  hipLaunchKernelGGL(bt_gram_kernel, dim3(ngrid), dim3(256), 0, st, (const double2*)c->d_bt,
                      (const double2*)Z, n_G, nb, (double2*)VGG);
   HIPCHK(c, hipEventRecord(c->ev_bt[1], st));
   HIPCHK(c, hipGetLastError());

@@ -3,7 +3,8 @@ Sec. III.A, eq. "APW trafo") against the oracle.
 
 V(k) comes from the library's FP64 path; the oracle computes its own V(k) and
 Z V Z^H. Bar: 1e-12 normwise (FP64 products of FP64 inputs). Sizes n_G = 1, 70,
-200, 333 cover single and partial 64-row tiles. With Z = S c, c^H S c = 1, the
+200, 333 cover single and partial 64-row tiles; band counts 8, 13, 21 and 37 cover
+partial steps of the band index. With Z = S c, c^H S c = 1, the
 projection c^H V_GG c returns the library's V(k) (1e-11 of its size).
 """
 import sys
@@ -34,8 +35,9 @@ def _ctx(cfg):
                         precision="fp64", form="herk", batched=True)
 
 
-def test_back_transform_matches_oracle():
-    cfg = synth.make_config("small")
+@pytest.mark.parametrize("name", ["small", "ragged"])      # ragged: 13, 37, 21 bands
+def test_back_transform_matches_oracle(name):
+    cfg = synth.make_config(name)
     ex = _ctx(cfg)
     ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda() for k in range(cfg.n_k)])
     E, D, C = synth.coulomb_blocks(cfg)
