@@ -91,7 +91,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the exchange path here is built and timed on a "
-              "single MI355X (multi-GPU sharding over q is described in DESIGN.md, not run).",
+              "single MI355X (sharding the q sum over GPUs, with one all-reduce of the FP64 partial V, is not run).",
               file=sys.stderr)
         return 2
 

@@ -10,7 +10,7 @@ where M^{n n''}_I(k,q) is the MPB projection of the wavefunction product
 (Sec. II, the sentence following eq. "HF exchange energy"), i.e. a weighted sum
 with weights w_q (1/N_q on an equidistant mesh).
 
-Readings taken here (each listed in the design doc):
+Readings taken here where the paper leaves a choice:
   * conjugation: the bra-side projection is conjugated, so with
     A_{n''} = M(k,q)[n''] viewed as an N_MB x n_b matrix, V = -sum w_q A^H v A;
   * the occupied set is the same n_occ bands at every k-q, unit occupation per
