@@ -64,7 +64,7 @@ typedef enum {
   EXC_ENOTPD = -3,        /* Cholesky pivot <= 0: v(q) is not positive definite     */
   EXC_EHIP = -4,          /* a HIP runtime call failed                              */
   EXC_ESTATE = -5,        /* context destroyed, not initialised, or result missing  */
-  EXC_EUNSUPPORTED = -6   /* valid request this build does not support              */
+  EXC_EUNSUPPORTED = -6   /* valid request the library does not support            */
 } exc_status;
 
 /* Arithmetic of the bulk products (Cholesky, q sum and diagonal are always FP64). */
