@@ -82,18 +82,19 @@ def test_full_shape_slice(name, precision):
         assert pr.normalised_eig_error(got, ref, rho) <= 1e-6
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
-def test_full_shape_inversion_variant(precision):
-    """The inversion-symmetric variant at the ZnO-like per-pair shapes (real parts of the
-    slice's v and projections, 18 real bands packed into 9 columns, 60 bands): FP64 1e-10,
-    reduced precision within 4x the emulated error (6x on the fp32 tile path, see below)
-    and <= 1e-6 Ha on the normalised eigenvalues."""
+@pytest.mark.parametrize("name,precision", [("c3", "fp64"), ("c3", "fp32"), ("c3", "bf16x3"),
+                                            ("c4", "fp64"), ("c4", "bf16x3")])
+def test_full_shape_inversion_variant(name, precision):
+    """The inversion-symmetric variant at the ZnO-like and SrTiO3-like per-pair shapes (real
+    parts of the slice's v and projections; 18 / 20 real bands packed into 9 / 10 columns,
+    60 / 100 bands): FP64 1e-10, reduced precision within 4x the emulated error (6x on the
+    fp32 tile path, see below) and <= 1e-6 Ha on the normalised eigenvalues."""
     import paper_1003_0524_amd as lib
-    sl, E, D, C = _slice("c3")
+    sl, E, D, C = _slice(name)
     Er, Dr, Cr = ([np.ascontiguousarray(x.real) for x in E], [np.ascontiguousarray(x.real) for x in D],
                   [np.ascontiguousarray(x.real) for x in C])
-    mr = [np.ascontiguousarray(m.real) for m in _m("c3")]
-    print(f"[full-shape] c3 inversion {precision}", flush=True)
+    mr = [np.ascontiguousarray(m.real) for m in _m(name)]
+    print(f"[full-shape] {name} inversion {precision}", flush=True)
     ex = lib.Exchange(sl.n_bands, sl.n_pw, sl.ch_nrad, sl.n_occ, Er, Dr, Cr, w_q=sl.weights_q(),
                       precision=precision, form="herk", batched=True, inversion=True)
     M = torch.from_numpy(np.concatenate([synth.pack_real_pairs(m).ravel() for m in mr])).cuda()
@@ -121,3 +122,35 @@ def test_full_shape_inversion_variant(precision):
     bound = 6.0 if (precision == "fp32" and 20 <= cfg_id < 30) else 4.0
     assert err <= bound * pred + 1e-12
     assert eig <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_eibz_sum_at_si_like_shapes(precision):
+    """The EIBZ-restricted q sum of the Si-like workload (154 of its 512 pairs, weights
+    w_q / N_{k,q} for its 8 irreducible k) against the oracle's restricted sum."""
+    import paper_1003_0524_amd as lib
+    from paper_1003_0524_amd import symmetry as sy
+    cfg = synth.make_config("c2")
+    ops = sy.point_group(cfg.lattice)
+    k_idx, _ = sy.irreducible(cfg.q_frac, ops)
+    w_kq = np.stack([sy.eibz_weights(cfg.q_frac[i], cfg.q_frac, ops, cfg.weights_q())[0] for i in k_idx])
+    E, D, C = synth.coulomb_blocks(cfg)
+    print(f"[full-shape] c2 EIBZ {precision}: {np.count_nonzero(w_kq)} pairs", flush=True)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True, w_kq=w_kq)
+    Ms = [torch.from_numpy(np.concatenate([synth.m_block(cfg, k, q).ravel() for q in range(cfg.n_q)
+                                           if w_kq[k, q] != 0])).cuda() for k in range(cfg.n_k)]
+    Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    L = [chol.cholesky(a) for a in v] if precision != "fp64" else None
+    for k in range(cfg.n_k):
+        keep = [q for q in range(cfg.n_q) if w_kq[k, q] != 0]
+        blocks = [synth.m_block(cfg, k, q) for q in keep]
+        ref = vx.vx_k(blocks, [v[q] for q in keep], w_kq[k, keep])
+        err = pr.normwise_error(Vs[k], ref)
+        if precision == "fp64":
+            assert err <= 1e-10, (k, err)
+        else:
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, [L[q] for q in keep], w_kq[k, keep], precision), ref)
+            assert err <= 4.0 * pred + 1e-12, (k, err, pred)
