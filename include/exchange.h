@@ -92,7 +92,8 @@ typedef struct {
   int32_t n_q;              /* number of q points of the mesh (>= 1)                     */
   int32_t n_occ;            /* occupied bands n'' summed at every k-q (>= 1)             */
   int32_t n_channels;       /* (atom, L, M) channels (>= 0)                              */
-  const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k (>= 1)                    */
+  const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k, 1..128 (the GEMM form:
+                               1..64; EXC_EUNSUPPORTED beyond)                           */
   const int32_t *n_pw;      /* [n_q] interstitial plane waves of q (>= 0)                */
   const int32_t *ch_nrad;   /* [n_channels] radial functions per channel (>= 1):
                                one multipole function + (nrad - 1) multipole-free ones  */

@@ -1,6 +1,7 @@
 """GPU parity on degenerate shapes: no muffin-tin channels (plane waves only), q points
 without plane waves (muffin-tin only), channels without multipole-free functions, and a
-single band with a single occupied band. Same bars as the parity tests.
+single band with a single occupied band, and the largest band count (128). Same bars as
+the parity tests.
 """
 import math
 
@@ -23,6 +24,9 @@ def _cfg(name):
     if name == "mt_only_q":
         return synth.Config(name, 22, 0, sc, q, n_k=2, n_occ=1, n_bands=[1, 3], ch_nrad=[3, 1, 4, 2],
                             n_pw=[0, 7, 0])
+    if name == "max_bands":                       # the largest band count the library takes
+        return synth.Config(name, 24, 0, sc, q, n_k=1, n_occ=3, n_bands=[128], ch_nrad=[3, 2, 5],
+                            n_pw=[40, 21, 33])
     if name == "one_band":
         return synth.Config(name, 23, 0, sc, q, n_k=1, n_occ=1, n_bands=[1], ch_nrad=[2, 1], n_pw=[3, 0, 5])
     raise ValueError(name)
@@ -30,12 +34,18 @@ def _cfg(name):
 
 @pytest.mark.parametrize("precision,form", [("fp64", "herk"), ("fp64", "gemm"), ("fp32", "herk"),
                                             ("bf16x3", "herk")])
-@pytest.mark.parametrize("name", ["pw_only", "mt_only_q", "one_band"])
+@pytest.mark.parametrize("name", ["pw_only", "mt_only_q", "one_band", "max_bands"])
 def test_degenerate_shapes(name, precision, form):
     import paper_1003_0524_amd as lib
     cfg = _cfg(name)
     print(f"[degenerate] {name} {precision} {form}", flush=True)
     E, D, C = synth.coulomb_blocks(cfg)
+    if form == "gemm" and max(cfg.n_bands) > 64:          # the GEMM form stops at 64 bands
+        with pytest.raises(lib.ExchangeError) as e:
+            lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                         precision=precision, form=form, batched=True)
+        assert e.value.status == -6
+        return
     ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
                       precision=precision, form=form, batched=True)
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda()
