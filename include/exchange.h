@@ -94,7 +94,8 @@ typedef struct {
   int32_t n_channels;       /* (atom, L, M) channels (>= 0)                              */
   const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k, 1..128 (the GEMM form:
                                1..64; EXC_EUNSUPPORTED beyond)                           */
-  const int32_t *n_pw;      /* [n_q] interstitial plane waves of q (>= 0)                */
+  const int32_t *n_pw;      /* [n_q] interstitial plane waves of q (>= 0; with no
+                               channels at least 1, else EXC_EINVAL: empty basis)        */
   const int32_t *ch_nrad;   /* [n_channels] radial functions per channel (>= 1):
                                one multipole function + (nrad - 1) multipole-free ones  */
   const double *w_q;        /* [n_q] q weights, host memory; NULL -> 1/n_q              */

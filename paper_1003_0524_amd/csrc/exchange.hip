@@ -930,8 +930,11 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     if (d->n_bands[k] < 1 || d->n_bands[k] > 128)
       return fail(nullptr, d->n_bands[k] < 1 ? EXC_EINVAL : EXC_EUNSUPPORTED,
                   "n_bands[%d] = %d outside [1, 128]", k, d->n_bands[k]);
-  for (int q = 0; q < d->n_q; ++q)
+  for (int q = 0; q < d->n_q; ++q) {
     if (d->n_pw[q] < 0) return fail(nullptr, EXC_EINVAL, "n_pw[%d] < 0", q);
+    if (d->n_channels + d->n_pw[q] < 1)          // no basis function at q: nothing to contract
+      return fail(nullptr, EXC_EINVAL, "the mixed basis of q = %d is empty (no channels, no plane waves)", q);
+  }
   for (int c = 0; c < d->n_channels; ++c)
     if (d->ch_nrad[c] < 1) return fail(nullptr, EXC_EINVAL, "ch_nrad[%d] < 1", c);
   if (d->w_q)

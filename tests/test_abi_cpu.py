@@ -58,6 +58,10 @@ def test_init_rejects_bad_sizes_without_gpu(lib):
     assert lib.exchange_init(ctypes.byref(d), ctypes.byref(c), None, ctypes.byref(out)) == -1
     d = pkg._Desc(1, 1, 1, 0, nb, pw, None, None, 2, 0, 1, 0)     # GEMM form is FP64 only
     assert lib.exchange_init(ctypes.byref(d), ctypes.byref(c), None, ctypes.byref(out)) == -6
+    pw0 = (ctypes.c_int32 * 1)(0)
+    d = pkg._Desc(1, 1, 1, 0, nb, pw0, None, None, 0, 1, 1, 0)    # empty mixed basis
+    assert lib.exchange_init(ctypes.byref(d), ctypes.byref(c), None, ctypes.byref(out)) == -1
+    assert b"empty" in lib.exchange_last_error(None)
     nb_big = (ctypes.c_int32 * 1)(129)
     d = pkg._Desc(1, 1, 1, 0, nb_big, pw, None, None, 0, 1, 1, 0)
     assert lib.exchange_init(ctypes.byref(d), ctypes.byref(c), None, ctypes.byref(out)) == -6
