@@ -3,7 +3,8 @@
 
 Data that respect the symmetry are built by copying: v(q) = v(rep_G(q)) (G the
 lattice's point group) and M(k,q) = M(k, rep_k(q)) (rep_k under the little group
-of k), on the small workload's fcc 2x2x2 mesh with its three irreducible k. Then
+of k), on the small workload's fcc 2x2x2 mesh with its three irreducible k and on a
+hexagonal 3x3x2 mesh with its six. Then
 the full-mesh V(k) equals |LG(k)| times the restricted, weighted sum (every
 member of an orbit contributes the same matrix), which pins the weights
 w_q / N_{k,q}. Bars: FP64 1e-12 normwise between the two GPU results and 1e-10
@@ -27,8 +28,17 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _symmetric_case():
-    cfg = synth.make_config("small")
+def _config(name):
+    if name == "small":
+        return synth.make_config("small")
+    # hexagonal (24 operations), 3 x 3 x 2 mesh with its 6 irreducible k: little groups of
+    # orders 24, 12 and 4
+    return synth.Config("hex_eibz", 25, 0, synth._hex(6.14, 9.84), synth._mesh(3, 3, 2), n_k=6, n_occ=2,
+                        n_bands=[12] * 6, ch_nrad=[3, 2, 1, 4], n_pw=[30] * 18)
+
+
+def _symmetric_case(name="small"):
+    cfg = _config(name)
     ops = sy.point_group(cfg.lattice)
     k_idx, _ = sy.irreducible(cfg.q_frac, ops)
     rep_g, _ = sy.orbits(cfg.q_frac, ops)
@@ -42,11 +52,12 @@ def _symmetric_case():
     return cfg, E_sym, D, C, per_k
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
-def test_eibz_sum_restores_the_full_sum(precision):
+@pytest.mark.parametrize("name,precision", [("small", "fp64"), ("small", "bf16x3"), ("hex", "fp64"),
+                                            ("hex", "bf16x3")])
+def test_eibz_sum_restores_the_full_sum(name, precision):
     import paper_1003_0524_amd as lib
-    cfg, E, D, C, per_k = _symmetric_case()
-    _say(f"[eibz] small precision={precision}")
+    cfg, E, D, C, per_k = _symmetric_case(name)
+    _say(f"[eibz] {cfg.name} precision={precision}")
     w_kq = np.stack([w for w, _, _ in per_k])
     kw = dict(w_q=cfg.weights_q(), precision=precision, form="herk", batched=True)
     full = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, **kw)
