@@ -39,6 +39,7 @@ CASES = [
     ("small", np.array([[1.0, 0.2, 0.1], [0.3, 0.9, -0.2], [0.0, 0.4, 1.3]]), (2, 3, 5), 0.02),   # skewed
     ("small", 2.0 * math.pi / 10.0 * np.eye(3), (4, 4, 4), 0.05),
     ("c2", None, (4, 4, 4), 0.005),                             # Si-like fcc, the paper's beta
+    ("small", 2.0 * math.pi * np.linalg.inv(synth._hex(6.14, 9.84)).T, (6, 6, 4), 0.005),   # ZnO-like hexagonal
 ]
 
 
