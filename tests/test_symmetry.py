@@ -4,8 +4,9 @@ meshes, little groups and the extended irreducible wedge EIBZ(k).
 Pins: the orders of the cubic and hexagonal holohedries (48, 24); the numbers of
 irreducible points of the Gamma-centred meshes the workloads use (fcc 2x2x2: 3,
 fcc 4x4x4: 8 as the Si workload states, sc 6x6x6: 20, hexagonal 6x6x4: 21);
-group closure; the orbit-stabiliser relation |orbit| N_{k,q} = |LG(k)|; and the
-little group checked against an independent floating-point test of k R = k + G.
+group closure; the orbit-stabiliser relation |orbit| N_{k,q} = |LG(k)|; the
+little group checked against an independent floating-point test of k R = k + G;
+and the EIBZ(k) sum of an LG(k)-invariant function equal to its full-mesh sum.
 """
 import math
 
@@ -67,3 +68,34 @@ def test_eibz_orbit_stabiliser(name):
         assert (w * n_lg).sum() == pytest.approx(1.0, abs=1e-12)
         if np.allclose(k, 0):
             assert sorted(members) == sorted(int(x) for x in idx)   # EIBZ(Gamma) = IBZ
+
+
+def _periodic_gaussian(f_frac: np.ndarray, B: np.ndarray, alpha: float = 2.0, nG: int = 6) -> np.ndarray:
+    """sum over reciprocal lattice vectors G of exp(-alpha |f B + G|^2): periodic in f and
+    unchanged by every operation of the lattice's point group (the G box reaches far enough
+    for the terms it leaves out to lie below 1e-12 of the sum on these lattices)."""
+    shifts = np.array(np.meshgrid(*[np.arange(-nG, nG + 1)] * 3, indexing="ij")).reshape(3, -1).T
+    p = (f_frac[:, None, :] + shifts[None, :, :]) @ B
+    return np.exp(-alpha * np.sum(p * p, axis=-1)).sum(axis=1)
+
+
+@pytest.mark.parametrize("name", ["small", "c2", "c3"])
+def test_eibz_sum_restores_the_full_mesh_sum(name):
+    """For a function f_k(q) = g(q + k) with g periodic and invariant under the whole point
+    group, f_k is invariant under LG(k) (but not under the whole group once k != 0), so
+    sum_q w_q f_k(q) = |LG(k)| sum_{q in EIBZ(k)} (w_q / N_{k,q}) f_k(q). Weights taken from
+    the whole group, or a wrong stabiliser count, break the equality for some k."""
+    cfg = synth.make_config(name)
+    ops = sy.point_group(cfg.lattice)
+    idx, _ = sy.irreducible(cfg.q_frac, ops)
+    B = cfg.recip()
+    for i in idx:
+        k = cfg.q_frac[i]
+        w, n_lg, _ = sy.eibz_weights(k, cfg.q_frac, ops)
+        f = _periodic_gaussian(cfg.q_frac + k, B)
+        full = f.mean()
+        assert n_lg * float(w @ f) == pytest.approx(full, rel=1e-12)
+        if n_lg < len(ops):
+            # the same sum with the whole group's orbits is not the full sum for this f
+            w_all, n_all, _ = sy.eibz_weights(np.zeros(3), cfg.q_frac, ops)
+            assert abs(n_all * float(w_all @ f) - full) > 1e-6 * abs(full)
