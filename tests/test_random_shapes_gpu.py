@@ -1,0 +1,87 @@
+"""GPU parity on seeded random shapes: band counts per k, occupied bands, channel sizes
+(including channels without multipole-free functions), plane waves per q and q points
+drawn at random inside the ranges the library documents (up to 40 bands in the first six
+cases, up to 100 in the rest), so that no tile size divides the problem. Each case goes
+through the batched FP64 Cholesky form, the unbatched FP64 GEMM form (which must refuse
+more than 64 bands with EXC_EUNSUPPORTED) and the batched FP32 / bf16x3 / bf16x6 forms
+(autotuned), and is compared element by element with the FP64 oracle. Bars as in the
+other parity tests: FP64 normwise 1e-10; reduced precision within 4x the error the
+input-rounding emulator predicts (plus 1e-12; for bf16x6, whose pieces carry binary32's 24
+bits, the larger of its own and the fp32 mode's prediction, since with 24-bit operands
+the error comes from the binary32 accumulation inside the matrix-core instruction, whose
+order the emulator can only assume); Hermitian mirror and real diagonal exact.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chol, precision as pr, vx
+
+torch = pytest.importorskip("torch")
+
+SEEDS = list(range(12))
+
+
+def _cfg(seed):
+    rng = np.random.default_rng([2718, seed])
+    n_k = int(rng.integers(1, 4))
+    n_q = int(rng.integers(2, 6))
+    n_bands = [int(x) for x in rng.integers(1, 41 if seed < 6 else 101, size=n_k)]
+    n_occ = int(rng.integers(1, min(5, min(n_bands)) + 1))
+    n_ch = int(rng.integers(0, 21))
+    ch = [int(x) for x in rng.integers(1, 8, size=n_ch)]
+    n_pw = [int(x) for x in rng.integers(0 if n_ch else 1, 131, size=n_q)]
+    q = rng.uniform(0.0, 1.0, size=(n_q, 3))
+    return synth.Config(f"random{seed}", 40 + seed, seed, 8.0 * np.eye(3), q, n_k=n_k, n_occ=n_occ,
+                        n_bands=n_bands, ch_nrad=ch, n_pw=n_pw)
+
+
+def test_shapes_are_drawn_inside_the_documented_ranges():
+    for s in SEEDS:
+        cfg = _cfg(s)
+        assert 1 <= min(cfg.n_bands) and max(cfg.n_bands) <= 128 and cfg.n_occ <= min(cfg.n_bands)
+        assert all(cfg.n_mb(q) > 0 for q in range(cfg.n_q))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,form,batched", [("fp64", "herk", True), ("fp64", "gemm", False),
+                                                    ("fp32", "herk", True), ("bf16x3", "herk", True),
+                                                    ("bf16x6", "herk", True)])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_matches_oracle(seed, precision, form, batched):
+    import paper_1003_0524_amd as lib
+    cfg = _cfg(seed)
+    print(f"[random] seed={seed} {precision} {form} batched={batched} n_b={cfg.n_bands} n_occ={cfg.n_occ} "
+          f"ch={len(cfg.ch_nrad)} n_pw={cfg.n_pw}", flush=True)
+    E, D, C = synth.coulomb_blocks(cfg)
+    if form == "gemm" and max(cfg.n_bands) > 64:          # the GEMM form stops at 64 bands
+        with pytest.raises(lib.ExchangeError) as e:
+            lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                         precision=precision, form=form, batched=batched)
+        assert e.value.status == -6
+        return
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form=form, batched=batched)
+    Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda()
+                                                  for k in range(cfg.n_k)])]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    for k in range(cfg.n_k):
+        blocks = [synth.m_block(cfg, k, q) for q in range(cfg.n_q)]
+        ref = vx.vx_k(blocks, v, cfg.weights_q())
+        err = pr.normwise_error(Vs[k], ref)
+        assert np.array_equal(Vs[k], Vs[k].conj().T)
+        assert np.all(np.diag(Vs[k]).imag == 0.0)
+        if precision == "fp64":
+            assert err <= 1e-10, (seed, k, err)
+        else:
+            L = [chol.cholesky(a) for a in v]
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), ref)
+            if precision == "bf16x6":
+                # three bf16 pieces carry 24 significant bits, as binary32 does, so the error
+                # is set by the binary32 accumulation; the emulator sums each 32-product chunk
+                # of a matrix-core instruction exactly and rounds once, an order the hardware
+                # does not document: the binary32 model with a rounding every 4 products
+                # (the fp32 mode's) bounds it as well
+                pred = max(pred, pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), "fp32"), ref))
+            assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
