@@ -9,7 +9,8 @@ other parity tests: FP64 normwise 1e-10; reduced precision within 4x the error t
 input-rounding emulator predicts (plus 1e-12; for bf16x6, whose pieces carry binary32's 24
 bits, the larger of its own and the fp32 mode's prediction, since with 24-bit operands
 the error comes from the binary32 accumulation inside the matrix-core instruction, whose
-order the emulator can only assume); Hermitian mirror and real diagonal exact.
+order the emulator can only assume); Hermitian mirror and real diagonal exact. The
+inversion-symmetric variant runs on the same shapes (FP64 and bf16x3).
 """
 import numpy as np
 import pytest
@@ -84,4 +85,36 @@ def test_random_shape_matches_oracle(seed, precision, form, batched):
                 # does not document: the binary32 model with a rounding every 4 products
                 # (the fp32 mode's) bounds it as well
                 pred = max(pred, pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), "fp32"), ref))
+            assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_inversion_variant(seed, precision):
+    """The inversion-symmetric variant (real v, real bands packed two per complex column,
+    odd occupied counts included) on the same shapes: FP64 1e-10 normwise against the real
+    oracle; bf16x3 within 4x the emulated error of the same packed product; V real and
+    exactly symmetric."""
+    import paper_1003_0524_amd as lib
+    cfg = _cfg(seed)
+    print(f"[random] seed={seed} inversion {precision} n_b={cfg.n_bands} n_occ={cfg.n_occ}", flush=True)
+    E, D, C = synth.coulomb_blocks_real(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True, inversion=True)
+    Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all_real_packed(cfg, k)).cuda()
+                                                  for k in range(cfg.n_k)])]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    L = [chol.cholesky(a) for a in v]
+    for k in range(cfg.n_k):
+        ref = vx.vx_k([synth.m_block_real(cfg, k, q) for q in range(cfg.n_q)], v, cfg.weights_q())
+        err = pr.normwise_error(Vs[k], ref)
+        assert not np.any(Vs[k].imag)
+        assert np.array_equal(Vs[k], Vs[k].T)
+        if precision == "fp64":
+            assert err <= 1e-10, (seed, k, err)
+        else:
+            packed = [synth.pack_real_pairs(synth.m_block_real(cfg, k, q)) for q in range(cfg.n_q)]
+            pred = pr.normwise_error(pr.vx_k_emulated(packed, L, cfg.weights_q(), precision).real, ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
