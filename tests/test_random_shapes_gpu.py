@@ -10,7 +10,8 @@ input-rounding emulator predicts (plus 1e-12; for bf16x6, whose pieces carry bin
 bits, the larger of its own and the fp32 mode's prediction, since with 24-bit operands
 the error comes from the binary32 accumulation inside the matrix-core instruction, whose
 order the emulator can only assume); Hermitian mirror and real diagonal exact. The
-inversion-symmetric variant runs on the same shapes (FP64 and bf16x3).
+inversion-symmetric variant and random per-pair weights (some zero) run on the same shapes
+(FP64 and bf16x3).
 """
 import numpy as np
 import pytest
@@ -117,4 +118,42 @@ def test_random_shape_inversion_variant(seed, precision):
         else:
             packed = [synth.pack_real_pairs(synth.m_block_real(cfg, k, q)) for q in range(cfg.n_q)]
             pred = pr.normwise_error(pr.vx_k_emulated(packed, L, cfg.weights_q(), precision).real, ref)
+            assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_pair_weights(seed, precision):
+    """Per-pair weights (exc_desc.w_kq, the EIBZ form of the q sum) drawn at random, about a
+    third of the pairs of each k at zero and left out of M(k), on the same shapes: FP64 1e-10
+    normwise against the oracle's weighted sum over the kept pairs; bf16x3 within 4x the
+    emulated error of that sum."""
+    import paper_1003_0524_amd as lib
+    cfg = _cfg(seed)
+    rng = np.random.default_rng([31337, seed])
+    w_kq = rng.uniform(0.05, 1.0, size=(cfg.n_k, cfg.n_q)) / cfg.n_q
+    w_kq[rng.random((cfg.n_k, cfg.n_q)) < 0.35] = 0.0
+    w_kq[np.arange(cfg.n_k), rng.integers(0, cfg.n_q, size=cfg.n_k)] = 0.5 / cfg.n_q   # a pair per k
+    print(f"[random] seed={seed} pair weights {precision} kept={int((w_kq != 0).sum())} of {w_kq.size}",
+          flush=True)
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True, w_kq=w_kq)
+    keep = [[q for q in range(cfg.n_q) if w_kq[k, q] != 0] for k in range(cfg.n_k)]
+    blocks = [[synth.m_block(cfg, k, q) for q in keep[k]] for k in range(cfg.n_k)]
+    Ms = [torch.from_numpy(np.concatenate([b.ravel() for b in blocks[k]])).cuda() for k in range(cfg.n_k)]
+    Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    L = [chol.cholesky(a) for a in v]
+    for k in range(cfg.n_k):
+        vk, wk = [v[q] for q in keep[k]], w_kq[k, keep[k]]
+        ref = vx.vx_k(blocks[k], vk, wk)
+        err = pr.normwise_error(Vs[k], ref)
+        assert np.array_equal(Vs[k], Vs[k].conj().T)
+        if precision == "fp64":
+            assert err <= 1e-10, (seed, k, err)
+        else:
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks[k], [L[q] for q in keep[k]], wk, precision), ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
