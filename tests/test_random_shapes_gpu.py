@@ -11,7 +11,8 @@ bits, the larger of its own and the fp32 mode's prediction, since with 24-bit op
 the error comes from the binary32 accumulation inside the matrix-core instruction, whose
 order the emulator can only assume); Hermitian mirror and real diagonal exact. The
 inversion-symmetric variant and random per-pair weights (some zero) run on the same shapes
-(FP64 and bf16x3).
+(FP64 and bf16x3), and so do the back-transform (random n_G) and the Gamma-point term
+(random skewed lattice, mesh and beta).
 """
 import numpy as np
 import pytest
@@ -157,3 +158,67 @@ def test_random_shape_pair_weights(seed, precision):
         else:
             pred = pr.normwise_error(pr.vx_k_emulated(blocks[k], [L[q] for q in keep[k]], wk, precision), ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
+
+
+def _colmajor(a):
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().T
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_back_transform(seed):
+    """Z V(k) Z^H (the back-transform to the LAPW basis) for every k of the shape, with a
+    random n_G in [1, 700] per k: 1e-12 normwise against the oracle's product of its own
+    V(k), Hermitian to 1e-13."""
+    import paper_1003_0524_amd as lib
+    from oracle import backx
+    cfg = _cfg(seed)
+    rng = np.random.default_rng([4242, seed])
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision="fp64", form="herk", batched=True)
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    try:
+        ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda() for k in range(cfg.n_k)])
+        for k in range(cfg.n_k):
+            nG, nb = int(rng.integers(1, 701)), cfg.n_bands[k]
+            print(f"[random] seed={seed} back-transform k={k} n_G={nG} n_b={nb}", flush=True)
+            Z = rng.standard_normal((nG, nb)) + 1j * rng.standard_normal((nG, nb))
+            G = ex.back_transform(k, _colmajor(Z)).cpu().numpy()
+            ref = backx.back_transform(Z, vx.vx_k([synth.m_block(cfg, k, q) for q in range(cfg.n_q)], v,
+                                                  cfg.weights_q()))
+            assert pr.normwise_error(G, ref) <= 1e-12, (seed, k, nG)
+            assert np.max(np.abs(G - G.conj().T)) <= 1e-13 * np.abs(G).max()
+    finally:
+        ex.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_gamma_term(seed):
+    """The Gamma-point term on a random (skewed) reciprocal lattice, mesh and beta: the
+    lattice-sum term count exactly, C to 1e-12 of the magnitude of its two terms."""
+    import math
+    import paper_1003_0524_amd as lib
+    from oracle import gamma as og
+    rng = np.random.default_rng([9001, seed])
+    a = rng.uniform(6.0, 12.0)
+    B = 2.0 * math.pi / a * (np.eye(3) + 0.3 * rng.uniform(-1.0, 1.0, size=(3, 3)))
+    mesh = tuple(int(x) for x in rng.integers(1, 7, size=3))
+    beta = float(rng.uniform(0.02, 0.2))
+    print(f"[random] seed={seed} gamma mesh={mesh} beta={beta:.4f}", flush=True)
+    cfg = _cfg(seed)
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision="fp64", form="herk", batched=True)
+    try:
+        Cg = ex.gamma_term(B, mesh, beta, apply=False)
+        _, nterm = ex.gamma_kernel_ms()
+    finally:
+        ex.close()
+    q0 = og.q0_of_beta(beta)
+    so, co = og.lattice_sum(B, mesh, beta, q0)
+    pref = 4.0 * math.pi / (int(np.prod(mesh)) * og.cell_volume(B))
+    Co = og.integral_term(beta, q0) - pref * so
+    assert nterm == co
+    assert abs(Cg - Co) <= 1e-12 * (og.integral_term(beta, q0) + pref * so)
