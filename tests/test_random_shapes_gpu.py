@@ -11,7 +11,7 @@ bits, the larger of its own and the fp32 mode's prediction, since with 24-bit op
 the error comes from the binary32 accumulation inside the matrix-core instruction, whose
 order the emulator can only assume); Hermitian mirror and real diagonal exact. The
 inversion-symmetric variant and random per-pair weights (some zero) run on the same shapes
-(FP64 and bf16x3), and so do the back-transform (random n_G) and the Gamma-point term
+(FP64 and bf16x3), as does M handed over in complex64, and so do the back-transform (random n_G) and the Gamma-point term
 (random skewed lattice, mesh and beta).
 """
 import numpy as np
@@ -222,3 +222,33 @@ def test_random_gamma_term(seed):
     Co = og.integral_term(beta, q0) - pref * so
     assert nterm == co
     assert abs(Cg - Co) <= 1e-12 * (og.integral_term(beta, q0) + pref * so)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_shape_complex64_input(seed, precision):
+    """M handed over as complex64 (as the ZnO- and SrTiO3-like workloads do): the oracle takes
+    the same complex64 values widened to complex128; FP64 1e-10 normwise, bf16x3 within 4x the
+    emulated error on those values."""
+    import paper_1003_0524_amd as lib
+    cfg = _cfg(seed)
+    print(f"[random] seed={seed} complex64 {precision} n_b={cfg.n_bands}", flush=True)
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True)
+    Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k, np.complex64)).cuda()
+                                                  for k in range(cfg.n_k)])]
+    ex.close()
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    L = [chol.cholesky(a) for a in v]
+    for k in range(cfg.n_k):
+        blocks = [synth.m_block(cfg, k, q, np.complex64).astype(np.complex128) for q in range(cfg.n_q)]
+        ref = vx.vx_k(blocks, v, cfg.weights_q())
+        err = pr.normwise_error(Vs[k], ref)
+        assert np.array_equal(Vs[k], Vs[k].conj().T)
+        if precision == "fp64":
+            assert err <= 1e-10, (seed, k, err)
+        else:
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), ref)
+            assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
