@@ -34,13 +34,14 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import List, Optional, Sequence
 
 import numpy as np
 
 __all__ = [
     "Config", "make_config", "coulomb_blocks", "m_block", "m_all",
-    "splitmix64_stream", "normal_pairs", "CONFIG_NAMES",
+    "splitmix64_stream", "normal_pairs", "CONFIG_NAMES", "m_all_device", "m_block_device",
 ]
 
 MASK64 = (1 << 64) - 1
@@ -414,3 +415,72 @@ def pack_real_pairs(m_real: np.ndarray, dtype=np.complex128) -> np.ndarray:
 def m_all_real_packed(cfg: Config, k: int, dtype=np.complex128) -> np.ndarray:
     """``pack_real_pairs`` of every q block of k, concatenated in mesh order (flat)."""
     return np.concatenate([pack_real_pairs(m_block_real(cfg, k, q), dtype).ravel() for q in range(cfg.n_q)])
+
+
+# ---------------------------------------------------------------------------
+# Device twin of the M generator (synth/csrc/synth.hip, built as synth/libsynth.so):
+# the same counter-mode SplitMix64 / Box-Muller values written straight into GPU
+# memory, for workloads whose M is too large to draw on the host (tens to hundreds
+# of GB). Only the draw happens on the device; nothing of the method.
+# ---------------------------------------------------------------------------
+_SYNTH_LIB = None
+SYNTH_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth.so")
+
+
+def _synth_lib():
+    global _SYNTH_LIB
+    if _SYNTH_LIB is None:
+        import ctypes
+        if not os.path.exists(SYNTH_LIB_PATH):
+            raise RuntimeError(f"{SYNTH_LIB_PATH} is not built; run `python -m paper_1003_0524_amd.build`")
+        lib = ctypes.CDLL(SYNTH_LIB_PATH)
+        lib.synth_fill_m.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_void_p]
+        lib.synth_fill_m.restype = ctypes.c_int32
+        _SYNTH_LIB = lib
+    return _SYNTH_LIB
+
+
+def _fill(dst_ptr: int, c64: bool, seed: int, n: int, nmb: int, stream_ptr: int) -> None:
+    import ctypes
+    st = _synth_lib().synth_fill_m(ctypes.c_void_p(dst_ptr), 1 if c64 else 0, ctypes.c_uint64(seed),
+                                   int(n), int(nmb), ctypes.c_void_p(stream_ptr))
+    if st != 0:
+        raise RuntimeError(f"synth_fill_m failed with status {st}")
+
+
+def m_block_device(cfg: Config, k: int, q: int, dtype: str = "c64", device=None):
+    """``m_block(cfg, k, q)`` drawn on the GPU: a flat torch tensor (complex64 for "c64",
+    complex128 for "c128") in device memory."""
+    import torch
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    n = cfg.n_occ * cfg.n_bands[k] * cfg.n_mb(q)
+    out = torch.empty(n, dtype=torch.complex64 if dtype == "c64" else torch.complex128, device=dev)
+    _fill(out.data_ptr(), dtype == "c64", stream_seed(cfg.seed, cfg.tag, k, _qid(cfg, q)), n, cfg.n_mb(q),
+          torch.cuda.current_stream(dev).cuda_stream)
+    return out
+
+
+def m_all_device(cfg: Config, k: int, dtype: str = "c64", device=None, out=None, keep=None):
+    """``m_all(cfg, k)`` drawn on the GPU into a flat torch tensor (``out`` if given, of
+    the right size and dtype). keep: optional [n_q] booleans, the q blocks to include
+    (in mesh order; for per-pair weights that leave pairs out)."""
+    import torch
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    qs = [q for q in range(cfg.n_q) if keep is None or keep[q]]
+    nb = cfg.n_bands[k]
+    sizes = [cfg.n_occ * nb * cfg.n_mb(q) for q in qs]
+    total = int(sum(sizes))
+    if out is None:
+        out = torch.empty(total, dtype=tdt, device=dev)
+    if out.dtype != tdt or out.numel() != total or not out.is_contiguous():
+        raise ValueError("out has the wrong dtype or size")
+    st = torch.cuda.current_stream(out.device).cuda_stream
+    esz = 8 if dtype == "c64" else 16
+    off = 0
+    for q, n in zip(qs, sizes):
+        _fill(out.data_ptr() + off * esz, dtype == "c64", stream_seed(cfg.seed, cfg.tag, k, _qid(cfg, q)), n,
+              cfg.n_mb(q), st)
+        off += n
+    return out
