@@ -92,8 +92,9 @@ typedef struct {
   int32_t n_q;              /* number of q points of the mesh (>= 1)                     */
   int32_t n_occ;            /* occupied bands n'' summed at every k-q (>= 1)             */
   int32_t n_channels;       /* (atom, L, M) channels (>= 0)                              */
-  const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k, 1..128 (the GEMM form:
-                               1..64; EXC_EUNSUPPORTED beyond)                           */
+  const int32_t *n_bands;   /* [n_k] bands n_b(k) = n_max at k, 1..128 (the batched GEMM
+                               form: 1..64, EXC_EUNSUPPORTED beyond; the unbatched GEMM
+                               form takes 1..128)                                        */
   const int32_t *n_pw;      /* [n_q] interstitial plane waves of q (>= 0; with no
                                channels at least 1, else EXC_EINVAL: empty basis)        */
   const int32_t *ch_nrad;   /* [n_channels] radial functions per channel (>= 1):
@@ -103,7 +104,10 @@ typedef struct {
   int32_t form;             /* exc_form                                                  */
   int32_t batched;          /* exchange_matrix_all: 1 = one persistent launch over all
                                (k,q) work captured in a HIP graph; 0 = one launch per
-                               (k,q) pair, no graph                                      */
+                               (k,q) pair, no graph. Unbatched, the GEMM form runs per
+                               pair the block-sparse rows of W = v A, W_d = E A_d + X and
+                               A^H W on FP64 matrix cores, and accumulates V(k) in FP64 in
+                               the order of q                                            */
   int32_t device;           /* HIP device ordinal                                        */
   int32_t inversion;        /* 1: inversion-symmetric system (Sec. III.D, symmetrized MT
                                functions): v(q) and the projections are real. Only the
@@ -188,9 +192,11 @@ exc_status exchange_energy(exc_ctx *ctx, const double *w_k, const void *const *r
  *   E_dev      : device pointer to one double, written on `stream` after the
  *                last exchange_matrix[_all] work (NULL stream: that work's stream;
  *                another stream is made to wait for it)
- * The sum over k is taken on the device in the order of k. Errors of the
- * enqueued kernels surface on the next synchronising call. EXC_ESTATE if some
- * V(k) was never computed.
+ * The sum over k is taken on the device in the order of k. Energy calls share the
+ * context's staging buffers: each call (this one and exchange_energy) first makes
+ * its stream wait for the previous energy call of the context, on whatever stream
+ * that ran. Errors of the enqueued kernels surface on the next synchronising call.
+ * EXC_ESTATE if some V(k) was never computed.
  */
 exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *const *rho_k,
                                   double *E_dev, void *stream);
@@ -212,7 +218,11 @@ exc_status exchange_energy_device(exc_ctx *ctx, const double *w_k, const void *c
  *           sum_i (j_i / mesh_i) b_i for integer j_i
  *   beta  : damping parameter, 0 < beta < 1 (the paper's choice is 0.005)
  *   apply : 1 -> every later exchange_matrix[_all] adds -C to the occupied diagonal
- *           of V(k) (and so to exchange_energy); 0 -> C is computed, no shift is applied
+ *           of V(k) (and so to exchange_energy); 0 -> C is computed, no shift is applied.
+ *           A context with per-pair weights (exc_desc.w_kq) returns EXC_EUNSUPPORTED
+ *           for apply = 1: its q sum is restricted (EIBZ(k)), the rotation over the
+ *           little group that completes it happens outside the library, and the shift
+ *           must enter the completed sum once -- the caller adds -C after the rotation
  *   C_out : host, receives C (may be NULL)
  * The lattice sum runs on the GPU in FP64 in a fixed order (the same inputs give
  * the same bits). The call waits for earlier exchange_matrix[_all] work, runs on

@@ -160,6 +160,8 @@ class Exchange:
         if w_kq is not None:
             wkq_arr = np.ascontiguousarray(np.asarray(w_kq, dtype=np.float64).reshape(self.n_k, self.n_q))
         self.pair_used = (np.ones((self.n_k, self.n_q), dtype=bool) if wkq_arr is None else wkq_arr != 0.0)
+        n_s = int(sum(int(b) - 1 for b in ch_nrad))
+        self.n_mb = [n_s + len(ch_nrad) + int(p) for p in n_pw]
         desc = _Desc(self.n_k, self.n_q, self.n_occ, len(ch_nrad), nb_p, pw_p,
                      ch_p if len(ch_nrad) else None,
                      wq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wq_arr is not None else None,
@@ -196,17 +198,38 @@ class Exchange:
             return DTYPES["c64"]
         raise ExchangeError(-1, f"M must be complex64 or complex128, got {M.dtype}")
 
-    def m_elems(self, k: int, n_mb: Sequence[int]) -> int:
+    def m_elems(self, k: int, n_mb: Optional[Sequence[int]] = None) -> int:
+        """Complex elements of M(k): the q blocks of the pairs k computes, [n''][n][I] each."""
+        n_mb = self.n_mb if n_mb is None else n_mb
         return int(sum(self.n_cols * self.n_bands[k] * int(n) for q, n in enumerate(n_mb) if self.pair_used[k, q]))
+
+    def _check_m(self, k: int, M) -> None:
+        """The kernels size their reads from the context's shapes, not from the buffer: a
+        short M (or one that still holds the blocks of pairs left out by w_kq) is refused
+        before anything is launched."""
+        n = int(M.numel()) if hasattr(M, "numel") else int(np.asarray(M).size)
+        want = self.m_elems(k)
+        if n != want:
+            raise ExchangeError(-1, f"M(k={k}) has {n} elements, the context needs {want} "
+                                    f"(n_occ columns x n_b(k) x N_MB(q) over the computed q)")
+
+    def _check_out(self, k: int, out) -> None:
+        t = self._torch
+        nb = self.n_bands[k]
+        if out.dtype != t.complex128 or int(out.numel()) != nb * nb or not out.is_contiguous():
+            raise ExchangeError(-1, f"out for k={k} must be a contiguous complex128 tensor of {nb * nb} elements")
 
     # -- API ---------------------------------------------------------------
     def matrix(self, k: int, M, out=None):
         """V^x(k) (n_b x n_b complex128, column-major storage returned as its transpose view)."""
         t = self._torch
         nb = self.n_bands[k]
+        self._dtype_code(M)
+        self._check_m(k, M)
         if out is None:
             out = t.empty(nb * nb, dtype=t.complex128, device=M.device)
-        if not (M.is_cuda and M.is_contiguous() and out.is_cuda and out.is_contiguous()):
+        self._check_out(k, out)
+        if not (M.is_cuda and M.is_contiguous() and out.is_cuda):
             raise ExchangeError(-1, "M and out must be contiguous device tensors")
         st = self.lib.exchange_matrix(self.ctx, int(k), ctypes.c_void_p(M.data_ptr()), self._dtype_code(M), 1,
                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(t, self.device))
@@ -217,12 +240,20 @@ class Exchange:
         t = self._torch
         if len(Ms) != self.n_k:
             raise ExchangeError(-1, f"need {self.n_k} M tensors")
+        code = self._dtype_code(Ms[0])
+        for k, M in enumerate(Ms):
+            if self._dtype_code(M) != code:
+                raise ExchangeError(-1, "all M must have one dtype")
+            self._check_m(k, M)
         if outs is None:
             outs = [t.empty(nb * nb, dtype=t.complex128, device=Ms[0].device) for nb in self.n_bands]
-        code = self._dtype_code(Ms[0])
-        for M in Ms:
-            if not (M.is_cuda and M.is_contiguous()) or self._dtype_code(M) != code:
-                raise ExchangeError(-1, "all M must be contiguous device tensors of one dtype")
+        if len(outs) != self.n_k:
+            raise ExchangeError(-1, f"need {self.n_k} output tensors")
+        for k, o in enumerate(outs):
+            self._check_out(k, o)
+        for M, o in zip(Ms, outs):
+            if not (M.is_cuda and M.is_contiguous() and o.is_cuda):
+                raise ExchangeError(-1, "all M and outputs must be contiguous device tensors")
         mp = (ctypes.c_void_p * self.n_k)(*[M.data_ptr() for M in Ms])
         vp = (ctypes.c_void_p * self.n_k)(*[o.data_ptr() for o in outs])
         st = self.lib.exchange_matrix_all(self.ctx, mp, code, 1, vp, _stream_handle(t, self.device))
@@ -236,6 +267,7 @@ class Exchange:
         code = DTYPES["c64"] if M.dtype == np.complex64 else DTYPES["c128"]
         if M.dtype not in (np.complex64, np.complex128):
             raise ExchangeError(-1, "M must be complex64 or complex128")
+        self._check_m(k, M)
         out = np.empty(nb * nb, dtype=np.complex128)
         st = self.lib.exchange_matrix(self.ctx, int(k), ctypes.c_void_p(M.ctypes.data), code, 0,
                                       ctypes.c_void_p(out.ctypes.data), _stream_handle(self._torch, self.device))

@@ -21,6 +21,7 @@
 #include "fused.hpp"
 #include "gamma.hpp"
 #include "backx.hpp"
+#include "plain.hpp"
 
 using namespace exc;
 
@@ -145,6 +146,7 @@ struct exc_ctx {
   std::vector<int> nb, npw, nrad, nd, nmb;
   std::vector<double> wq;
   std::vector<double> wkq;            // [n_k * n_q] weight of pair (k, q); 0: pair not computed
+  bool has_wkq = false;               // the caller gave per-pair weights
   int n_s = 0, nb_max = 0, nbt_max = 0, ns_pad = 0;
   std::vector<int> ch_off, ch_len;
   std::vector<int64_t> ch_coef;
@@ -179,7 +181,11 @@ struct exc_ctx {
   int fsplit = 0;                     // fused batched items: 1 = one per n'' chunk (more, smaller items)
   int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
   bool tune_done = false;
-  size_t ws_bytes = 0;                // block-sparse workspace the unfused path needs
+  size_t ws_bytes = 0;                // block-sparse workspace of all pairs (the batched graph)
+  size_t ws_elem = 16;                // bytes per workspace element
+  std::vector<int64_t> k_ws_start;    // [n_k + 1] first workspace element of each k's pairs
+  size_t ws_k_bytes = 0;              // the largest workspace of one k (per-k calls)
+  size_t ws_cap = 0;                  // bytes allocated at d_ws (grown on demand)
   void* d_ws = nullptr;
   double* d_dsp = nullptr;
   void* d_gpart = nullptr;
@@ -200,6 +206,8 @@ struct exc_ctx {
   hipGraphExec_t gexec = nullptr;
   hipStream_t own = nullptr;          // capturable stream of the batched path
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_en = nullptr;         // end of the last energy call (its buffers are shared)
+  bool ev_en_set = false;
   int g_dtype = -1;
   // live kernel timing of the batched path: event-record nodes around the
   // sparse and tile kernels; one pool entry (3 events) per graph replay
@@ -224,6 +232,13 @@ struct exc_ctx {
   hipEvent_t ev_bt[2] = {nullptr, nullptr};
   bool bt_timed = false;
   hipStream_t last_stream = nullptr;
+  // plain GEMM form (unbatched): one pair at a time through sparse_kernel<0> and zgemm_kernel
+  bool plain_gemm = false;
+  PairInfo* d_ppairs = nullptr;       // the pairs with the column pitch of W = v A (N_MB, offset 0)
+  double2* d_pw = nullptr;            // W of one pair, laid out as M
+  double2* d_pg = nullptr;            // split partials of A^H W of one pair
+  double2* d_pvacc = nullptr;         // the upper triangle of V(k) being accumulated
+  std::vector<int> p_split;           // [pairs] splits of the MPB index in A^H W
   // accounting
   double flops_nominal = 0, flops_exec = 0, bytes_alg = 0;
   // learned extrapolator
@@ -257,6 +272,7 @@ exc_status dalloc(exc_ctx* c, T** p, size_t n) {
   if (n == 0) n = 1;
   if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
     *p = nullptr;
+    (void)hipGetLastError();          // a failed allocation must not surface at a later launch check
     return fail(c, EXC_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
   }
   return EXC_OK;
@@ -272,6 +288,30 @@ exc_status upload(exc_ctx* c, T** d, const std::vector<T>& h) {
   TRY(dalloc(c, d, h.size()));
   if (!h.empty()) HIPCHK(c, hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return EXC_OK;
+}
+
+// The block-sparse workspace holds `bytes` (the pairs of one k, or of every k for the
+// batched graph). Growing it waits for the device: earlier launches may still use it.
+exc_status ensure_ws(exc_ctx* c, size_t bytes) {
+  if (c->d_ws && c->ws_cap >= bytes) return EXC_OK;
+  if (c->d_ws) {
+    HIPCHK(c, hipDeviceSynchronize());
+    hipFree(c->d_ws);
+    c->d_ws = nullptr;
+    c->ws_cap = 0;
+  }
+  TRY(dalloc(c, (char**)&c->d_ws, bytes));
+  c->ws_cap = bytes;
+  return EXC_OK;
+}
+
+// Workspace base for the pairs of k (k < 0: every pair). Pair offsets are global; a
+// per-k call keeps only its own pairs' rows, so the base is shifted back by the
+// first offset of k (an address the kernels never form below the allocation).
+void* ws_base(const exc_ctx* c, int k) {
+  if (!c->d_ws) return nullptr;
+  if (k < 0) return c->d_ws;
+  return (void*)((uintptr_t)c->d_ws - (uintptr_t)c->k_ws_start[k] * c->ws_elem);
 }
 
 size_t lds_elem_size(int mode) { return mode == M_F64 ? 8 : (mode == M_F32 ? 4 : 2); }
@@ -300,6 +340,8 @@ void release(exc_ctx* c) {
   c->graph = nullptr;
   release_timing(c);
   if (c->ev_in) hipEventDestroy(c->ev_in);
+  if (c->ev_en) hipEventDestroy(c->ev_en);
+  c->ev_en = nullptr;
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own) hipStreamDestroy(c->own);
   for (hipEvent_t& e : c->ev_g) if (e) hipEventDestroy(e);
@@ -312,7 +354,8 @@ void release(exc_ctx* c) {
                   c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
-                  c->d_gamma, c->d_gpartial, c->d_bt, c->d_tmask};
+                  c->d_gamma, c->d_gpartial, c->d_bt, c->d_tmask, c->d_ppairs, c->d_pw, c->d_pg,
+                  c->d_pvacc};
   for (void* p : ptrs) if (p) hipFree(p);
   free_plan(c->plain);
   free_plan(c->bat);
@@ -494,7 +537,7 @@ exc_status set_tables(exc_ctx* c, int k0, int nk, const void* const* M, void* co
   return EXC_OK;
 }
 
-TileArgs tile_args(exc_ctx* c, int dtype) {
+TileArgs tile_args(exc_ctx* c, int dtype, int k) {
   TileArgs a{};
   a.pairs = c->d_pairs;
   a.mtab = (const void* const*)c->d_mtab;
@@ -503,7 +546,7 @@ TileArgs tile_args(exc_ctx* c, int dtype) {
   a.n_ch = c->n_ch;
   a.ns_pad = c->ns_pad;
   a.U = c->d_U;
-  a.ws = c->d_ws;
+  a.ws = ws_base(c, k);
   a.dsp = c->d_dsp;
   a.dsp_stride = c->n_occ * c->nb_max;
   a.gpart = c->d_gpart;
@@ -514,7 +557,7 @@ TileArgs tile_args(exc_ctx* c, int dtype) {
   return a;
 }
 
-SparseArgs sparse_args(exc_ctx* c, int dtype) {
+SparseArgs sparse_args(exc_ctx* c, int dtype, int k) {
   SparseArgs s{};
   s.pairs = c->d_pairs;
   s.mtab = (const void* const*)c->d_mtab;
@@ -522,7 +565,7 @@ SparseArgs sparse_args(exc_ctx* c, int dtype) {
   s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max; s.ns_pad = c->ns_pad;
   s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
   s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
-  s.ws = c->d_ws; s.dsp = c->d_dsp;
+  s.ws = ws_base(c, k); s.dsp = c->d_dsp;
   return s;
 }
 
@@ -585,12 +628,13 @@ const void* sparse_fn(const exc_ctx* c) {
   }
 }
 
-// Block-sparse rows of pairs [pair0, pair0 + npairs). Returns false when there is nothing to do.
-bool cfg_sparse(exc_ctx* c, int dtype, int pair0, int npairs, SparseArgs& s, KLaunch& L) {
+// Block-sparse rows of pairs [pair0, pair0 + npairs), all of k (k < 0: every pair). Returns
+// false when there is nothing to do.
+bool cfg_sparse(exc_ctx* c, int dtype, int k, int pair0, int npairs, SparseArgs& s, KLaunch& L) {
   if (c->fused) return false;                    // the fused kernel does the block-sparse rows itself
   const bool packs = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;   // packs the dense rows too
   if (!packs && c->n_s == 0 && (c->form == EXC_FORM_CHOL_HERK || c->n_ch == 0)) return false;
-  s = sparse_args(c, dtype);
+  s = sparse_args(c, dtype, k);
   s.pairs = c->d_pairs + pair0;
   // dsp is indexed by blockIdx.y: offset it to the first pair
   s.dsp = c->d_dsp ? c->d_dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
@@ -626,7 +670,7 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   L.arg = &r;
 }
 
-void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persistent, MainArgs& m,
+void cfg_tile(exc_ctx* c, int dtype, int k, const WorkItem* items, int n, bool persistent, MainArgs& m,
               KLaunch& L) {
   L.grid = dim3(persistent ? std::min(n, c->persist_grid) : n);
   L.shmem = 0;
@@ -644,7 +688,7 @@ void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persiste
     return;
   }
   TileArgs& a = m.t;
-  a = tile_args(c, dtype);
+  a = tile_args(c, dtype, k);
   a.items = items;
   a.n_items = n;
   a.counter = persistent ? c->d_counter : nullptr;
@@ -653,10 +697,10 @@ void cfg_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, bool persiste
   L.arg = &a;
 }
 
-void launch_sparse(exc_ctx* c, int dtype, int pair0, int npairs, hipStream_t st) {
+void launch_sparse(exc_ctx* c, int dtype, int k, int pair0, int npairs, hipStream_t st) {
   SparseArgs s;
   KLaunch L;
-  if (cfg_sparse(c, dtype, pair0, npairs, s, L)) (void)enqueue(L, st);
+  if (cfg_sparse(c, dtype, k, pair0, npairs, s, L)) (void)enqueue(L, st);
 }
 
 void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
@@ -666,31 +710,90 @@ void launch_reduce(exc_ctx* c, const Plan& P, int k0, int nk, hipStream_t st) {
   (void)enqueue(L, st);
 }
 
-void launch_tile(exc_ctx* c, int dtype, const WorkItem* items, int n, hipStream_t st) {
+void launch_tile(exc_ctx* c, int dtype, int k, const WorkItem* items, int n, hipStream_t st) {
   if (n <= 0) return;
   MainArgs a;
   KLaunch L;
-  cfg_tile(c, dtype, items, n, false, a, L);
+  cfg_tile(c, dtype, k, items, n, false, a, L);
   (void)enqueue(L, st);
 }
 
 // One k, batched over its q: sparse rows of all pairs of k, one tile launch, reduce.
-void run_k_batched(exc_ctx* c, int k, int dtype, hipStream_t st) {
+exc_status run_k_batched(exc_ctx* c, int k, int dtype, hipStream_t st) {
+  if (!c->fused) TRY(ensure_ws(c, c->ws_k_bytes));
   const int p0 = c->k_pair[k], p1 = c->k_pair[k + 1];
-  launch_sparse(c, dtype, p0, p1 - p0, st);
+  launch_sparse(c, dtype, k, p0, p1 - p0, st);
   const Plan& P = c->bat;
-  launch_tile(c, dtype, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], st);
+  launch_tile(c, dtype, k, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], st);
   launch_reduce(c, P, k, 1, st);
+  return EXC_OK;
 }
 
 // One k, plain form: one launch of each kernel per (k, q) pair.
-void run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
+exc_status run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
+  if (!c->fused) TRY(ensure_ws(c, c->ws_k_bytes));
   const Plan& P = c->plain;
   for (int p = c->k_pair[k]; p < c->k_pair[k + 1]; ++p) {
-    launch_sparse(c, dtype, p, 1, st);
-    launch_tile(c, dtype, P.d_items + P.pair_item[p], P.pair_item[p + 1] - P.pair_item[p], st);
+    launch_sparse(c, dtype, k, p, 1, st);
+    launch_tile(c, dtype, k, P.d_items + P.pair_item[p], P.pair_item[p + 1] - P.pair_item[p], st);
   }
   launch_reduce(c, P, k, 1, st);
+  return EXC_OK;
+}
+
+// Plain GEMM form, one k: per (k, q) pair the block-sparse rows of W = v A
+// (sparse_kernel<0>), the dense rows W_d = E A_d + X (zgemm_kernel), the band
+// contraction G_b = A_b^H W_b split over the MPB index (zgemm_kernel) and its FP64
+// accumulation into V(k); then V(k) with its mirror. One launch of each kernel per pair.
+constexpr int PG_BM = 64, PG_BNC = 64, PG_KC = 16;
+exc_status run_k_plain_gemm(exc_ctx* c, int k, int dtype, hipStream_t st) {
+  const bool c64 = dtype == EXC_C64;
+  const size_t esz = c64 ? 8 : 16;
+  const char* Mk = (const char*)c->h_mtab[k];
+  for (int p = c->k_pair[k]; p < c->k_pair[k + 1]; ++p) {
+    const PairInfo& pi = c->pairs[p];
+    const int ncol = c->n_occ * pi.nb;
+    // block-sparse rows of W and X = C_c^H A_c into the multipole rows
+    if (c->n_s > 0 || c->n_ch > 0) {
+      SparseArgs sa = sparse_args(c, dtype, -1);
+      sa.pairs = c->d_ppairs + p;
+      sa.ws = c->d_pw;
+      sa.dsp = nullptr;
+      hipLaunchKernelGGL((sparse_kernel<0, M_F64>), dim3((ncol + 3) / 4, 1), dim3(256), sparse_lds_bytes(c), st, sa);
+    }
+    if (pi.nd > 0) {
+      ZgemmArgs z{};
+      z.a = (const double*)c->d_U + pi.u_off;
+      z.lda = pi.ldu; z.a_plane = (int64_t)pi.ldu * pi.ldu; z.a_kind = 0; z.a_rows_alloc = pi.ldu;
+      z.b = Mk + (pi.m_off + c->n_s) * esz; z.ldb = pi.nmb; z.b_c64 = c64;
+      z.c = c->d_pw + c->n_s; z.ldc = pi.nmb;
+      z.M = pi.nd; z.N = ncol; z.K = pi.nd; z.kchunk = (pi.nd + PG_KC - 1) / PG_KC * PG_KC;
+      z.add_rows = c->n_ch;
+      const int tiles = ((pi.nd + PG_BM - 1) / PG_BM) * ((ncol + PG_BNC - 1) / PG_BNC);
+      hipLaunchKernelGGL((zgemm_kernel<PG_BM, PG_BNC, PG_KC, 2>), dim3(tiles, 1, 1), dim3(256), 0, st, z);
+    }
+    {
+      ZgemmArgs z{};
+      z.a = Mk + pi.m_off * esz; z.lda = pi.nmb; z.a_bstride = (int64_t)pi.nb * pi.nmb; z.a_kind = 1;
+      z.a_c64 = c64; z.a_conj = 1;
+      z.b = c->d_pw; z.ldb = pi.nmb; z.b_bstride = (int64_t)pi.nb * pi.nmb;
+      z.c = c->d_pg; z.ldc = pi.nb; z.c_bstride = (int64_t)pi.nb * pi.nb;
+      z.c_sstride = (int64_t)c->n_occ * pi.nb * pi.nb;
+      z.M = z.N = pi.nb; z.K = pi.nmb; z.upper = 1;
+      const int ns = c->p_split[p];
+      z.kchunk = ((pi.nmb + ns - 1) / ns + PG_KC - 1) / PG_KC * PG_KC;
+      const int nt = (pi.nb + PG_BM - 1) / PG_BM;
+      hipLaunchKernelGGL((zgemm_kernel<PG_BM, PG_BNC, PG_KC, 2>), dim3(nt * nt, c->n_occ, ns), dim3(256), 0, st, z);
+      hipLaunchKernelGGL(pair_accumulate_kernel, dim3((pi.nb * pi.nb + 255) / 256), dim3(256), 0, st,
+                         (const double2*)c->d_pg, ns, c->n_occ, pi.nb, c->pair_w[p], (int)(p == c->k_pair[k]),
+                         c->d_pvacc);
+    }
+  }
+  const int nb = c->nb[k];
+  hipLaunchKernelGGL(pair_finish_kernel, dim3((nb * nb + 255) / 256), dim3(256), 0, st, (const double2*)c->d_pvacc,
+                     nb, c->n_occ_v, (const double*)(c->d_gamma + 3), (int)c->real_v,
+                     (const uint64_t*)(c->d_tmask + 3 * k), c->d_vres + c->v_off[k], (double2*)c->h_vtab[k]);
+  return EXC_OK;
 }
 
 // The batched path as an explicit graph:
@@ -700,6 +803,7 @@ void run_k_plain(exc_ctx* c, int k, int dtype, hipStream_t st) {
 // The event-record nodes exist only while kernel timing is on; their events are
 // swapped per replay (hipGraphExecEventRecordNodeSetEvent).
 exc_status build_batched_graph(exc_ctx* c, int dtype) {
+  if (!c->fused) TRY(ensure_ws(c, c->ws_bytes));   // every pair's block-sparse rows at once
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
   const bool timed = c->t_slots > 0;
@@ -715,7 +819,7 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   };
   SparseArgs sa;
   KLaunch L;
-  if (e == hipSuccess && cfg_sparse(c, dtype, 0, (int)c->pairs.size(), sa, L)) {
+  if (e == hipSuccess && cfg_sparse(c, dtype, -1, 0, (int)c->pairs.size(), sa, L)) {
     e = add_ev(0);                      // (the fused path has no block-sparse kernel to time)
     if (e == hipSuccess) e = add_node(g, L, last ? &last : nullptr, &node);
     last = node;
@@ -723,7 +827,7 @@ exc_status build_batched_graph(exc_ctx* c, int dtype) {
   e = add_ev(1);
   MainArgs ta;
   if (e == hipSuccess) {
-    cfg_tile(c, dtype, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
+    cfg_tile(c, dtype, -1, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
     e = add_node(g, L, last ? &last : nullptr, &node);
     last = node;
   }
@@ -759,19 +863,23 @@ exc_status configure(exc_ctx* c, const FusedKCfg* f, hipStream_t st) {
   if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
   HIPCHK(c, hipStreamSynchronize(st));
   if (c->own) HIPCHK(c, hipStreamSynchronize(c->own));
+  // the block-sparse workspace itself is sized at first use: the pairs of one k for
+  // per-k calls, every pair for the batched graph
   const bool need_ws = !c->fused;
-  if (need_ws && !c->d_ws) TRY(dalloc(c, (char**)&c->d_ws, c->ws_bytes));
-  if (!need_ws && c->d_ws) { hipFree(c->d_ws); c->d_ws = nullptr; }
+  if (!need_ws && c->d_ws) { hipFree(c->d_ws); c->d_ws = nullptr; c->ws_cap = 0; }
   if (need_ws && mixed_herk && !c->d_dsp) {
     const size_t n = c->pairs.size() * (size_t)c->n_occ * c->nb_max;
     TRY(dalloc(c, &c->d_dsp, n));
     HIPCHK(c, hipMemset(c->d_dsp, 0, n * sizeof(double)));
   }
   if (!need_ws && c->d_dsp) { hipFree(c->d_dsp); c->d_dsp = nullptr; }
+  // only the plan of the context's path: one item per pair (or n'' chunk) for the batched
+  // path, one per (n'' chunk, row block) for one launch per pair
   free_plan(c->plain);
   free_plan(c->bat);
-  TRY(build_plan(c, c->plain, 1));
-  TRY(build_plan(c, c->bat, 0));
+  c->plain.n_slots = c->bat.n_slots = 0;
+  if (c->batched) TRY(build_plan(c, c->bat, 0));
+  else TRY(build_plan(c, c->plain, 1));
   const size_t nslot = std::max(c->plain.n_slots, c->bat.n_slots);
   const size_t asz = c->precision == EXC_FP64 ? 8 : 4;
   hipFree(c->d_gpart);
@@ -871,7 +979,8 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
     exc_status s2 = configure(c, f, st);
     if (s2 == EXC_ENOMEM) { c->err.clear(); continue; }   // e.g. no room for the block-sparse workspace
     if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
-    if ((s2 = build_batched_graph(c, dtype)) != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
+    if ((s2 = build_batched_graph(c, dtype)) == EXC_ENOMEM) { c->err.clear(); continue; }   // workspace too large
+    if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
     HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
     HIPCHK(c, hipEventRecord(e0, c->own));
     for (int r = 0; r < 5; ++r) HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
@@ -977,6 +1086,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (c->n_ch) c->nrad.assign(d->ch_nrad, d->ch_nrad + c->n_ch);
   c->wq.resize(c->n_q);
   for (int q = 0; q < c->n_q; ++q) c->wq[q] = d->w_q ? d->w_q[q] : 1.0 / c->n_q;
+  c->has_wkq = d->w_kq != nullptr;
   c->wkq.resize((size_t)c->n_k * c->n_q);
   for (int k = 0; k < c->n_k; ++k)
     for (int q = 0; q < c->n_q; ++q)
@@ -999,8 +1109,14 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   }
   c->nb_max = *std::max_element(c->nb.begin(), c->nb.end());
   c->nbt_max = (c->nb_max + 7) / 8;
+  // the unbatched GEMM form runs one pair at a time through its own kernels (any band count)
+  c->plain_gemm = c->form == EXC_FORM_GEMM && !c->batched;
   c->cfg = pick_cfg(c->precision, c->form, c->nbt_max);
-  if (!c->cfg) { fail(c, EXC_EUNSUPPORTED, "no tile configuration for n_b = %d", c->nb_max); return bail(EXC_EUNSUPPORTED); }
+  if (!c->cfg && !c->plain_gemm) {
+    fail(c, EXC_EUNSUPPORTED, "no tile configuration for n_b = %d%s", c->nb_max,
+         c->form == EXC_FORM_GEMM ? " (the batched GEMM form takes at most 64 bands)" : "");
+    return bail(EXC_EUNSUPPORTED);
+  }
   if (c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64) {
     const char* ev = getenv("EXC_FUSED");
     c->fcfg = pick_fused(c->precision, c->nbt_max, c->real_v);
@@ -1009,7 +1125,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     c->fused = c->fused_ok && !(ev && ev[0] == '0');
     if (!c->fused) c->fcfg = nullptr;
   }
-  const int BM = c->cfg->BM;
+  const int BM = c->cfg ? c->cfg->BM : 64;
 
   c->nd.resize(c->n_q); c->nmb.resize(c->n_q); c->ldu.resize(c->n_q); c->u_off.resize(c->n_q);
   const int npl = 2 * npieces(c->precision);
@@ -1150,6 +1266,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   const int ws_cols = split_ws ? 2 * npieces(c->precision) : 1;   // planes per column
   int64_t ws_total = 0, m_max = 0;
   c->k_pair.assign(1, 0);
+  c->k_ws_start.assign(1, 0);
+  int64_t ws_kmax = 0;
   for (int k = 0; k < c->n_k; ++k) {
     int64_t moff = 0;
     for (int q = 0; q < c->n_q; ++q) {
@@ -1179,6 +1297,8 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     }
     m_max = std::max(m_max, moff);
     c->m_len.push_back(moff);
+    ws_kmax = std::max(ws_kmax, ws_total - c->k_ws_start.back());
+    c->k_ws_start.push_back(ws_total);
     c->k_pair.push_back((int)c->pairs.size());
   }
   for (int k = 0; k < c->n_k; ++k)
@@ -1210,7 +1330,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   ITRY(upload(c, &c->d_pair_w, c->pair_w));
   ITRY(upload(c, &c->d_pair_begin, std::vector<int32_t>(c->k_pair.begin(), c->k_pair.end())));
   const size_t wsz = split_ws ? lds_elem_size(c->precision) : 16;
+  c->ws_elem = wsz;
   c->ws_bytes = (size_t)std::max<int64_t>(1, ws_total) * wsz;
+  c->ws_k_bytes = (size_t)std::max<int64_t>(1, ws_kmax) * wsz;
   const int nbt = c->nbt_max;
   c->gstride = nbt * (nbt + 1) / 2 * 256;
   c->dstride = nbt * 8;
@@ -1240,10 +1362,34 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = ev[0] == '1';   // (fixed-configuration runs)
-  ITRY(configure(c, c->fused ? c->fcfg : nullptr, st));
+  if (c->plain_gemm) {
+    // W of the largest pair (laid out as M), the split partials of A^H W, the V(k) accumulator
+    std::vector<PairInfo> pp(c->pairs);
+    size_t w_max = 1, g_max = 1;
+    c->p_split.resize(c->pairs.size());
+    for (size_t i = 0; i < pp.size(); ++i) {
+      pp[i].ws_off = 0;
+      pp[i].ldw = pp[i].nmb;
+      w_max = std::max(w_max, (size_t)pp[i].nmb * c->n_occ * pp[i].nb);
+      // split the MPB index so that the band contraction has about 512 workgroups
+      const int nt = (pp[i].nb + PG_BM - 1) / PG_BM, tiles = nt * (nt + 1) / 2 * c->n_occ;
+      int ns = std::max(1, std::min((512 + tiles - 1) / tiles, (pp[i].nmb + 63) / 64));
+      const int kch = ((pp[i].nmb + ns - 1) / ns + PG_KC - 1) / PG_KC * PG_KC;
+      ns = (pp[i].nmb + kch - 1) / kch;
+      c->p_split[i] = ns;
+      g_max = std::max(g_max, (size_t)ns * c->n_occ * pp[i].nb * pp[i].nb);
+    }
+    ITRY(upload(c, &c->d_ppairs, pp));
+    ITRY(dalloc(c, &c->d_pw, w_max));
+    ITRY(dalloc(c, &c->d_pg, g_max));
+    ITRY(dalloc(c, &c->d_pvacc, (size_t)c->nb_max * c->nb_max));
+  } else {
+    ITRY(configure(c, c->fused ? c->fcfg : nullptr, st));
+  }
   IHIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   IHIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   IHIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  IHIP(hipEventCreateWithFlags(&c->ev_en, hipEventDisableTiming));
   IHIP(hipStreamSynchronize(st));
 #undef ITRY
 #undef IHIP
@@ -1278,8 +1424,9 @@ exc_status exchange_matrix(exc_ctx* c, int32_t k, const void* M, int32_t dtype, 
   const void* mp[1] = {Md};
   void* vp[1] = {Vd};
   TRY(set_tables(c, k, 1, mp, vp, st));
-  if (c->batched) run_k_batched(c, k, dtype, st);
-  else run_k_plain(c, k, dtype, st);
+  if (c->plain_gemm) TRY(run_k_plain_gemm(c, k, dtype, st));
+  else if (c->batched) TRY(run_k_batched(c, k, dtype, st));
+  else TRY(run_k_plain(c, k, dtype, st));
   HIPCHK(c, hipGetLastError());
   if (!on_device) {
     HIPCHK(c, hipMemcpyAsync(Vx, c->d_vres + c->v_off[k], (size_t)c->nb[k] * c->nb[k] * 16,
@@ -1306,7 +1453,8 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
   HIPCHK(c, hipSetDevice(c->device));
   if (!c->batched) {
     TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
-    for (int k = 0; k < c->n_k; ++k) run_k_plain(c, k, dtype, st);
+    for (int k = 0; k < c->n_k; ++k)
+      TRY(c->plain_gemm ? run_k_plain_gemm(c, k, dtype, st) : run_k_plain(c, k, dtype, st));
     HIPCHK(c, hipGetLastError());
   } else {
     if (!c->tune_done) {
@@ -1351,6 +1499,8 @@ exc_status exchange_energy(exc_ctx* c, const double* w_k, const void* const* rho
   for (int k = 0; k < c->n_k; ++k)
     if (!c->v_valid[k]) return fail(c, EXC_ESTATE, "V(k=%d) has not been computed", k);
   hipStream_t st = c->last_stream;
+  // the energy buffers are shared by every energy call: after the previous one, on any stream
+  if (c->ev_en_set) HIPCHK(c, hipStreamWaitEvent(st, c->ev_en, 0));
   void** d_rho = nullptr;
   if (rho_k) {
     TRY(dalloc(c, &d_rho, (size_t)c->n_k));
@@ -1363,6 +1513,8 @@ exc_status exchange_energy(exc_ctx* c, const double* w_k, const void* const* rho
                      (const void* const*)d_rho, c->n_occ_v, c->d_eout);
   std::vector<double> e(c->n_k);
   hipError_t e1 = hipGetLastError();
+  if (e1 == hipSuccess) e1 = hipEventRecord(c->ev_en, st);
+  c->ev_en_set = e1 == hipSuccess;
   hipError_t e2 = hipStreamSynchronize(st);
   hipError_t e3 = hipMemcpy(e.data(), c->d_eout, c->n_k * sizeof(double), hipMemcpyDeviceToHost);
   if (d_rho) hipFree(d_rho);
@@ -1384,6 +1536,9 @@ exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* con
     HIPCHK(c, hipEventRecord(c->ev_out, c->last_stream));
     HIPCHK(c, hipStreamWaitEvent(st, c->ev_out, 0));
   }
+  // the staging buffers (weights, rho pointers, per-k energies) are shared by every energy
+  // call: after the previous one, whatever its stream
+  if (c->ev_en_set) HIPCHK(c, hipStreamWaitEvent(st, c->ev_en, 0));
   // the host arrays are copied before this call returns (pageable source)
   if (w_k) HIPCHK(c, hipMemcpyAsync(c->d_ewk, w_k, c->n_k * sizeof(double), hipMemcpyHostToDevice, st));
   if (rho_k) HIPCHK(c, hipMemcpyAsync(c->d_erho, rho_k, c->n_k * sizeof(void*), hipMemcpyHostToDevice, st));
@@ -1397,6 +1552,8 @@ exc_status exchange_energy_device(exc_ctx* c, const double* w_k, const void* con
                        c->n_k, c->n_occ_v, w_k ? c->d_ewk : nullptr, E_dev);
   }
   HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(c->ev_en, st));
+  c->ev_en_set = true;
   return EXC_OK;
 }
 
@@ -1409,6 +1566,9 @@ exc_status exchange_gamma_term(exc_ctx* c, const double* recip, const int32_t* m
     if (mesh[i] < 1) return fail(c, EXC_EINVAL, "mesh[%d] = %d < 1", i, mesh[i]);
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(recip[i])) return fail(c, EXC_EINVAL, "recip[%d] is not finite", i);
+  if (apply && c->has_wkq)
+    return fail(c, EXC_EUNSUPPORTED, "the Gamma-point shift enters the full q sum once; with per-pair weights "
+                "(w_kq) add -C to the occupied diagonal after the rotation over the little group of k");
   // cofactor rows of B: a_i = 2 pi cof_i / det B are the real-space vectors
   const double(*B)[3] = (const double(*)[3])recip;
   double cof[3][3];
@@ -1554,7 +1714,7 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 0: *value = c->bat.n_slots; return EXC_OK;
     case 1: *value = c->flops_nominal; return EXC_OK;
     case 2: *value = c->flops_exec; return EXC_OK;
-    case 3: *value = c->fused ? c->fcfg->id : (c->cfg ? c->cfg->id : -1); return EXC_OK;
+    case 3: *value = c->plain_gemm ? 900 : (c->fused ? c->fcfg->id : (c->cfg ? c->cfg->id : -1)); return EXC_OK;
     case 4: *value = c->bytes_alg; return EXC_OK;
     case 5:
     case 7: {

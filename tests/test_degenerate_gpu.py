@@ -40,14 +40,16 @@ def test_degenerate_shapes(name, precision, form):
     cfg = _cfg(name)
     print(f"[degenerate] {name} {precision} {form}", flush=True)
     E, D, C = synth.coulomb_blocks(cfg)
-    if form == "gemm" and max(cfg.n_bands) > 64:          # the GEMM form stops at 64 bands
+    # the GEMM form runs unbatched (one launch of each kernel per pair), the HERK forms batched
+    batched = form != "gemm"
+    if form == "gemm" and max(cfg.n_bands) > 64:
+        # the batched GEMM form (persistent tile kernel) stops at 64 bands
         with pytest.raises(lib.ExchangeError) as e:
             lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
                          precision=precision, form=form, batched=True)
         assert e.value.status == -6
-        return
     ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
-                      precision=precision, form=form, batched=True)
+                      precision=precision, form=form, batched=batched)
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda()
                                                   for k in range(cfg.n_k)])]
     e_gpu = ex.energy()

@@ -234,9 +234,14 @@ def test_outer_loop_gain_over_stale():
     assert any(not r.exact for r in recs)
     for r in judged:
         assert r.err_pred is not None and r.err_stale is not None
-        assert r.err_pred < r.err_stale, r
-    # the network removes most of the stale error, and is accepted at tau = 1e-4
-    assert np.mean([r.err_pred / r.err_stale for r in judged]) < 0.5
+        # on the block the network predicts it beats the stale V; on the whole spectrum
+        # (the other eigenvalues keep the anchor's values) it is no worse
+        assert r.err_pred_block < r.err_stale_block, r
+        assert r.err_pred <= r.err_stale * (1 + 1e-6) + 1e-15, r
+        assert r.err_pred >= r.err_pred_block
+    # the network removes most of the stale error on its block, and the whole spectrum of the
+    # V it hands on is within tau = 1e-4 (acceptance is judged on every eigenvalue)
+    assert np.mean([r.err_pred_block / r.err_stale_block for r in judged]) < 0.5
     assert all(r.accepted for r in judged)
 
 
@@ -251,7 +256,8 @@ def test_outer_loop_at_zno_like_shapes():
     """The outer-iteration scheme at the ZnO-like workload's per-pair shapes: 60 bands,
     18 occupied, N_MB 827-1399 (its Gamma, smallest and largest mixed basis) on the
     first 4 irreducible k, 30 iterations, 10 training pairs, judged every 5th. The
-    network must beat the stale V^x at every judgement and be accepted at 1e-4 Ha."""
+    network must beat the stale V^x on its block at every judgement, be no worse on the
+    whole spectrum and be accepted at 1e-4 Ha on every eigenvalue."""
     import synth
     import synth.scf as scf
     from paper_1003_0524_amd import learned
@@ -275,6 +281,7 @@ def test_outer_loop_at_zno_like_shapes():
     judged = [r for r in recs if r.judged]
     assert [r.t for r in judged] == [15, 20, 25, 30]
     for r in judged:
-        assert r.err_pred < r.err_stale, r
-    assert np.mean([r.err_pred / r.err_stale for r in judged]) < 0.5
+        assert r.err_pred_block < r.err_stale_block, r
+        assert r.err_pred <= r.err_stale * (1 + 1e-6) + 1e-15, r
+    assert np.mean([r.err_pred_block / r.err_stale_block for r in judged]) < 0.5
     assert all(r.accepted for r in judged)
