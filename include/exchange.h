@@ -301,10 +301,13 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
 /*
  * Autotuning (reduced-precision Cholesky/HERK contexts, batched path): the first
  * exchange_matrix_all times every main-kernel configuration that can serve the
- * context (fused instances with enough band tiles; the block-sparse + tile
- * kernels; then the fused instances again with a work item per n'' chunk) on the
- * caller's own inputs, one untimed and five timed runs each, and keeps the
- * fastest (later candidates must win by more than 3 %). Environment: EXC_TUNE=0
+ * context and the element type of M (fused instances with enough band tiles; for
+ * complex64 M also the wide instances for large pairs; the block-sparse + tile
+ * kernels; then, when the (k, q) pairs number fewer than 8 per CU, the fused
+ * instances again with a work item per n'' chunk) on the caller's own inputs: one
+ * untimed run, one timed run (a candidate more than twice as slow as the best so far
+ * stops there) and five more timed runs, keeping the fastest (later candidates must
+ * win by more than 3 %). Environment: EXC_TUNE=0
  * keeps the default choice; EXC_TUNE_CACHE=<file> looks the choice up / appends
  * it under a key of the problem's sizes; EXC_FUSED_CFG=<id> fixes a fused
  * instance (EXC_FUSED_SPLIT=1: an item per n'' chunk) and EXC_FUSED=0 the

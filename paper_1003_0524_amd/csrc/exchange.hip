@@ -19,6 +19,7 @@
 #include "aux.hpp"
 #include "tile.hpp"
 #include "fused.hpp"
+#include "wide.hpp"
 #include "gamma.hpp"
 #include "backx.hpp"
 #include "plain.hpp"
@@ -76,6 +77,8 @@ struct FusedKCfg {
   size_t lds;
   int id;
   bool realf = false;               // real factor only (inversion-symmetric contexts)
+  int nt = 256;                     // threads per workgroup
+  bool c64only = false;             // reads complex64 M only (the wide kernel)
 };
 
 #define FCFG(MODE, RTW, NCT, NB8M, KC, ID)                                                       \
@@ -91,6 +94,11 @@ struct FusedKCfg {
 #define FCFG2R(MODE, RTW, NCT, NB8M, ID)                                                         \
   FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2, true>, \
             FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID, true}
+
+// wide kernel (large pairs, complex64 M): 8 wavefronts, 256-row dense blocks, NB8M band tiles
+#define WCFG(MODE, NB8M, RT, ID)                                                                  \
+  FusedKCfg{MODE, RT, NB8M, NB8M, 32, 32, 1, wide_kernel<MODE, NB8M, RT>, WideCfg<MODE, NB8M, RT>::LDS_B, \
+            ID, false, 512, true}
 
 // Listed in order of preference among equal band-tile capacity (the two-per-CU
 // instances first: they hide more memory latency).
@@ -111,6 +119,9 @@ const FusedKCfg kFused[] = {
     FCFG2R(M_F32, 2, 6, 3, 250),       FCFG2R(M_F32, 3, 6, 3, 251),
     FCFG2R(M_BF16X3, 3, 6, 3, 261),    FCFG2R(M_BF16X3, 2, 6, 3, 260),
     FCFG2R(M_BF16X6, 2, 6, 3, 270),    FCFG2R(M_BF16X6, 3, 6, 3, 271),
+    WCFG(M_F32, 13, 2, 180),           WCFG(M_BF16X3, 13, 2, 181),        WCFG(M_BF16X6, 13, 2, 182),
+    WCFG(M_F32, 16, 2, 183),           WCFG(M_BF16X3, 16, 2, 184),
+    WCFG(M_F32, 13, 1, 186),           WCFG(M_BF16X3, 13, 1, 187),        WCFG(M_BF16X6, 13, 1, 188),
 };
 
 struct Plan {
@@ -491,20 +502,23 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
 }
 
 // Real-factor instances serve only contexts with a real factor; there they are
-// preferred over the general ones of the same capacity.
-bool fused_fits(const FusedKCfg& k, int mode, int nbt_max, bool real) {
-  return k.mode == mode && k.NB8M >= nbt_max && k.NCT >= nbt_max && (real || !k.realf);
+// preferred over the general ones of the same capacity. dtype: the element type of M
+// (-1: not known yet -- instances that read complex64 only are left out).
+bool fused_fits(const FusedKCfg& k, int mode, int nbt_max, bool real, int dtype) {
+  return k.mode == mode && k.NB8M >= nbt_max && k.NCT >= nbt_max && (real || !k.realf) &&
+         (!k.c64only || (dtype == EXC_C64 && !real));
 }
 
-const FusedKCfg* pick_fused(int mode, int nbt_max, bool real) {
+const FusedKCfg* pick_fused(int mode, int nbt_max, bool real, int dtype = -1) {
   const FusedKCfg* best = nullptr;
   if (const char* ev = getenv("EXC_FUSED_CFG")) {      // a fixed configuration id (tuning runs)
     const int id = atoi(ev);
     for (const auto& k : kFused)
-      if (k.id == id && fused_fits(k, mode, nbt_max, real)) return &k;
+      if (k.id == id && fused_fits(k, mode, nbt_max, real, k.c64only && dtype < 0 ? EXC_C64 : dtype))
+        return &k;                                      // (at set-up the M type is not known yet)
   }
   for (const auto& k : kFused) {
-    if (!fused_fits(k, mode, nbt_max, real)) continue;
+    if (!fused_fits(k, mode, nbt_max, real, dtype) || k.c64only) continue;
     if (!best || k.NB8M < best->NB8M || (k.NB8M == best->NB8M && k.realf && !best->realf)) best = &k;
   }
   return best;
@@ -682,7 +696,7 @@ void cfg_tile(exc_ctx* c, int dtype, int k, const WorkItem* items, int n, bool p
     f.counter = persistent ? c->d_counter : nullptr;
     f.qbeg = c->bat.d_qbeg;
     f.nq = c->bat.nq;
-    L.block = dim3(256);
+    L.block = dim3(c->fcfg->nt);
     L.fn = (const void*)c->fcfg->fn;
     L.arg = &f;
     return;
@@ -891,7 +905,7 @@ exc_status configure(exc_ctx* c, const FusedKCfg* f, hipStream_t st) {
   HIPCHK(c, hipMemset(c->d_gpart, 0, nslot * c->gstride * asz));
   HIPCHK(c, hipMemset(c->d_dpart, 0, nslot * (size_t)c->dstride * 8));
   const void* main_fn = c->fused ? (const void*)c->fcfg->fn : (const void*)c->cfg->fn;
-  const int main_threads = c->fused ? 256 : 64 * c->cfg->NW();
+  const int main_threads = c->fused ? c->fcfg->nt : 64 * c->cfg->NW();
   hipFuncAttributes fa{};
   HIPCHK(c, hipFuncGetAttributes(&fa, main_fn));
   if (fa.maxThreadsPerBlock < main_threads)
@@ -936,11 +950,14 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
   std::vector<std::pair<const FusedKCfg*, int>> cands;
   if (c->fused_ok)
     for (const auto& k : kFused)
-      if (fused_fits(k, c->precision, c->nbt_max, c->real_v)) cands.push_back({&k, 0});
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v, dtype)) cands.push_back({&k, 0});
   cands.push_back({nullptr, 0});                 // block-sparse + tile kernels
-  if (c->fused_ok && c->n_occ > 1)
+  // items per n'' chunk only where the pairs alone leave the CUs short of work
+  int n_cu = 256;
+  (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (c->fused_ok && c->n_occ > 1 && (int)c->pairs.size() < 8 * n_cu)
     for (const auto& k : kFused)
-      if (fused_fits(k, c->precision, c->nbt_max, c->real_v) &&
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v, dtype) &&
           std::min(c->n_occ, k.NCT / c->nbt_max) < c->n_occ) cands.push_back({&k, 1});
   const std::string key = tune_key(c, dtype);
   const char* cache = getenv("EXC_TUNE_CACHE");
@@ -981,13 +998,22 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
     if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
     if ((s2 = build_batched_graph(c, dtype)) == EXC_ENOMEM) { c->err.clear(); continue; }   // workspace too large
     if (s2 != EXC_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s2; }
+    // one untimed run, then one timed: a candidate more than twice as slow as the best so
+    // far is dropped there; the others are timed over five more runs
     HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
     HIPCHK(c, hipEventRecord(e0, c->own));
-    for (int r = 0; r < 5; ++r) HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
     HIPCHK(c, hipEventRecord(e1, c->own));
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (any && ms > 2.0f * best_ms) continue;
+    HIPCHK(c, hipEventRecord(e0, c->own));
+    for (int r = 0; r < 5; ++r) HIPCHK(c, hipGraphLaunch(c->gexec, c->own));
+    HIPCHK(c, hipEventRecord(e1, c->own));
+    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    ms /= 5.0f;
     // candidates come in order of preference: a later one must be clearly faster
     if (!any || ms < 0.97f * best_ms) { best_ms = ms; best = f; best_split = cd.second; any = true; }
   }
@@ -1004,6 +1030,14 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
     }
   }
   return EXC_OK;
+}
+
+// The wide kernel reads complex64 M only: a call with complex128 M switches the context
+// to the best instance for it (which drops the captured graph).
+exc_status fit_dtype(exc_ctx* c, int dtype, hipStream_t st) {
+  if (!c->fused || !c->fcfg->c64only || dtype == EXC_C64) return EXC_OK;
+  c->fsplit = 0;
+  return configure(c, pick_fused(c->precision, c->nbt_max, c->real_v, dtype), st);
 }
 
 exc_status check_ctx(const exc_ctx* c) {
@@ -1423,6 +1457,7 @@ exc_status exchange_matrix(exc_ctx* c, int32_t k, const void* M, int32_t dtype, 
   }
   const void* mp[1] = {Md};
   void* vp[1] = {Vd};
+  TRY(fit_dtype(c, dtype, st));
   TRY(set_tables(c, k, 1, mp, vp, st));
   if (c->plain_gemm) TRY(run_k_plain_gemm(c, k, dtype, st));
   else if (c->batched) TRY(run_k_batched(c, k, dtype, st));
@@ -1452,6 +1487,7 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
   c->last_stream = st;
   HIPCHK(c, hipSetDevice(c->device));
   if (!c->batched) {
+    TRY(fit_dtype(c, dtype, st));
     TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
     for (int k = 0; k < c->n_k; ++k)
       TRY(c->plain_gemm ? run_k_plain_gemm(c, k, dtype, st) : run_k_plain(c, k, dtype, st));
@@ -1471,6 +1507,7 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
       }
       c->tune_done = true;
     }
+    TRY(fit_dtype(c, dtype, st));                  // (a fixed or earlier choice may read complex64 only)
     bool same = c->gexec && c->g_dtype == dtype;
     for (int k = 0; k < c->n_k && same; ++k)
       if (c->h_mtab[k] != M_k[k] || c->h_vtab[k] != Vx_k[k]) same = false;

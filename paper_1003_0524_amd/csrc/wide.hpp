@@ -1,0 +1,665 @@
+// Wide exchange kernel for large (k, q) pairs in the reduced-precision Cholesky/HERK
+// form (complex64 M): the same work item and partial layout as fused_kernel -- a
+// pair and a range of n'' values, G = sum_{n''} Y^H Y with Y = [Y_s ; Y_d],
+// Y_s = L_c^H A_c + l_c a_{j(c)} (block-sparse rows, FP64 VALU) and Y_d = L22^H A_d
+// (dense rows, MFMA in the mode's pieces) -- laid out for mixed bases of thousands
+// of functions and 50-128 bands (Sec. III.C, eq. "vec-mat-vec"; Fig. 1 sparsity):
+//
+//  * 8 wavefronts (two per SIMD), one workgroup per CU: while one wavefront of a
+//    SIMD waits at a barrier or on memory the other issues matrix instructions;
+//  * dense row blocks of 256 rows (two 16-row tiles per wavefront), so each K panel
+//    of A_d is read and converted once for 256 rows of the factor;
+//  * K panels of A_d move global -> LDS by direct buffer loads three panels ahead
+//    (complex64: 26 KB a panel), are split into bf16 / FP32 pieces once per panel
+//    (binary32 arithmetic: complex64 inputs split exactly as from their float64
+//    value), into one of two piece buffers: one workgroup barrier per panel;
+//  * the factor pieces of the wavefront's rows come from L2 one panel ahead;
+//  * the Gram tiles of an n'' chunk stay in registers (at most 17 per wavefront) and
+//    go to the item's partial slot once per chunk (not once per 64 rows).
+// The block-sparse phase is fused_kernel's (chunks of whole channels, DPP lane
+// shifts), with 32 columns per step (four per wavefront).
+#pragma once
+#include "fused.hpp"
+
+namespace exc {
+
+template <int MODE, int NB8M, int RTW = 2>
+struct WideCfg {
+  using T = Traits<MODE>;
+  using lds_t = typename T::lds_t;
+  static constexpr int NW = 8, NT = 512;
+  static constexpr int RT = RTW;                      // 16-row tiles per wavefront of a dense row block
+  static constexpr int BM = 16 * RT * NW;             // rows of a dense row block
+  static constexpr int NP = T::NPIECE, KS = T::KS, KPL = KS / 4, NPL = 2 * NP;
+  static constexpr int KC = 32;                       // k of a K panel
+  static constexpr int NCT = NB8M, NCC = 8 * NCT;     // band tiles (8 complex columns each), columns
+  static constexpr int ESZ = (int)sizeof(lds_t), EPV = 16 / ESZ;
+  static constexpr int APL = NCC * KC;                // one piece plane of a panel: [column][k]
+  static constexpr int PCS = NPL * APL;               // one piece buffer (elements)
+  static constexpr int RAWP = NCC * KC * 8;           // bytes of a raw complex64 panel
+  static constexpr int NI = (RAWP + 1023) / 1024;     // 1 KB direct loads per panel
+  static constexpr int NIW = (NI + NW - 1) / NW;      // per wavefront (the extra ones land in a trash KB)
+  static constexpr int RAW_B = NI * 1024;
+  // factor loads per wavefront and panel: each lane takes 8 consecutive k of a row per piece
+  // plane (one 16-byte load for bf16 pieces, two for FP32)
+  static constexpr int NFL = RT * 2 * (MODE == M_F32 ? 2 : NP);
+  // block-sparse phase
+  static constexpr int GR = 64, CB = 32, CPW = CB / NW, MPC = GR / CPW, MAXT = 12, MAXCK = 64;
+  static constexpr int NCB = (NCC + CB - 1) / CB;
+  static constexpr int LDRS = GR + EPV;
+  static constexpr int SP_MP = 0, SP_CF = SP_MP + CB * MPC * 16, SP_ST = SP_CF + MAXT * GR * 16;
+  static constexpr size_t SPARSE_B = (size_t)SP_ST + (size_t)NPL * NCC * LDRS * ESZ;
+  static constexpr size_t DACC_B = (size_t)NW * NCC * 2 * sizeof(double);
+  static constexpr size_t BUDGET = 163840 - 16 * MAXCK - 256;
+  // Gram stage of the dense rows: GS rows at a time (rows contiguous per column)
+  static constexpr int GS = (BM >= 128 && (size_t)NPL * NCC * (128 + EPV) * ESZ + DACC_B <= BUDGET) ? 128 : 64;
+  static constexpr int LDR = GS + EPV;
+  static constexpr size_t STAGE_B = (size_t)NPL * NCC * LDR * ESZ;
+  static constexpr size_t PIECE_B = (size_t)2 * PCS * ESZ;
+  static constexpr int NRAW = ((size_t)3 * RAW_B + 1024 + PIECE_B + DACC_B <= BUDGET) ? 3 : 2;
+  static constexpr size_t KLOOP_B = (size_t)NRAW * RAW_B + 1024 + PIECE_B;
+  static constexpr size_t M1 = KLOOP_B > STAGE_B ? KLOOP_B : STAGE_B;
+  static constexpr size_t M2 = M1 > SPARSE_B ? M1 : SPARSE_B;
+  static constexpr size_t MAIN_B = (M2 + 15) / 16 * 16;
+  static constexpr size_t LDS_B = MAIN_B + DACC_B;
+  static constexpr int NPT = NB8M * (NB8M + 1) / 2;
+  static constexpr int NPW = (NPT + NW - 1) / NW;     // Gram tiles per wavefront (round robin)
+  static_assert(MODE != M_F64, "the wide kernel serves the reduced-precision modes");
+  static_assert(LDS_B <= BUDGET, "wide configuration exceeds the 160 KB of LDS");
+  static_assert((size_t)2 * RAW_B + 1024 + PIECE_B + DACC_B <= BUDGET, "at least two raw panels in flight");
+  static_assert(KC == 32 && GS % KS == 0 && GR % KS == 0, "whole MFMA steps; 8 k per lane a panel");
+  static_assert(CPW * MPC == 64 && CB % NW == 0, "one multipole block load per wavefront and step");
+  static_assert(NCC * (KC / 8) <= NT, "one conversion unit per thread and panel");
+};
+
+// vmcnt(n) alone (gfx9 encoding: expcnt and lgkmcnt at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit count");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Split 4 consecutive k of one value into the mode's pieces and store each piece
+// plane's 4 values (8 B for bf16, 16 B for FP32) at dst + plane * ps.
+template <int MODE>
+__device__ __forceinline__ void store_pieces4(typename Traits<MODE>::lds_t* dst, int ps, float x0, float x1,
+                                              float x2, float x3) {
+  if constexpr (MODE == M_F32) {
+    *(f4_t*)dst = f4_t{x0, x1, x2, x3};
+  } else {
+    constexpr int NP = Traits<MODE>::NPIECE;
+    uint16_t h0[NP], h1[NP], h2[NP], h3[NP];
+    split_f<NP>(x0, h0);
+    split_f<NP>(x1, h1);
+    split_f<NP>(x2, h2);
+    split_f<NP>(x3, h3);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      *(uint2*)(dst + (long)p * ps) = make_uint2((uint32_t)h0[p] | ((uint32_t)h1[p] << 16),
+                                                 (uint32_t)h2[p] | ((uint32_t)h3[p] << 16));
+  }
+}
+
+template <int MODE, int NB8M, int RTW>
+__global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
+  using C = WideCfg<MODE, NB8M, RTW>;
+  using lds_t = typename C::lds_t;
+  using acc_t = typename Traits<MODE>::acc_t;
+  using accv_t = typename Traits<MODE>::accv_t;
+  using op_t = decltype(lds_operand<MODE>((const lds_t*)nullptr));
+  constexpr int NW = C::NW, NT = C::NT, NP = C::NP, KS = C::KS, KPL = C::KPL, NPL = C::NPL;
+  constexpr int NCC = C::NCC, NCT = C::NCT, KC = C::KC, APL = C::APL, PCS = C::PCS, RT = C::RT;
+  constexpr int BM = C::BM, GR = C::GR, GS = C::GS, LDR = C::LDR, NIW = C::NIW, NI = C::NI;
+  constexpr int NRAW = C::NRAW, NFL = C::NFL;
+
+  __shared__ __align__(16) unsigned char smem[C::LDS_B];
+  __shared__ int s_item;
+  __shared__ int4 s_chunk[C::MAXCK];
+  __shared__ int s_left[NQ_MAX];
+  unsigned char* Raw = smem;                                        // NRAW x [NCC][KC] complex64
+  unsigned char* Trash = smem + NRAW * C::RAW_B;                    // 1 KB for the padding loads
+  lds_t* Pcs = (lds_t*)(smem + NRAW * C::RAW_B + 1024);             // 2 x [NPL][NCC][KC] pieces
+  lds_t* Ys = (lds_t*)smem;                                         // [NPL][NCC][LDR] Gram stage
+  double* Dacc = (double*)(smem + C::MAIN_B);                       // [NW][NCC][2]
+
+  const int tid0 = threadIdx.x;
+  const int nq = a.counter ? a.nq : 1;
+  const int G = (int)gridDim.x;
+  const int qi = a.counter ? (int)(blockIdx.x % nq) : 0;
+  auto n_static = [&](int q) { return (G - q + nq - 1) / nq; };
+  int qh0 = 0, qh1 = 0;
+  int idx;
+  if (a.counter) {
+    qh0 = uni(a.qbeg[qi]);
+    qh1 = uni(a.qbeg[qi + 1]);
+    const int j = qh0 + (int)blockIdx.x / nq;
+    idx = j < qh1 ? j : -1;
+  } else {
+    idx = (int)blockIdx.x < a.n_items ? (int)blockIdx.x : -1;
+  }
+  bool home = a.counter != nullptr;
+  auto steal = [&]() -> int {
+    if (tid0 < nq) {
+      const int cnt = __hip_atomic_load(a.counter + tid0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_left[tid0] = a.qbeg[tid0] + n_static(tid0) + cnt < a.qbeg[tid0 + 1];
+    }
+    __syncthreads();
+    int got = -1;
+    for (int o = 1; o < nq && got < 0; ++o) {
+      const int q = (qi + o) % nq;
+      if (!s_left[q]) continue;
+      if (tid0 == 0) s_item = atomicAdd(a.counter + q, 1);
+      __syncthreads();
+      const int j = a.qbeg[q] + n_static(q) + __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+      if (j < a.qbeg[q + 1]) got = j;
+    }
+    __syncthreads();
+    return uni(got);
+  };
+
+  for (;;) {
+    if (idx < 0) {
+      if (!a.counter) break;
+      idx = steal();
+      if (idx < 0) break;
+    }
+    int claim = 0;
+    if (home && tid0 == 0) claim = atomicAdd(a.counter + qi, 1);
+
+    int tid_o = tid0;
+    asm volatile("" : "+v"(tid_o));
+    const int tid = tid_o, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int c8 = l16 & 7, part = l16 >> 3;
+
+    WorkItem wi = a.items[idx];
+    wi.pair = uni(wi.pair); wi.g0 = uni(wi.g0); wi.g1 = uni(wi.g1); wi.ngc = uni(wi.ngc); wi.slot = uni(wi.slot);
+    PairInfo pi = a.pairs[wi.pair];
+    pi.k = uni(pi.k); pi.nb = uni(pi.nb); pi.nmb = uni(pi.nmb); pi.nd = uni(pi.nd); pi.nb8 = uni(pi.nb8);
+    pi.m_off = uni(pi.m_off); pi.u_off = uni(pi.u_off); pi.ldu = uni(pi.ldu);
+    const int nb = pi.nb, nb8 = pi.nb8, nbt = nb8 >> 3;
+    const uint32_t nb8_rcp = uni((int32_t)(0xFFFFFFFFu / (uint32_t)nb8 + 1u));
+    const int npt = nbt * (nbt + 1) / 2;
+    const int nd = pi.nd;
+    constexpr int esz = 8;                                          // complex64 M
+    const char* mbase = uni((const char*)a.mtab[pi.k]) + pi.m_off * esz;
+    const __amdgpu_buffer_rsrc_t mrs = make_rsrc(mbase, (uint32_t)((long)a.n_occ * nb * pi.nmb * esz));
+    const lds_t* Ug = (const lds_t*)a.U + pi.u_off;
+    const long plane = (long)pi.ldu * pi.ldu;
+    const __amdgpu_buffer_rsrc_t urs = make_rsrc(Ug, (uint32_t)(NPL * plane * C::ESZ));
+    const uint32_t u_lane = (uint32_t)((l16 * pi.ldu + 8 * lq) * C::ESZ);
+
+    accv_t gacc[C::NPW];
+#pragma unroll
+    for (int s = 0; s < C::NPW; ++s) gacc[s] = accv_t{0, 0, 0, 0};
+    acc_t* gp = (acc_t*)a.gpart + (long)wi.slot * a.gstride;
+    for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
+    const uint64_t wkeep = tile_keep_bits(a.tmask, pi.k, w, NW, C::NPW);
+
+    // ---- contraction of ROWS staged rows (pitch `pitch`) into this wave's Gram tiles ----
+    auto contract = [&](const lds_t* S, int ng, auto rows_c, int pitch) {
+      constexpr int ROWS = decltype(rows_c)::value;
+      // lane-derived addresses from an opaque copy of the lane index: formed afresh per call
+      // instead of being hoisted out of the row-block loops and kept live (or spilled)
+      int lx = lane;
+      asm volatile("" : "+v"(lx));
+      const lds_t* Sl = S + (((lx >> 3) & 1) * NP) * NCC * pitch + (lx & 7) * pitch + KPL * (lx >> 4);
+#pragma unroll
+      for (int s = 0; s < C::NPW; ++s) {
+        const int tp = w + NW * s;
+        if (tp >= npt || !((wkeep >> s) & 1)) continue;
+        int I, J;
+        tp_to_ij(tp, I, J);
+        accv_t acc = gacc[s];
+        for (int g = 0; g < ng; ++g) {
+          const lds_t* SA = Sl + (g * nb8 + I * 8) * pitch;
+          const lds_t* SB = Sl + (g * nb8 + J * 8) * pitch;
+#pragma unroll 1
+          for (int ks = 0; ks < ROWS / KS; ++ks) {
+            op_t ao[NP], bo[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              ao[p] = lds_operand<MODE>(SA + p * NCC * pitch + ks * KS);
+              bo[p] = lds_operand<MODE>(SB + p * NCC * pitch + ks * KS);
+            }
+#pragma unroll
+            for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+              acc = mfma(ao[NP == 1 ? 0 : prod_a(NP, pr)], bo[NP == 1 ? 0 : prod_b(NP, pr)], acc);
+          }
+        }
+        gacc[s] = acc;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+
+    for (int gbase = wi.g0; gbase < wi.g1; gbase += wi.ngc) {
+      const int ng = min(wi.ngc, wi.g1 - gbase);
+      const int ncols = ng * nb8;
+      auto col_index = [&](int c, int& n) -> long {
+        const int g = (int)__umulhi((uint32_t)c, nb8_rcp);
+        n = c - g * nb8;
+        return (long)(gbase + g) * nb + n;
+      };
+
+      // ================= multipole-free rows (block-sparse), as in fused_kernel =================
+      if (a.n_s > 0) {
+        constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, MPC = C::MPC;
+        constexpr int LDRS = C::LDRS;
+        const int nck = a.n_schunk;
+        const int ncb = (ncols + CB - 1) / CB;
+        const int nsteps = nck * ncb;
+        double2* Mp = (double2*)(smem + C::SP_MP + w * CPW * MPC * 16);
+        double2* Cf = (double2*)(smem + C::SP_CF);
+        lds_t* Ss = (lds_t*)(smem + C::SP_ST);
+        double dreg[NCB][CPW];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) dreg[b][j] = 0.0;
+
+        struct RowData { double2 lc; int cs, len, mloc; };
+        auto chunk_info = [&](int ck) -> int4 {
+          const int4 v = s_chunk[ck];
+          return make_int4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
+        };
+        auto load_rows = [&](const int4& ci, RowData& d) {
+          d.len = 0; d.cs = 0; d.mloc = 0;
+          d.lc = make_double2(0.0, 0.0);
+          if (lane < ci.y) {
+            const int4 ri = a.rowinfo[ci.x + lane];
+            d.cs = ri.x; d.len = ri.y; d.mloc = ri.z - ci.w;
+            d.lc = a.cvec[ci.x + lane];
+          }
+        };
+        constexpr int CFN = MAXT * GR;                  // coefficient table entries (16 B)
+        constexpr int CFL = (CFN + NT - 1) / NT;
+        u4_t cfn[CFL];
+        auto load_coef = [&](int ck) {
+          const u4_t* src = (const u4_t*)(a.coefpad + (long)ck * MAXT * GR);
+#pragma unroll
+          for (int i = 0; i < CFL; ++i)
+            if (tid + NT * i < CFN) cfn[i] = src[tid + NT * i];
+        };
+        auto store_coef = [&]() {
+#pragma unroll
+          for (int i = 0; i < CFL; ++i)
+            if (tid + NT * i < CFN) ((u4_t*)Cf)[tid + NT * i] = cfn[i];
+        };
+        struct StepRegs { uint2 xn[CPW]; uint2 pn; };
+        auto fetch = [&](int st, StepRegs& X) {
+          const int4 ci = chunk_info(st / ncb);
+          const int cb0 = (st % ncb) * CB;
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            const int c = cb0 + w + NW * j;
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = c < ncols && n < nb && lane < ci.y;
+            const uint32_t vx = ok ? (uint32_t)((col * pi.nmb + ci.x + lane) * esz) : 0x80000000u;
+            X.xn[j] = buf_load<uint2>(mrs, vx, 0u);
+          }
+          {
+            const int c = cb0 + w + NW * (lane / MPC);
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = c < ncols && n < nb;
+            const uint32_t vm = ok ? (uint32_t)((col * pi.nmb + ci.w + lane % MPC) * esz) : 0x80000000u;
+            X.pn = buf_load<uint2>(mrs, vm, 0u);
+          }
+        };
+        auto to_d2 = [&](uint2 v) -> double2 {
+          return make_double2((double)__uint_as_float(v.x), (double)__uint_as_float(v.y));
+        };
+
+        __syncthreads();
+        for (int e = tid; e < nck; e += NT) s_chunk[e] = a.schunk[e];
+        load_coef(0);
+        store_coef();
+        __syncthreads();
+        int4 ci = chunk_info(0);
+        RowData rd, rd_next;
+        load_rows(ci, rd);
+        rd_next = rd;
+        if (nck > 1) {
+          load_rows(chunk_info(1), rd_next);
+          load_coef(1);
+        }
+        StepRegs SA, SB;
+        fetch(0, SA);
+        if (nsteps > 1) fetch(1, SB);
+
+        auto step = [&](int st, StepRegs& X) {
+          const int cbk = st % ncb, cb0 = cbk * CB;
+          double2 xs[CPW];
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) xs[j] = to_d2(X.xn[j]);
+          Mp[lane] = to_d2(X.pn);
+          if (st + 2 < nsteps) fetch(st + 2, X);
+          __builtin_amdgcn_wave_barrier();
+          double2 y[CPW];
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            const double2 xm = Mp[j * MPC + rd.mloc];
+            y[j].x = rd.lc.x * xm.x - rd.lc.y * xm.y;
+            y[j].y = rd.lc.x * xm.y + rd.lc.y * xm.x;
+          }
+          auto term = [&](const double2 l) {
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+              y[j].x = fma(l.x, xs[j].x, y[j].x);
+              y[j].y = fma(l.x, xs[j].y, y[j].y);
+              y[j].x = fma(l.y, xs[j].y, y[j].x);
+              y[j].y = fma(-l.y, xs[j].x, y[j].y);
+              xs[j] = shift_down1(xs[j]);
+            }
+          };
+          const int Tn = min(ci.z, MAXT);
+          for (int t = 0; t < Tn; ++t) term(Cf[t * GR + lane]);
+          for (int t = MAXT; t < ci.z; ++t) term(t < rd.len ? a.coef[rd.cs + t] : make_double2(0.0, 0.0));
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            const int c = cb0 + w + NW * j;
+            if (c < NCC) {
+              put_real<MODE>(Ss + (0 * NP) * NCC * LDRS + c * LDRS + lane, NCC * LDRS, y[j].x);
+              put_real<MODE>(Ss + (1 * NP) * NCC * LDRS + c * LDRS + lane, NCC * LDRS, y[j].y);
+            }
+            const double d = y[j].x * y[j].x + y[j].y * y[j].y;
+#pragma unroll
+            for (int b = 0; b < NCB; ++b)
+              if (b == cbk) dreg[b][j] += d;
+          }
+          if (cbk == ncb - 1) {
+            __syncthreads();
+            const int ck = st / ncb;
+            if (ck + 1 < nck) {
+              store_coef();
+              ci = chunk_info(ck + 1);
+              rd = rd_next;
+              if (ck + 2 < nck) {
+                load_rows(chunk_info(ck + 2), rd_next);
+                load_coef(ck + 2);
+              }
+            }
+            contract(Ss, ng, std::integral_constant<int, GR>{}, LDRS);
+            __syncthreads();
+          }
+        };
+        for (int st = 0; st < nsteps; st += 2) {
+          step(st, SA);
+          if (st + 1 < nsteps) step(st + 1, SB);
+        }
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) {
+            double d = dreg[b][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+            const int c = b * CB + w + NW * j;
+            if (lane == 0 && c < NCC) Dacc[(w * NCC + c) * 2] += d;
+          }
+      }
+
+      // ================= dense rows: row blocks of BM rows =================
+      for (int r0 = 0; r0 < nd; r0 += BM) {
+        accv_t acc[RT][NCT];
+#pragma unroll
+        for (int ii = 0; ii < RT; ++ii)
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) acc[ii][j] = accv_t{0, 0, 0, 0};
+        const int kc0 = (r0 / KC) * KC;
+        const int kend = (nd + KC - 1) / KC * KC;
+        const int np = (kend - kc0) / KC;                // K panels of this row block (>= 1)
+
+        // direct loads of a raw panel: instruction t of this wavefront moves 1 KB = four columns
+        // of KC complex64 values (16 lanes a column, two values a lane); instructions past the
+        // panel's NI land in the trash KB, columns past the item's read zero
+        uint32_t r_off[NIW];
+        {
+          int lane_d = lane;
+          asm volatile("" : "+v"(lane_d));
+#pragma unroll
+          for (int t = 0; t < NIW; ++t) {
+            const int ix = w + NW * t;
+            const int c = ix * 4 + lane_d / 16;
+            const int k = (lane_d % 16) * 2;
+            int n = 0;
+            const long col = col_index(c, n);
+            const bool ok = ix < NI && c < ncols && n < nb;
+            r_off[t] = ok ? (uint32_t)((col * pi.nmb + a.n_s + k) * esz) : 0x80000000u;
+          }
+        }
+        auto issue_raw = [&](int kc, int buf) {
+#pragma unroll
+          for (int t = 0; t < NIW; ++t) {
+            const int ix = w + NW * t;
+            unsigned char* dst = ix < NI ? Raw + buf * C::RAW_B + ix * 1024 : Trash;
+            lds_load16(mrs, dst, r_off[t], (uint32_t)(kc * esz));
+          }
+        };
+        // raw panel -> pieces: thread u converts column u / (KC/8), k = 8 (u % (KC/8)) .. +7, four
+        // k at a time; rows past N_d are zero
+        auto convert = [&](int kc, int rbuf, int pbuf) {
+          constexpr int KG = KC / 8;
+          if (tid < NCC * KG) {
+            const int c = tid / KG, kg = tid % KG;
+            const float* src = (const float*)(Raw + rbuf * C::RAW_B + (c * KC + kg * 8) * 8);
+            lds_t* dst = Pcs + pbuf * PCS + c * KC + kg * 8;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+              const f4_t v0 = *(const f4_t*)(src + 8 * hf), v1 = *(const f4_t*)(src + 8 * hf + 4);
+              const int k0 = kc + kg * 8 + 4 * hf;
+              const bool o0 = k0 < nd, o1 = k0 + 1 < nd, o2 = k0 + 2 < nd, o3 = k0 + 3 < nd;
+              store_pieces4<MODE>(dst + 4 * hf, APL, o0 ? v0[0] : 0.f, o1 ? v0[2] : 0.f, o2 ? v1[0] : 0.f,
+                                  o3 ? v1[2] : 0.f);
+              store_pieces4<MODE>(dst + NP * APL + 4 * hf, APL, o0 ? v0[1] : 0.f, o1 ? v0[3] : 0.f,
+                                  o2 ? v1[1] : 0.f, o3 ? v1[3] : 0.f);
+            }
+          }
+        };
+        // factor pieces of this wave's two row tiles (w and w + NW of the block) for the panel at kc:
+        // lane (l16, lq) holds row l16, k = 8 lq .. 8 lq + 7 of each piece plane (Re, then Im). The
+        // matrix-core step ks takes k = 8 lq + ks from every lane group (bf16: one step over all 32
+        // k; FP32: eight steps), the same permutation of k for both operands. Rows past N_d or
+        // below the diagonal hold zeros (their products are skipped anyway).
+        using ureg_t = typename std::conditional<MODE == M_F32, f4_t, u4_t>::type;
+        constexpr int UPV = MODE == M_F32 ? 2 : NP;       // 16-byte registers per (row tile, Re/Im)
+        ureg_t ucur[RT][2][UPV];
+        auto load_u = [&](int kc) {
+#pragma unroll
+          for (int ii = 0; ii < RT; ++ii) {
+            const long row0 = (long)(r0 + 16 * (w + NW * ii)) * pi.ldu + kc;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+              for (int v = 0; v < UPV; ++v) {
+                const long e = MODE == M_F32 ? h * plane + row0 + 4 * v : (h * NP + v) * plane + row0;
+                ucur[ii][h][v] = buf_load<ureg_t>(urs, u_lane, (uint32_t)(e * C::ESZ));
+              }
+          }
+        };
+        // A operand of step ks, piece pa, from the registers above
+        auto uop = [&](int ii, int h, int ks, int pa) -> op_t {
+          if constexpr (MODE == M_F32) {
+            return ucur[ii][h][ks >> 2][ks & 3];
+          } else {
+            (void)ks;
+            return ucur[ii][h][pa];
+          }
+        };
+        auto n_active = [&](int kc) {
+          int n = 0;
+#pragma unroll
+          for (int ii = 0; ii < RT; ++ii)
+            if (r0 + 16 * (w + NW * ii) < min(kc + KC, nd)) n = ii + 1;
+          return n;
+        };
+
+        __syncthreads();                                  // LDS of the previous phase is free
+        // prologue: raw panels 0 .. NRAW-1 in flight, then the factor of panel 0
+        issue_raw(kc0, 0);
+        if (np > 1) issue_raw(kc0 + KC, 1);
+        if (NRAW == 3 && np > 2) issue_raw(kc0 + 2 * KC, 2);
+        load_u(kc0);
+        // own part of raw panel 0 landed: the later NIW (panels 1, 2) + NFL (factor) loads may fly
+        if (NRAW == 3 && np > 2) wait_vm<2 * NIW + NFL>();
+        else if (np > 1) wait_vm<NIW + NFL>();
+        else wait_vm<NFL>();
+        __syncthreads();
+        convert(kc0, 0, 0);
+        if (np > 1) {                                     // own part of raw panel 1 landed
+          if (NRAW == 3 && np > 2) wait_vm<NIW + NFL>();
+          else wait_vm<NFL>();
+        }
+        __syncthreads();
+
+        for (int p = 0; p < np; ++p) {
+          const int kc = kc0 + p * KC;
+          // A: raw panel p + NRAW into the buffer panel p came in (converted before the last barrier)
+          const bool issued = p + NRAW < np;
+          if (issued) issue_raw(kc + NRAW * KC, p % NRAW);
+          // B: this panel's factor landed (only the raw loads just issued may still fly)
+          if (issued) wait_vm<NIW>();
+          else wait_vm<0>();
+          // C: [Yr|Yi] += Ur [Ar|Ai] + Ui [-Ai|Ar] over the panel
+          const int na = n_active(kc);
+          // per-panel lane addresses from an opaque lane copy (see contract): the B operand of
+          // step (h, j) is plane part (h = 0) or, for h = 1, -Im (part 0) or Re (part 1), read at
+          // column j 8 + c8 and k = 8 lq + ks (see load_u); every other term is an immediate offset
+          int lx = lane;
+          asm volatile("" : "+v"(lx));
+          const int xpart = (lx >> 3) & 1;
+          const lds_t* Pl = Pcs + (p & 1) * PCS + (lx & 7) * KC + 8 * (lx >> 4);
+          const lds_t* B0 = Pl + xpart * NP * APL;
+          const lds_t* B1 = Pl + (1 - xpart) * NP * APL;
+          const bool negl = xpart == 0;
+#pragma unroll
+          for (int ks = 0; ks < KC / KS; ++ks) {
+            auto bload = [&](int hj, op_t (&b)[NP]) {
+              const int h = hj / NCT, j = hj % NCT;
+              const lds_t* Bh = h == 0 ? B0 : B1;
+#pragma unroll
+              for (int p2 = 0; p2 < NP; ++p2) {
+                b[p2] = lds_operand<MODE>(Bh + p2 * APL + j * 8 * KC + ks);
+                if (h == 1 && negl) b[p2] = negate(b[p2]);
+              }
+            };
+            op_t bA[NP], bB[NP];
+            bload(0, bA);
+#pragma unroll
+            for (int hj = 0; hj < 2 * NCT; ++hj) {
+              const int h = hj / NCT, j = hj % NCT;
+              op_t (&bc)[NP] = (hj & 1) ? bB : bA;
+              op_t (&bn)[NP] = (hj & 1) ? bA : bB;
+              if (hj + 1 < 2 * NCT) bload(hj + 1, bn);
+#pragma unroll
+              for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+#pragma unroll
+                for (int ii = 0; ii < RT; ++ii)
+                  if (ii < na)
+                    acc[ii][j] = mfma(uop(ii, h, ks, NP == 1 ? 0 : prod_a(NP, pr)),
+                                      bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
+              // keep the scheduler from hoisting later operand loads (register pressure)
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+          if (p + 1 < np) {
+            // E: next panel's pieces from its raw panel (landed and visible since the last
+            // barrier) into the other piece buffer; D: next panel's factor (after the
+            // conversion, so that the two never hold registers at once)
+            convert(kc + KC, (p + 1) % NRAW, (p + 1) & 1);
+            load_u(kc + KC);
+            // F: own part of raw panel p + 2 landed, for the conversion after the next barrier.
+            // Loads issued after it: NRAW = 3 -> factor p + 1 (issued one panel earlier... no:
+            // the factor of this panel, issued at the end of the last one), raw p + 3 (A above,
+            // if issued) and factor p + 1 (D above); NRAW = 2 -> factor p + 1.
+            if (p + 2 < np) {
+              if constexpr (NRAW == 3) {
+                if (issued) wait_vm<NIW + 2 * NFL>();
+                else wait_vm<2 * NFL>();
+              } else {
+                wait_vm<NFL>();
+              }
+            }
+          }
+          __syncthreads();
+        }
+
+        // ---- the row block's rows through LDS into the Gram tiles, GS rows at a time ----
+        constexpr int RPS = GS / 16;                      // row tiles per stage round
+#pragma unroll
+        for (int rr = 0; rr < BM / GS; ++rr) {
+          if (r0 + rr * GS >= nd) break;                  // uniform
+          __syncthreads();                                // the stage is free
+          // lane addresses from an opaque lane copy (see contract): column c8 of the part's
+          // plane, rows 4 lq .. 4 lq + 3 of the tile (the accumulator rows of the lane)
+          int lx = lane;
+          asm volatile("" : "+v"(lx));
+          const int xlq = lx >> 4, xpart = (lx >> 3) & 1;
+          lds_t* Yl = Ys + (xpart * NP) * NCC * LDR + (lx & 7) * LDR + 4 * xlq;
+          double* Dl = Dacc + (w * NCC + (lx & 7)) * 2 + xpart;
+#pragma unroll
+          for (int ii = 0; ii < RT; ++ii) {
+            const int tile = w + NW * ii;                 // this wave's row tile in the block
+            if (tile / RPS != rr) continue;
+            const int trow = (tile % RPS) * 16;
+            const int rlim = nd - (r0 + rr * GS + trow + 4 * xlq);   // rows of the lane below N_d
+#pragma unroll
+            for (int j = 0; j < NCT; ++j) {
+              double d = 0.0;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const float y = e < rlim ? (float)acc[ii][j][e] : 0.f;
+                put_realf<MODE>(Yl + j * 8 * LDR + trow + e, NCC * LDR, y);
+                d += (double)y * (double)y;
+              }
+              d += __shfl_xor(d, 16);
+              d += __shfl_xor(d, 32);
+              if (xlq == 0) Dl[j * 16] += d;
+            }
+          }
+          __syncthreads();
+          contract(Ys, ng, std::integral_constant<int, GS>{}, LDR);
+        }
+      }
+      // ---- this n'' chunk's Gram tiles into the item's partial slot (stored by the first
+      // chunk, added by the others): each chunk's sums over the mixed basis run in their own
+      // binary32 accumulators, as one (pair, n'') slot would hold them, and the chunks of an
+      // item meet in one binary32 addition each instead of one sequential sum over every row
+      // of every n''
+#pragma unroll
+      for (int s = 0; s < C::NPW; ++s) {
+        const int tp = w + NW * s;
+        if (tp < npt) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc_t* d = gp + (tp * 4 + i) * 64 + lane;
+            *d = gbase == wi.g0 ? gacc[s][i] : *d + gacc[s][i];
+          }
+        }
+        gacc[s] = accv_t{0, 0, 0, 0};
+      }
+    }  // n'' chunks
+
+    __syncthreads();
+    for (int n = tid; n < nb8; n += NT) {
+      double s = 0.0;
+      for (int c = n; c < NCC; c += nb8)
+        for (int ww = 0; ww < NW; ++ww) s += Dacc[(ww * NCC + c) * 2] + Dacc[(ww * NCC + c) * 2 + 1];
+      a.dpart[(long)wi.slot * a.dstride + n] = s;
+    }
+    if (tid0 == 0) s_item = claim;
+    __syncthreads();
+    idx = -1;
+    if (home) {
+      const int j = qh0 + n_static(qi) + __builtin_amdgcn_readfirstlane(s_item);
+      if (j < qh1) idx = j;
+      else home = false;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace exc

@@ -1,0 +1,112 @@
+"""GPU parity of the wide kernel (large pairs, complex64 M): every instance forced in
+turn on the small and ragged workloads (one to five band tiles, channels without
+multipole-free functions) and on full per-pair shapes of the ZnO-like and SrTiO3-like
+workloads (their Gamma, smallest and largest mixed basis, 60 / 100 bands, N_MB up to
+1399 / 2600), against the float64 oracle on the same complex64 values widened.
+
+Bars as in test_parity: normwise error within 4x the input-rounding emulator's
+prediction (plus 1e-12); on the full shapes also the normalised eigenvalue error
+<= 1e-6 Ha; Hermitian mirror and real diagonal exact. Work items per n'' chunk, and a
+complex128 call on a context fixed to a wide instance (which switches to an instance
+that reads complex128), are covered too.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chol, precision as pr, vx
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WIDE = {"fp32": [180, 186, 183], "bf16x3": [181, 187, 184], "bf16x6": [182, 188]}
+CAP = {180: 13, 181: 13, 182: 13, 183: 16, 184: 16, 186: 13, 187: 13, 188: 13}
+
+
+@functools.lru_cache(maxsize=None)
+def _work(name):
+    cfg = synth.make_config(name)
+    if name in ("c3", "c4"):
+        nmb = np.array([cfg.n_mb(q) for q in range(cfg.n_q)])
+        cfg = synth.q_slice(cfg, [0, int(nmb.argmin()), int(nmb.argmax())], n_k=1)
+    E, D, C = synth.coulomb_blocks(cfg)
+    v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
+    m64 = [[synth.m_block(cfg, k, q, np.complex64).astype(np.complex128) for q in range(cfg.n_q)]
+           for k in range(cfg.n_k)]
+    refs = [vx.vx_k(m64[k], v, cfg.weights_q()) for k in range(cfg.n_k)]
+    rho = max(float(np.abs(np.linalg.eigvalsh(vx.hermitian_part(r))).max()) for r in refs)
+    return cfg, E, D, C, v, m64, refs, rho
+
+
+@functools.lru_cache(maxsize=None)
+def _emulated(name, mode):
+    cfg, E, D, C, v, m64, refs, rho = _work(name)
+    L = [chol.cholesky(a) for a in v]
+    return [pr.vx_k_emulated(m64[k], L, cfg.weights_q(), mode) for k in range(cfg.n_k)]
+
+
+def _run(name, precision, dt=np.complex64):
+    import paper_1003_0524_amd as lib
+    cfg, E, D, C, v, m64, refs, rho = _work(name)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision=precision, form="herk", batched=True)
+    Ms = [torch.from_numpy(synth.m_all(cfg, k, np.complex64).astype(dt)).cuda() for k in range(cfg.n_k)]
+    Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    cid = int(ex.query(3))
+    ex.close()
+    return Vs, cid
+
+
+def _check(name, precision, Vs, eig=False):
+    cfg, E, D, C, v, m64, refs, rho = _work(name)
+    emu = _emulated(name, precision)
+    for k in range(cfg.n_k):
+        err = pr.normwise_error(Vs[k], refs[k])
+        pred = pr.normwise_error(emu[k], refs[k])
+        print(f"[wide] {name} {precision} k={k}: error {err:.3e}, emulated {pred:.3e}", flush=True)
+        assert np.array_equal(Vs[k], Vs[k].conj().T) and np.all(np.diag(Vs[k]).imag == 0.0)
+        assert err <= 4.0 * pred + 1e-12, (name, precision, k, err, pred)
+        if eig:
+            assert pr.normalised_eig_error(Vs[k], refs[k], rho) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("name", ["small", "ragged", "c3", "c4"])
+def test_wide_instance_matches_oracle(name, precision, monkeypatch):
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_FUSED_SPLIT", raising=False)
+    cfg = _work(name)[0]
+    nbt = max((nb + 7) // 8 for nb in cfg.n_bands)
+    for cid in WIDE[precision]:
+        if CAP[cid] < nbt or (name in ("small", "ragged") and CAP[cid] == 16):
+            continue
+        monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
+        print(f"[wide] {name} {precision} instance {cid}", flush=True)
+        sys.stdout.flush()
+        Vs, got = _run(name, precision)
+        assert got == cid
+        _check(name, precision, Vs, eig=name in ("c3", "c4"))
+
+
+@pytest.mark.parametrize("precision,cid", [("bf16x3", 181), ("fp32", 186)])
+def test_wide_split_items(precision, cid, monkeypatch):
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
+    monkeypatch.setenv("EXC_FUSED_SPLIT", "1")
+    print(f"[wide] ragged {precision} {cid} items per n'' chunk", flush=True)
+    Vs, got = _run("ragged", precision)
+    assert got == cid
+    _check("ragged", precision, Vs)
+
+
+def test_complex128_call_leaves_the_wide_instance(monkeypatch):
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_FUSED_SPLIT", raising=False)
+    monkeypatch.setenv("EXC_FUSED_CFG", "181")
+    print("[wide] small bf16x3 fixed to 181, complex128 M", flush=True)
+    Vs, got = _run("small", "bf16x3", dt=np.complex128)
+    assert got != 181
+    _check("small", "bf16x3", Vs)
