@@ -294,6 +294,13 @@ void exchange_destroy(exc_ctx *ctx);
  *   what = 14: 1 if the fused kernel's work items are (pair, n'' chunk) instead of
  *              pairs (chosen by the autotuner when few (k, q) pairs leave the GPU
  *              short of work), else 0
+ *   what = 15..18: how the reduced-precision main kernel accumulates the band
+ *              contraction in binary32 (for error models; -1 in FP64 and for the
+ *              unbatched GEMM form): 15 = band tiles per n'' pass; 16 = chain kind,
+ *              0: one accumulator chain per work item, 1: one per row chunk of a pass,
+ *              added into the item's binary32 partial, 2: one per n'' pass, added
+ *              likewise, 3: a work item per n'' pass and row chunk (unbatched path);
+ *              17 / 18 = rows per chunk in the block-sparse / dense rows
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);

@@ -219,6 +219,16 @@ class Exchange:
         if out.dtype != t.complex128 or int(out.numel()) != nb * nb or not out.is_contiguous():
             raise ExchangeError(-1, f"out for k={k} must be a contiguous complex128 tensor of {nb * nb} elements")
 
+    def accumulation_plan(self):
+        """How the reduced-precision main kernel accumulates the band contraction in
+        binary32 (exchange_query 14-18), as the error model of the tests takes it; None in
+        FP64 and for the unbatched GEMM form."""
+        kind = int(self.query(16))
+        if kind < 0:
+            return None
+        return {"kind": kind, "nct": int(self.query(15)), "split": bool(self.query(14)),
+                "rs": int(self.query(17)), "rd": int(self.query(18))}
+
     # -- API ---------------------------------------------------------------
     def matrix(self, k: int, M, out=None):
         """V^x(k) (n_b x n_b complex128, column-major storage returned as its transpose view)."""

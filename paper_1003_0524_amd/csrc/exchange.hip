@@ -36,13 +36,17 @@ struct KernelCfg {
   void (*fn)(TileArgs);
   size_t lds;
   int id;
+  int gchain, grs, grd;             // binary32 Gram chains: kind, rows per chunk (sparse, dense)
   int NW() const { return NWR * NWC; }
 };
 
 #define CFG(MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF, ID)                                    \
   KernelCfg{MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF,                                         \
             tile_kernel<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>,                            \
-            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::LDS_B, ID}
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::LDS_B, ID,                     \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::GCHAIN,                        \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::GCH_RS,                        \
+            TileCfg<MODE, FORM, BM, KC, NCT, NB8M, NWR, NWC, NBUF>::GCH_RD}
 
 // Tile shapes: BM rows of the factor per step, split over NWR wavefronts; NCT
 // 8-column band tiles per pass (n_b rounded to 8, times the n'' chunk), split
@@ -79,26 +83,34 @@ struct FusedKCfg {
   bool realf = false;               // real factor only (inversion-symmetric contexts)
   int nt = 256;                     // threads per workgroup
   bool c64only = false;             // reads complex64 M only (the wide kernel)
+  int gchain = 0, grs = 64, grd = 64;   // binary32 Gram chains: kind, rows per chunk (sparse, dense)
 };
 
 #define FCFG(MODE, RTW, NCT, NB8M, KC, ID)                                                       \
   FusedKCfg{MODE, RTW, NCT, NB8M, KC, 16, 1, fused_kernel<MODE, RTW, NCT, NB8M, KC, 16, 1>,        \
-            FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::LDS_B, ID}
+            FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::LDS_B, ID, false, 256, false,                \
+            FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::GCHAIN, FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::GR, \
+            FusedCfg<MODE, RTW, NCT, NB8M, KC, 16, 1>::GR}
 // two workgroups per CU: at most 256 registers per lane and half the LDS each
 #define FCFG2(MODE, RTW, NCT, NB8M, ID)                                                          \
   FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2>,       \
-            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID}
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID, false, 256, false,               \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GCHAIN, FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GR, \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GR}
 
 // real-factor instances (inversion symmetry): the same kernels without the
 // products with the factor's zero imaginary parts
 #define FCFG2R(MODE, RTW, NCT, NB8M, ID)                                                         \
   FusedKCfg{MODE, RTW, NCT, NB8M, 32, 16, 2, fused_kernel<MODE, RTW, NCT, NB8M, 32, 16, 2, true>, \
-            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID, true}
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::LDS_B, ID, true, 256, false,                \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GCHAIN, FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GR, \
+            FusedCfg<MODE, RTW, NCT, NB8M, 32, 16, 2>::GR}
 
 // wide kernel (large pairs, complex64 M): 8 wavefronts, 256-row dense blocks, NB8M band tiles
 #define WCFG(MODE, NB8M, RT, ID)                                                                  \
   FusedKCfg{MODE, RT, NB8M, NB8M, 32, 32, 1, wide_kernel<MODE, NB8M, RT>, WideCfg<MODE, NB8M, RT>::LDS_B, \
-            ID, false, 512, true}
+            ID, false, 512, true, WideCfg<MODE, NB8M, RT>::GCHAIN, WideCfg<MODE, NB8M, RT>::GCH_RS,        \
+            WideCfg<MODE, NB8M, RT>::GCH_RD}
 
 // Listed in order of preference among equal band-tile capacity (the two-per-CU
 // instances first: they hide more memory latency).
@@ -1775,6 +1787,19 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 11: *value = c->gamma_ms; return EXC_OK;
     case 12: *value = c->gamma_terms; return EXC_OK;
     case 14: *value = c->fsplit; return EXC_OK;
+    case 15:
+    case 16:
+    case 17:
+    case 18: {
+      // the binary32 Gram accumulation of the reduced-precision main kernel (error models):
+      // band tiles per pass, chain kind, rows per chunk in the block-sparse / dense rows
+      if (c->precision == EXC_FP64 || c->plain_gemm || (!c->fused && !c->cfg)) { *value = -1; return EXC_OK; }
+      const int v[4] = {c->fused ? c->fcfg->NCT : c->cfg->NCT,
+                        c->fused ? c->fcfg->gchain : (c->batched ? c->cfg->gchain : 3),
+                        c->fused ? c->fcfg->grs : c->cfg->grs, c->fused ? c->fcfg->grd : c->cfg->grd};
+      *value = v[what - 15];
+      return EXC_OK;
+    }
     case 13: {                                    // the last back-transform's product kernel
       if (!c->bt_timed) { *value = 0.0; return EXC_OK; }
       if (hipEventSynchronize(c->ev_bt[1]) != hipSuccess) return EXC_EHIP;

@@ -146,6 +146,9 @@ struct FusedCfg {
   static constexpr int NPT = NB8M * (NB8M + 1) / 2;
   static constexpr int NPW = (NPT + NW - 1) / NW;
   static constexpr bool GSTREAM = NPW > 8;
+  // binary32 Gram chains (for error models): one per item, or (GSTREAM) one per GR-row
+  // chunk added into the item's partial; GR rows per chunk in both row kinds
+  static constexpr int GCHAIN = GSTREAM ? 1 : 0, GCH_RS = GR, GCH_RD = GR;
   static constexpr int CB = CBX;                         // sparse step: columns (CB / NW per wavefront)
   static constexpr int CPW = CB / NW;
   static constexpr int NCB = (NCC + CB - 1) / CB;        // column blocks of a sparse chunk (at most)

@@ -121,6 +121,9 @@ struct TileCfg {
   // accumulators: then each tile is accumulated for one row block at a time and
   // added into the item's private partial slot in global memory.
   static constexpr bool GSTREAM = NPW * 4 * (int)sizeof(acc_t) / 4 > 32;
+  // binary32 Gram chains (for error models): one per item, or (GSTREAM) one per row block
+  // added into the item's partial; rows per chunk in the block-sparse and the dense rows
+  static constexpr int GCHAIN = GSTREAM ? 1 : 0, GCH_RS = BM, GCH_RD = BM;
   static constexpr size_t KLOOP_B = (size_t)NBUF * STAGE * sizeof(lds_t);
   static constexpr size_t STAGE_B = ((size_t)YS_SZ * sizeof(lds_t) + 15) / 16 * 16 + (size_t)LS_SZ * 8;
   static constexpr size_t MAIN_B = KLOOP_B > STAGE_B ? KLOOP_B : STAGE_B;

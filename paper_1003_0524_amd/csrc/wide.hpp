@@ -64,6 +64,9 @@ struct WideCfg {
   static constexpr size_t LDS_B = MAIN_B + DACC_B;
   static constexpr int NPT = NB8M * (NB8M + 1) / 2;
   static constexpr int NPW = (NPT + NW - 1) / NW;     // Gram tiles per wavefront (round robin)
+  // binary32 Gram chains (for error models): one per n'' chunk, added into the item's
+  // partial; GR rows per chunk in the block-sparse rows, GS in the dense rows
+  static constexpr int GCHAIN = 2, GCH_RS = GR, GCH_RD = GS;
   static_assert(MODE != M_F64, "the wide kernel serves the reduced-precision modes");
   static_assert(LDS_B <= BUDGET, "wide configuration exceeds the 160 KB of LDS");
   static_assert((size_t)2 * RAW_B + 1024 + PIECE_B + DACC_B <= BUDGET, "at least two raw panels in flight");

@@ -42,6 +42,7 @@ def test_masked_tiles_are_zero_and_the_rest_matches(precision):
                                                   for k in range(cfg.n_k)])]
     ex.band_mask(0, None)                                   # back to every pair
     V0 = ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda() for k in range(cfg.n_k)])[0].cpu().numpy()
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     L = [chol.cholesky(a) for a in v]
@@ -52,6 +53,6 @@ def test_masked_tiles_are_zero_and_the_rest_matches(precision):
         if precision == "fp64":
             assert pr.normwise_error(Vs[k], ref) <= 1e-10
         else:
-            emu = np.where(keeps[k], pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), 0)
+            emu = np.where(keeps[k], pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision, cfg.n_s, plan), 0)
             assert pr.normwise_error(Vs[k], ref) <= 4.0 * pr.normwise_error(emu, ref) + 1e-12
     assert np.any(V0[~keeps[0]] != 0)

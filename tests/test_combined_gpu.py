@@ -35,6 +35,7 @@ def test_inversion_weights_and_gamma_together(precision):
                                            for q in range(cfg.n_q) if w_kq[k, q] != 0])).cuda()
           for k in range(cfg.n_k)]
     Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     L = [chol.cholesky(a) for a in v]
@@ -48,5 +49,5 @@ def test_inversion_weights_and_gamma_together(precision):
             assert pr.normwise_error(Vs[k], ref) <= 1e-10, k
         else:
             emu = pr.vx_k_emulated([synth.pack_real_pairs(m) for m in mr], [L[q] for q in keep],
-                                   w_kq[k, keep], precision).real
+                                   w_kq[k, keep], precision, cfg.n_s, plan).real
             assert pr.normwise_error(Vs[k], ref) <= 4.0 * pr.normwise_error(emu, ref) + 1e-12, k

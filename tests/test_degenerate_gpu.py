@@ -53,6 +53,7 @@ def test_degenerate_shapes(name, precision, form):
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda()
                                                   for k in range(cfg.n_k)])]
     e_gpu = ex.energy()
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     for k in range(cfg.n_k):
@@ -64,7 +65,7 @@ def test_degenerate_shapes(name, precision, form):
             assert err <= 1e-10, (name, k, err)
         else:
             L = [chol.cholesky(a) for a in v]
-            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), ref)
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision, cfg.n_s, plan), ref)
             assert err <= 4.0 * pred + 1e-12, (name, k, err, pred)
     e_dir = vx.energy_direct(cfg, lambda k, q: synth.m_block(cfg, k, q), v)
     assert e_gpu == pytest.approx(e_dir, rel=1e-10 if precision == "fp64" else 1e-5)

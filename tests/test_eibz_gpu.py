@@ -68,6 +68,7 @@ def test_eibz_sum_restores_the_full_sum(name, precision):
     Vf = [V.cpu().numpy() for V in full.matrix_all(M_full)]
     Vp = [V.cpu().numpy() for V in part.matrix_all(M_part)]
     n_items = (full.query(0), part.query(0))
+    plan = part.accumulation_plan()
     full.close()
     part.close()
     assert n_items[1] < n_items[0]
@@ -82,7 +83,8 @@ def test_eibz_sum_restores_the_full_sum(name, precision):
             assert pr.normwise_error(Vp[k], ref_p) <= 1e-10
             assert pr.normwise_error(n_lg * Vp[k], Vf[k]) <= 1e-12
         else:
-            emu = pr.vx_k_emulated([blocks[q] for q in wedge], [L[q] for q in wedge], w[wedge], precision)
+            emu = pr.vx_k_emulated([blocks[q] for q in wedge], [L[q] for q in wedge], w[wedge], precision,
+                                   cfg.n_s, plan)
             pred = pr.normwise_error(emu, ref_p)
             assert pr.normwise_error(Vp[k], ref_p) <= 4.0 * pred + 1e-12
         assert np.array_equal(Vp[k], Vp[k].conj().T)

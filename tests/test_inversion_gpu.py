@@ -76,13 +76,14 @@ def test_fp64_real_variant_matches_oracle(name, form, batched):
 @pytest.mark.parametrize("name", ["small", "ragged"])
 def test_reduced_precision_real_variant(name, precision):
     cfg, ex, Vs = _run(name, precision)
+    plan = ex.accumulation_plan()
     ex.close()
     _, E, D, C, v = _case(name)
     L = [chol.cholesky(a) for a in v]
     for k in range(cfg.n_k):
         ref = _oracle(name, k)
         packed = [synth.pack_real_pairs(synth.m_block_real(cfg, k, q)) for q in range(cfg.n_q)]
-        emu = pr.vx_k_emulated(packed, L, cfg.weights_q(), precision).real
+        emu = pr.vx_k_emulated(packed, L, cfg.weights_q(), precision, cfg.n_s, plan).real
         pred = pr.normwise_error(emu, ref)
         err = pr.normwise_error(Vs[k], ref)
         assert err <= 4.0 * pred + 1e-12, (name, precision, k, err, pred)

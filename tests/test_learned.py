@@ -237,7 +237,9 @@ def test_outer_loop_gain_over_stale():
         # on the block the network predicts it beats the stale V; on the whole spectrum
         # (the other eigenvalues keep the anchor's values) it is no worse
         assert r.err_pred_block < r.err_stale_block, r
-        assert r.err_pred <= r.err_stale * (1 + 1e-6) + 1e-15, r
+        # the correction acts inside span B (eigenvectors of the anchor), so the eigenvalues
+        # outside it are the anchor's: the whole-spectrum errors differ by eigensolver rounding
+        assert r.err_pred <= r.err_stale + 1e-12, r
         assert r.err_pred >= r.err_pred_block
     # the network removes most of the stale error on its block, and the whole spectrum of the
     # V it hands on is within tau = 1e-4 (acceptance is judged on every eigenvalue)
@@ -282,6 +284,8 @@ def test_outer_loop_at_zno_like_shapes():
     assert [r.t for r in judged] == [15, 20, 25, 30]
     for r in judged:
         assert r.err_pred_block < r.err_stale_block, r
-        assert r.err_pred <= r.err_stale * (1 + 1e-6) + 1e-15, r
+        # the correction acts inside span B (eigenvectors of the anchor), so the eigenvalues
+        # outside it are the anchor's: the whole-spectrum errors differ by eigensolver rounding
+        assert r.err_pred <= r.err_stale + 1e-12, r
     assert np.mean([r.err_pred_block / r.err_stale_block for r in judged]) < 0.5
     assert all(r.accepted for r in judged)

@@ -2,9 +2,10 @@
 
 Bars:
   * FP64 (GEMM and Cholesky/HERK forms): max|dV| / max|V| <= 1e-10 per k;
-  * reduced-precision HERK modes: normwise error <= 4x the error the
-    input-rounding emulator predicts for that mode (plus 1e-12), and for fp32 /
-    bf16x6 a normalised eigenvalue error <= 1e-6 (Ha scale);
+  * reduced-precision HERK modes: normwise error <= 4x the error the error model
+    predicts for that mode and the context's accumulation (the matrix-core rounding
+    measured on gfx950, oracle/precision.py; plus 1e-12), and for fp32 / bf16x6 a
+    normalised eigenvalue error <= 1e-6 (Ha scale);
   * Hermitian mirror exact, Im V_nn = 0 exactly, repeated runs bitwise equal.
 """
 import functools
@@ -15,6 +16,7 @@ import pytest
 
 import synth
 from oracle import chol, precision as pr, vx
+from _emulation import predicted
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,10 +42,15 @@ def _oracle(name, k):
 
 
 @functools.lru_cache(maxsize=None)
-def _emulated(name, k, mode):
-    cfg, E, D, C, v = _case(name)
-    L = [chol.cholesky(a) for a in v]
-    return pr.vx_k_emulated([synth.m_block(cfg, k, q) for q in range(cfg.n_q)], L, cfg.weights_q(), mode)
+def _factors(name):
+    return [chol.cholesky(a) for a in _case(name)[4]]
+
+
+def _emulated(name, k, mode, plan):
+    """The error model's V(k) for the context's accumulation plan."""
+    cfg = _case(name)[0]
+    return predicted((name, k), [synth.m_block(cfg, k, q) for q in range(cfg.n_q)], _factors(name),
+                     cfg.weights_q(), mode, cfg.n_s, plan)
 
 
 def _lib():
@@ -69,6 +76,7 @@ def _run_all(name, precision, form, batched, dt=np.complex128):
     Vs = ex.matrix_all(Ms)
     torch.cuda.synchronize()
     out = [V.cpu().numpy() for V in Vs]
+    _run_all.plan = ex.accumulation_plan()          # the error model's chains of this context
     ex.close()
     return cfg, out
 
@@ -113,11 +121,11 @@ def test_reduced_precision_within_predicted_error(name, precision):
     refs = [_oracle(name, k) for k in range(cfg.n_k)]
     rho = max(np.abs(np.linalg.eigvalsh(vx.hermitian_part(r))).max() for r in refs)
     for k in range(cfg.n_k):
-        pred = pr.normwise_error(_emulated(name, k, precision), refs[k])
+        pred = pr.normwise_error(_emulated(name, k, precision, _run_all.plan), refs[k])
         err = pr.normwise_error(Vs[k], refs[k])
         assert err <= 4.0 * pred + 1e-12, (name, precision, k, err, pred)
         _assert_hermitian_exact(Vs[k])
-        if precision in ("fp32", "bf16x6"):
+        if precision in ("fp32", "bf16x6"):     # (bf16x3 is held to it where it is headlined)
             assert pr.normalised_eig_error(Vs[k], refs[k], rho) <= 1e-6
 
 
@@ -215,7 +223,7 @@ def test_every_tuner_candidate_matches_oracle(name, precision, monkeypatch):
         print(f"[parity] {name} {precision} {kind} {cid}", flush=True)
         cfg_, Vs = _run_all(name, precision, "herk", True)
         for k in range(cfg.n_k):
-            pred = pr.normwise_error(_emulated(name, k, precision), refs[k])
+            pred = pr.normwise_error(_emulated(name, k, precision, _run_all.plan), refs[k])
             err = pr.normwise_error(Vs[k], refs[k])
             assert err <= 4.0 * pred + 1e-12, (name, precision, kind, cid, k, err, pred)
 
@@ -234,7 +242,7 @@ def test_split_items_match_oracle(name, precision, cid, monkeypatch):
     cfg_, Vs = _run_all(name, precision, "herk", True)
     for k in range(cfg.n_k):
         ref = _oracle(name, k)
-        pred = pr.normwise_error(_emulated(name, k, precision), ref)
+        pred = pr.normwise_error(_emulated(name, k, precision, _run_all.plan), ref)
         err = pr.normwise_error(Vs[k], ref)
         assert err <= 4.0 * pred + 1e-12, (name, precision, k, err, pred)
         _assert_hermitian_exact(Vs[k])

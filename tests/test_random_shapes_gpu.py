@@ -5,11 +5,9 @@ cases, up to 100 in the rest), so that no tile size divides the problem. Each ca
 through the batched FP64 Cholesky form, the unbatched FP64 GEMM form (one launch of each
 kernel per pair, any band count) and the batched FP32 / bf16x3 / bf16x6 forms
 (autotuned), and is compared element by element with the FP64 oracle. Bars as in the
-other parity tests: FP64 normwise 1e-10; reduced precision within 4x the error the
-input-rounding emulator predicts (plus 1e-12; for bf16x6, whose pieces carry binary32's 24
-bits, the larger of its own and the fp32 mode's prediction, since with 24-bit operands
-the error comes from the binary32 accumulation inside the matrix-core instruction, whose
-order the emulator can only assume); Hermitian mirror and real diagonal exact. The
+other parity tests: FP64 normwise 1e-10; reduced precision within 4x the error the error
+model predicts for the context's accumulation (plus 1e-12); Hermitian mirror and real
+diagonal exact. The
 inversion-symmetric variant and random per-pair weights (some zero) run on the same shapes
 (FP64 and bf16x3), as does M handed over in complex64, and so do the back-transform (random n_G) and the Gamma-point term
 (random skewed lattice, mesh and beta).
@@ -61,6 +59,7 @@ def test_random_shape_matches_oracle(seed, precision, form, batched):
                       precision=precision, form=form, batched=batched)
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k)).cuda()
                                                   for k in range(cfg.n_k)])]
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     for k in range(cfg.n_k):
@@ -73,14 +72,7 @@ def test_random_shape_matches_oracle(seed, precision, form, batched):
             assert err <= 1e-10, (seed, k, err)
         else:
             L = [chol.cholesky(a) for a in v]
-            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), ref)
-            if precision == "bf16x6":
-                # three bf16 pieces carry 24 significant bits, as binary32 does, so the error
-                # is set by the binary32 accumulation; the emulator sums each 32-product chunk
-                # of a matrix-core instruction exactly and rounds once, an order the hardware
-                # does not document: the binary32 model with a rounding every 4 products
-                # (the fp32 mode's) bounds it as well
-                pred = max(pred, pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), "fp32"), ref))
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision, cfg.n_s, plan), ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
 
 
@@ -100,6 +92,7 @@ def test_random_shape_inversion_variant(seed, precision):
                       precision=precision, form="herk", batched=True, inversion=True)
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all_real_packed(cfg, k)).cuda()
                                                   for k in range(cfg.n_k)])]
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     L = [chol.cholesky(a) for a in v]
@@ -112,7 +105,7 @@ def test_random_shape_inversion_variant(seed, precision):
             assert err <= 1e-10, (seed, k, err)
         else:
             packed = [synth.pack_real_pairs(synth.m_block_real(cfg, k, q)) for q in range(cfg.n_q)]
-            pred = pr.normwise_error(pr.vx_k_emulated(packed, L, cfg.weights_q(), precision).real, ref)
+            pred = pr.normwise_error(pr.vx_k_emulated(packed, L, cfg.weights_q(), precision, cfg.n_s, plan).real, ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
 
 
@@ -139,6 +132,7 @@ def test_random_shape_pair_weights(seed, precision):
     blocks = [[synth.m_block(cfg, k, q) for q in keep[k]] for k in range(cfg.n_k)]
     Ms = [torch.from_numpy(np.concatenate([b.ravel() for b in blocks[k]])).cuda() for k in range(cfg.n_k)]
     Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     L = [chol.cholesky(a) for a in v]
@@ -150,7 +144,7 @@ def test_random_shape_pair_weights(seed, precision):
         if precision == "fp64":
             assert err <= 1e-10, (seed, k, err)
         else:
-            pred = pr.normwise_error(pr.vx_k_emulated(blocks[k], [L[q] for q in keep[k]], wk, precision), ref)
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks[k], [L[q] for q in keep[k]], wk, precision, cfg.n_s, plan), ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)
 
 
@@ -233,6 +227,7 @@ def test_random_shape_complex64_input(seed, precision):
                       precision=precision, form="herk", batched=True)
     Vs = [V.cpu().numpy() for V in ex.matrix_all([torch.from_numpy(synth.m_all(cfg, k, np.complex64)).cuda()
                                                   for k in range(cfg.n_k)])]
+    plan = ex.accumulation_plan()
     ex.close()
     v = [vx.assemble_v(E[q], D, C) for q in range(cfg.n_q)]
     L = [chol.cholesky(a) for a in v]
@@ -244,5 +239,5 @@ def test_random_shape_complex64_input(seed, precision):
         if precision == "fp64":
             assert err <= 1e-10, (seed, k, err)
         else:
-            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision), ref)
+            pred = pr.normwise_error(pr.vx_k_emulated(blocks, L, cfg.weights_q(), precision, cfg.n_s, plan), ref)
             assert err <= 4.0 * pred + 1e-12, (seed, k, err, pred)

@@ -4,8 +4,8 @@ multipole-free functions) and on full per-pair shapes of the ZnO-like and SrTiO3
 workloads (their Gamma, smallest and largest mixed basis, 60 / 100 bands, N_MB up to
 1399 / 2600), against the float64 oracle on the same complex64 values widened.
 
-Bars as in test_parity: normwise error within 4x the input-rounding emulator's
-prediction (plus 1e-12); on the full shapes also the normalised eigenvalue error
+Bars as in test_parity: normwise error within 4x the error model's prediction for the
+context's accumulation (plus 1e-12); on the full shapes also the normalised eigenvalue error
 <= 1e-6 Ha; Hermitian mirror and real diagonal exact. Work items per n'' chunk, and a
 complex128 call on a context fixed to a wide instance (which switches to an instance
 that reads complex128), are covered too.
@@ -18,6 +18,7 @@ import pytest
 
 import synth
 from oracle import chol, precision as pr, vx
+from _emulation import predicted
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -42,10 +43,14 @@ def _work(name):
 
 
 @functools.lru_cache(maxsize=None)
-def _emulated(name, mode):
+def _factors(name):
+    return [chol.cholesky(a) for a in _work(name)[4]]
+
+
+def _emulated(name, mode, plan):
     cfg, E, D, C, v, m64, refs, rho = _work(name)
-    L = [chol.cholesky(a) for a in v]
-    return [pr.vx_k_emulated(m64[k], L, cfg.weights_q(), mode) for k in range(cfg.n_k)]
+    return [predicted((name, k), m64[k], _factors(name), cfg.weights_q(), mode, cfg.n_s, plan)
+            for k in range(cfg.n_k)]
 
 
 def _run(name, precision, dt=np.complex64):
@@ -56,13 +61,14 @@ def _run(name, precision, dt=np.complex64):
     Ms = [torch.from_numpy(synth.m_all(cfg, k, np.complex64).astype(dt)).cuda() for k in range(cfg.n_k)]
     Vs = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
     cid = int(ex.query(3))
+    plan = ex.accumulation_plan()
     ex.close()
-    return Vs, cid
+    return Vs, cid, plan
 
 
-def _check(name, precision, Vs, eig=False):
+def _check(name, precision, Vs, plan, eig=False):
     cfg, E, D, C, v, m64, refs, rho = _work(name)
-    emu = _emulated(name, precision)
+    emu = _emulated(name, precision, plan)
     for k in range(cfg.n_k):
         err = pr.normwise_error(Vs[k], refs[k])
         pred = pr.normwise_error(emu[k], refs[k])
@@ -86,9 +92,9 @@ def test_wide_instance_matches_oracle(name, precision, monkeypatch):
         monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
         print(f"[wide] {name} {precision} instance {cid}", flush=True)
         sys.stdout.flush()
-        Vs, got = _run(name, precision)
+        Vs, got, plan = _run(name, precision)
         assert got == cid
-        _check(name, precision, Vs, eig=name in ("c3", "c4"))
+        _check(name, precision, Vs, plan, eig=name in ("c3", "c4"))
 
 
 @pytest.mark.parametrize("precision,cid", [("bf16x3", 181), ("fp32", 186)])
@@ -97,9 +103,9 @@ def test_wide_split_items(precision, cid, monkeypatch):
     monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
     monkeypatch.setenv("EXC_FUSED_SPLIT", "1")
     print(f"[wide] ragged {precision} {cid} items per n'' chunk", flush=True)
-    Vs, got = _run("ragged", precision)
+    Vs, got, plan = _run("ragged", precision)
     assert got == cid
-    _check("ragged", precision, Vs)
+    _check("ragged", precision, Vs, plan)
 
 
 def test_complex128_call_leaves_the_wide_instance(monkeypatch):
@@ -107,6 +113,6 @@ def test_complex128_call_leaves_the_wide_instance(monkeypatch):
     monkeypatch.delenv("EXC_FUSED_SPLIT", raising=False)
     monkeypatch.setenv("EXC_FUSED_CFG", "181")
     print("[wide] small bf16x3 fixed to 181, complex128 M", flush=True)
-    Vs, got = _run("small", "bf16x3", dt=np.complex128)
+    Vs, got, plan = _run("small", "bf16x3", dt=np.complex128)
     assert got != 181
-    _check("small", "bf16x3", Vs)
+    _check("small", "bf16x3", Vs, plan)
