@@ -164,6 +164,20 @@ exc_status exchange_matrix(exc_ctx *ctx, int32_t k, const void *M, int32_t dtype
                            int32_t on_device, void *Vx, void *stream);
 
 /*
+ * exchange_matrix_noalloc -- exchange_matrix for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and result (bitwise), on device pointers M and Vx, with
+ * the call's partial results and block-sparse workspace in a static per-GPU scratch
+ * array of 64 MiB instead of context buffers. It calls no hipMalloc or hipFree.
+ *   Batched contexts only (EXC_EUNSUPPORTED otherwise, and for complex128 M when the
+ *   context's kernel reads complex64 only). EXC_EINVAL when this k needs more scratch
+ *   than the array holds (the message gives both sizes). All calls on one GPU share the
+ *   array: calls that overlap on one GPU (other streams, other threads) race.
+ */
+exc_status exchange_matrix_noalloc(exc_ctx *ctx, int32_t k, const void *M, int32_t dtype,
+                                   void *Vx, void *stream);
+
+/*
  * exchange_matrix_all -- V^x(k) for every irreducible k. M_k[k] and Vx_k[k] are
  * laid out as for exchange_matrix. With desc.batched = 1 all (k, q) work runs
  * in one persistent launch replayed from a HIP graph (re-captured when the

@@ -29,7 +29,8 @@ FORMS = {"gemm": 0, "herk": 1}
 DTYPES = {"c128": 0, "c64": 1}
 STATUS = {0: "EXC_OK", -1: "EXC_EINVAL", -2: "EXC_ENOMEM", -3: "EXC_ENOTPD", -4: "EXC_EHIP",
           -5: "EXC_ESTATE", -6: "EXC_EUNSUPPORTED"}
-EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_all", "exchange_energy",
+EXPORTED_SYMBOLS = ("exchange_init", "exchange_matrix", "exchange_matrix_noalloc", "exchange_matrix_all",
+                    "exchange_energy",
                     "exchange_energy_device", "exchange_gamma_term", "exchange_back_transform",
                     "exchange_band_mask",
                     "exchange_last_error", "exchange_destroy", "exchange_query", "exchange_timing",
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     lib.exchange_init.restype = i32
     lib.exchange_matrix.argtypes = [vp, i32, vp, i32, i32, vp, vp]
     lib.exchange_matrix.restype = i32
+    lib.exchange_matrix_noalloc.argtypes = [vp, i32, vp, i32, vp, vp]
+    lib.exchange_matrix_noalloc.restype = i32
     lib.exchange_matrix_all.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
     lib.exchange_matrix_all.restype = i32
     lib.exchange_energy.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp),
@@ -245,6 +248,21 @@ class Exchange:
                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(t, self.device))
         self._check(st)
         return out.view(nb, nb).T      # column-major -> [n][n'] view
+
+    def matrix_noalloc(self, k: int, M, out):
+        """V^x(k) through exchange_matrix_noalloc (no device allocation inside the call; out
+        is the caller's contiguous complex128 device tensor of n_b(k)^2 elements)."""
+        t = self._torch
+        nb = self.n_bands[k]
+        self._check_m(k, M)
+        self._check_out(k, out)
+        if not (M.is_cuda and M.is_contiguous() and out.is_cuda):
+            raise ExchangeError(-1, "M and out must be contiguous device tensors")
+        st = self.lib.exchange_matrix_noalloc(self.ctx, int(k), ctypes.c_void_p(M.data_ptr()),
+                                              self._dtype_code(M), ctypes.c_void_p(out.data_ptr()),
+                                              _stream_handle(t, self.device))
+        self._check(st)
+        return out.view(nb, nb).T
 
     def matrix_all(self, Ms: Sequence, outs=None):
         t = self._torch

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -29,6 +30,25 @@ using namespace exc;
 namespace {
 
 constexpr uint32_t kAlive = 0x45584331u;   // "EXC1"
+
+// Scratch of the no-allocation entry point (exchange_matrix_noalloc): the partial slots and
+// the block-sparse workspace of one k. One copy per GPU, held until the process ends; every
+// call on a GPU shares it. Host code takes its device address from hipGetSymbolAddress
+// (once per device, at exchange_init) and never uses the array's name as an address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device buffers that replace the context's own for one no-allocation call (see ScratchView
+// users: ws_base, tile_args, sparse_args, fused_args, cfg_sparse, cfg_reduce).
+struct ScratchView {
+  void* ws;          // workspace of the call's k, shifted by the k's first element
+  double* dsp;       // FP64 |Y_s|^2 sums, shifted by the k's first pair
+  void* gpart;       // Gram partial slots, shifted by the k's first slot
+  double* dpart;     // FP64 diagonal partials, shifted likewise
+};
 thread_local std::string g_init_err;
 
 struct KernelCfg {
@@ -213,6 +233,7 @@ struct exc_ctx {
   double* d_dsp = nullptr;
   void* d_gpart = nullptr;
   double* d_dpart = nullptr;
+  const ScratchView* sv = nullptr;    // set only during exchange_matrix_noalloc
   int gstride = 0, dstride = 0;
   double2* d_vres = nullptr;
   std::vector<int64_t> v_off;
@@ -332,6 +353,7 @@ exc_status ensure_ws(exc_ctx* c, size_t bytes) {
 // per-k call keeps only its own pairs' rows, so the base is shifted back by the
 // first offset of k (an address the kernels never form below the allocation).
 void* ws_base(const exc_ctx* c, int k) {
+  if (c->sv) return c->sv->ws;
   if (!c->d_ws) return nullptr;
   if (k < 0) return c->d_ws;
   return (void*)((uintptr_t)c->d_ws - (uintptr_t)c->k_ws_start[k] * c->ws_elem);
@@ -573,10 +595,10 @@ TileArgs tile_args(exc_ctx* c, int dtype, int k) {
   a.ns_pad = c->ns_pad;
   a.U = c->d_U;
   a.ws = ws_base(c, k);
-  a.dsp = c->d_dsp;
+  a.dsp = c->sv ? c->sv->dsp : c->d_dsp;
   a.dsp_stride = c->n_occ * c->nb_max;
-  a.gpart = c->d_gpart;
-  a.dpart = c->d_dpart;
+  a.gpart = c->sv ? c->sv->gpart : c->d_gpart;
+  a.dpart = c->sv ? c->sv->dpart : c->d_dpart;
   a.gstride = c->gstride;
   a.tmask = c->d_tmask;
   a.dstride = c->dstride;
@@ -591,7 +613,7 @@ SparseArgs sparse_args(exc_ctx* c, int dtype, int k) {
   s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max; s.ns_pad = c->ns_pad;
   s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
   s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
-  s.ws = ws_base(c, k); s.dsp = c->d_dsp;
+  s.ws = ws_base(c, k); s.dsp = c->sv ? c->sv->dsp : c->d_dsp;
   return s;
 }
 
@@ -605,7 +627,8 @@ FusedArgs fused_args(exc_ctx* c, int dtype) {
   f.row_chan = c->d_row_chan; f.ch_off = c->d_ch_off; f.ch_len = c->d_ch_len; f.ch_coef = c->d_ch_coef;
   f.coef = c->d_coef; f.cvec = c->d_cvec; f.rowinfo = c->d_rowinfo; f.coefpad = c->d_coefpad;
   f.schunk = c->d_schunk; f.n_schunk = c->n_schunk;
-  f.gpart = c->d_gpart; f.dpart = c->d_dpart;
+  f.gpart = c->sv ? c->sv->gpart : c->d_gpart;
+  f.dpart = c->sv ? c->sv->dpart : c->d_dpart;
   f.gstride = c->gstride; f.dstride = c->dstride;
   f.tmask = c->d_tmask;
   return f;
@@ -663,7 +686,7 @@ bool cfg_sparse(exc_ctx* c, int dtype, int k, int pair0, int npairs, SparseArgs&
   s = sparse_args(c, dtype, k);
   s.pairs = c->d_pairs + pair0;
   // dsp is indexed by blockIdx.y: offset it to the first pair
-  s.dsp = c->d_dsp ? c->d_dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
+  s.dsp = s.dsp ? s.dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
   L.grid = dim3((c->n_occ * c->nb_max + 3) / 4, npairs);
   L.block = dim3(256);
   L.shmem = sparse_lds_bytes(c);
@@ -677,10 +700,10 @@ void cfg_reduce(exc_ctx* c, const Plan& P, int k0, int nk, ReduceArgs& r, KLaunc
   r.k_nb = c->d_knb + k0;
   r.slot_begin = P.d_slot_begin + k0;
   r.slot_w = P.d_slot_w;
-  r.gpart = c->d_gpart;
+  r.gpart = c->sv ? c->sv->gpart : c->d_gpart;
   r.gstride = c->gstride;
   r.acc64 = c->precision == EXC_FP64;
-  r.dpart = c->d_dpart;
+  r.dpart = c->sv ? c->sv->dpart : c->d_dpart;
   r.dstride = c->dstride;
   r.use_d64 = c->form == EXC_FORM_CHOL_HERK && c->precision != EXC_FP64;
   r.vres = c->d_vres;
@@ -1052,6 +1075,21 @@ exc_status fit_dtype(exc_ctx* c, int dtype, hipStream_t st) {
   return configure(c, pick_fused(c->precision, c->nbt_max, c->real_v, dtype), st);
 }
 
+// The device address of this GPU's scratch array (once per device, with it current).
+exc_status scratch_setup(exc_ctx* c) {
+  if (c->device < 0 || c->device >= kScratchDevices)
+    return fail(c, EXC_EUNSUPPORTED, "device %d beyond the %d the library keeps scratch for", c->device,
+                kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[c->device]) return EXC_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(c, EXC_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_ptr[c->device] = p;
+  return EXC_OK;
+}
+
 exc_status check_ctx(const exc_ctx* c) {
   if (!c) return EXC_EINVAL;
   if (c->magic != kAlive) return EXC_ESTATE;
@@ -1139,6 +1177,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       c->wkq[(size_t)k * c->n_q + q] = d->w_kq ? d->w_kq[(size_t)k * c->n_q + q] : c->wq[q];
 
   IHIP(hipSetDevice(c->device));
+  ITRY(scratch_setup(c));
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
 
@@ -1480,6 +1519,56 @@ exc_status exchange_matrix(exc_ctx* c, int32_t k, const void* M, int32_t dtype, 
                              hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
   }
+  c->v_valid[k] = 1;
+  return EXC_OK;
+}
+
+exc_status exchange_matrix_noalloc(exc_ctx* c, int32_t k, const void* M, int32_t dtype, void* Vx,
+                                   void* stream) {
+  TRY(check_ctx(c));
+  if (k < 0 || k >= c->n_k) return fail(c, EXC_EINVAL, "k = %d outside [0, %d)", k, c->n_k);
+  if (!M || !Vx) return fail(c, EXC_EINVAL, "M or Vx is NULL");
+  if (dtype != EXC_C128 && dtype != EXC_C64) return fail(c, EXC_EINVAL, "bad dtype %d", dtype);
+  if (!c->batched || c->plain_gemm)
+    return fail(c, EXC_EUNSUPPORTED, "the no-allocation call serves batched contexts only");
+  if (c->fused && c->fcfg->c64only && dtype != EXC_C64)
+    return fail(c, EXC_EUNSUPPORTED, "this context's kernel reads complex64 M (exchange_matrix switches kernels)");
+  void* base = c->device >= 0 && c->device < kScratchDevices ? g_scratch_ptr[c->device] : nullptr;
+  if (!base) return fail(c, EXC_ESTATE, "no scratch address for device %d", c->device);
+  // this k's share of the buffers, each region 256-byte aligned
+  const Plan& P = c->bat;
+  const int s0 = P.slot_begin[k], ns = P.slot_begin[k + 1] - s0;
+  const int p0 = c->k_pair[k], np = c->k_pair[k + 1] - p0;
+  const size_t asz = c->precision == EXC_FP64 ? 8 : 4;
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t g_b = up((size_t)ns * c->gstride * asz), d_b = up((size_t)ns * c->dstride * 8);
+  const bool tile_path = !c->fused;
+  const size_t w_b = tile_path ? up((size_t)(c->k_ws_start[k + 1] - c->k_ws_start[k]) * c->ws_elem) : 0;
+  const size_t s_b = tile_path && c->d_dsp ? up((size_t)np * c->n_occ * c->nb_max * 8) : 0;
+  const size_t need = g_b + d_b + w_b + s_b;
+  if (need > kScratchBytes)
+    return fail(c, EXC_EINVAL, "k = %d needs %zu bytes of scratch; the no-allocation call holds %zu "
+                "(exchange_matrix has no such limit)", k, need, kScratchBytes);
+  const uintptr_t b = (uintptr_t)base;
+  ScratchView v{};
+  v.gpart = (void*)(b - (uintptr_t)s0 * c->gstride * asz);
+  v.dpart = (double*)(b + g_b - (uintptr_t)s0 * c->dstride * 8);
+  v.ws = tile_path ? (void*)(b + g_b + d_b - (uintptr_t)c->k_ws_start[k] * c->ws_elem) : nullptr;
+  v.dsp = s_b ? (double*)(b + g_b + d_b + w_b - (uintptr_t)p0 * c->n_occ * c->nb_max * 8) : nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  HIPCHK(c, hipSetDevice(c->device));
+  const void* mp[1] = {M};
+  void* vp[1] = {Vx};
+  TRY(set_tables(c, k, 1, mp, vp, st));
+  // the launches of run_k_batched, on the scratch (every slot, workspace row and |Y_s|^2 sum
+  // the reduction reads is written first by this call's kernels: nothing needs clearing)
+  c->sv = &v;
+  launch_sparse(c, dtype, k, p0, np, st);
+  launch_tile(c, dtype, k, P.d_items + P.k_item[k], P.k_item[k + 1] - P.k_item[k], st);
+  launch_reduce(c, P, k, 1, st);
+  c->sv = nullptr;
+  HIPCHK(c, hipGetLastError());
   c->v_valid[k] = 1;
   return EXC_OK;
 }

@@ -71,6 +71,7 @@ def test_null_context_calls(lib):
     v = ctypes.c_double()
     assert lib.exchange_query(None, 0, ctypes.byref(v)) == -1
     assert lib.exchange_matrix(None, 0, None, 0, 1, None, None) == -1
+    assert lib.exchange_matrix_noalloc(None, 0, None, 0, None, None) == -1
     assert lib.exchange_matrix_all(None, None, 0, 1, None, None) == -1
     assert lib.exchange_energy(None, None, None, ctypes.byref(v)) == -1
     assert lib.exchange_gamma_term(None, None, None, 0.005, 1, ctypes.byref(v), None) == -1
