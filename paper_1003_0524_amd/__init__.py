@@ -23,7 +23,9 @@ import numpy as np
 __all__ = ["Exchange", "ExchangeError", "load_library", "LIB_PATH", "PRECISIONS", "FORMS",
            "EXPORTED_SYMBOLS"]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libexchange.so")
+# EXC_LIBRARY: another build of the same library (the host-sanitizer build of the ABI checks)
+LIB_PATH = os.environ.get("EXC_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "libexchange.so")
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 FORMS = {"gemm": 0, "herk": 1}
 DTYPES = {"c128": 0, "c64": 1}

@@ -23,6 +23,12 @@
 
 namespace exc {
 
+// x with the sign bits of `mask` flipped (per 32-bit word; bf16 pairs: 0x80008000)
+__device__ __forceinline__ float sign_flip(float x, uint32_t mask) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ mask);
+}
+__device__ __forceinline__ u4_t sign_flip(u4_t x, uint32_t mask) { return x ^ mask; }
+
 template <int MODE, int NB8M, int RTW = 2>
 struct WideCfg {
   using T = Traits<MODE>;
@@ -219,17 +225,26 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
         for (int g = 0; g < ng; ++g) {
           const lds_t* SA = Sl + (g * nb8 + I * 8) * pitch;
           const lds_t* SB = Sl + (g * nb8 + J * 8) * pitch;
-#pragma unroll 1
-          for (int ks = 0; ks < ROWS / KS; ++ks) {
-            op_t ao[NP], bo[NP];
+          // operands of step ks + 1 requested before the products of step ks
+          op_t ao[2][NP], bo[2][NP];
+          auto ld = [&](int ks, op_t (&a_)[NP], op_t (&b_)[NP]) {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-              ao[p] = lds_operand<MODE>(SA + p * NCC * pitch + ks * KS);
-              bo[p] = lds_operand<MODE>(SB + p * NCC * pitch + ks * KS);
+              a_[p] = lds_operand<MODE>(SA + p * NCC * pitch + ks * KS);
+              b_[p] = lds_operand<MODE>(SB + p * NCC * pitch + ks * KS);
             }
+          };
+          ld(0, ao[0], bo[0]);
+          static_assert((ROWS / KS) % 2 == 0, "steps in pairs");
+#pragma unroll 1
+          for (int ks = 0; ks < ROWS / KS; ks += 2) {
 #pragma unroll
-            for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
-              acc = mfma(ao[NP == 1 ? 0 : prod_a(NP, pr)], bo[NP == 1 ? 0 : prod_b(NP, pr)], acc);
+            for (int u = 0; u < 2; ++u) {
+              if (ks + u + 1 < ROWS / KS) ld(ks + u + 1, ao[u ^ 1], bo[u ^ 1]);
+#pragma unroll
+              for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+                acc = mfma(ao[u][NP == 1 ? 0 : prod_a(NP, pr)], bo[u][NP == 1 ? 0 : prod_b(NP, pr)], acc);
+            }
           }
         }
         gacc[s] = acc;
@@ -537,37 +552,43 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           const lds_t* Pl = Pcs + (p & 1) * PCS + (lx & 7) * KC + 8 * (lx >> 4);
           const lds_t* B0 = Pl + xpart * NP * APL;
           const lds_t* B1 = Pl + (1 - xpart) * NP * APL;
-          const bool negl = xpart == 0;
+          // -Im for the real-part lanes of the h = 1 operand: a sign-bit mask, no branch
+          const uint32_t nmask = xpart == 0 ? (MODE == M_F32 ? 0x80000000u : 0x80008000u) : 0u;
+          // the panel's products for NA active row tiles (NA known at compile time: the loop
+          // below is straight-line code with no per-instruction branches)
+          auto panel = [&](auto na_c) {
+            constexpr int NA = decltype(na_c)::value;
 #pragma unroll
-          for (int ks = 0; ks < KC / KS; ++ks) {
-            auto bload = [&](int hj, op_t (&b)[NP]) {
-              const int h = hj / NCT, j = hj % NCT;
-              const lds_t* Bh = h == 0 ? B0 : B1;
+            for (int ks = 0; ks < KC / KS; ++ks) {
+              auto bload = [&](int hj, op_t (&b)[NP]) {
+                const int h = hj / NCT, j = hj % NCT;
+                const lds_t* Bh = h == 0 ? B0 : B1;
 #pragma unroll
-              for (int p2 = 0; p2 < NP; ++p2) {
-                b[p2] = lds_operand<MODE>(Bh + p2 * APL + j * 8 * KC + ks);
-                if (h == 1 && negl) b[p2] = negate(b[p2]);
-              }
-            };
-            op_t bA[NP], bB[NP];
-            bload(0, bA);
+                for (int p2 = 0; p2 < NP; ++p2) {
+                  b[p2] = lds_operand<MODE>(Bh + p2 * APL + j * 8 * KC + ks);
+                  if (h == 1) b[p2] = sign_flip(b[p2], nmask);
+                }
+              };
+              op_t bA[NP], bB[NP];
+              bload(0, bA);
 #pragma unroll
-            for (int hj = 0; hj < 2 * NCT; ++hj) {
-              const int h = hj / NCT, j = hj % NCT;
-              op_t (&bc)[NP] = (hj & 1) ? bB : bA;
-              op_t (&bn)[NP] = (hj & 1) ? bA : bB;
-              if (hj + 1 < 2 * NCT) bload(hj + 1, bn);
+              for (int hj = 0; hj < 2 * NCT; ++hj) {
+                const int h = hj / NCT, j = hj % NCT;
+                op_t (&bc)[NP] = (hj & 1) ? bB : bA;
+                op_t (&bn)[NP] = (hj & 1) ? bA : bB;
+                if (hj + 1 < 2 * NCT) bload(hj + 1, bn);
 #pragma unroll
-              for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+                for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
 #pragma unroll
-                for (int ii = 0; ii < RT; ++ii)
-                  if (ii < na)
+                  for (int ii = 0; ii < NA; ++ii)
                     acc[ii][j] = mfma(uop(ii, h, ks, NP == 1 ? 0 : prod_a(NP, pr)),
                                       bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
-              // keep the scheduler from hoisting later operand loads (register pressure)
-              __builtin_amdgcn_sched_barrier(0);
+                // keep the scheduler from hoisting later operand loads (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+              }
             }
-          }
+          };
+          if (na > 0) panel(std::integral_constant<int, RT>{});
           if (p + 1 < np) {
             // E: next panel's pieces from its raw panel (landed and visible since the last
             // barrier) into the other piece buffer; D: next panel's factor (after the
