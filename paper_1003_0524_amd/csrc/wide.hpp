@@ -459,14 +459,13 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
         };
         // raw panel -> pieces: thread u converts column u / (KC/8), k = 8 (u % (KC/8)) .. +7, four
         // k at a time; rows past N_d are zero
-        auto convert = [&](int kc, int rbuf, int pbuf) {
+        auto convert_half = [&](int kc, int rbuf, int pbuf, int hf) {
           constexpr int KG = KC / 8;
           if (tid < NCC * KG) {
             const int c = tid / KG, kg = tid % KG;
             const float* src = (const float*)(Raw + rbuf * C::RAW_B + (c * KC + kg * 8) * 8);
             lds_t* dst = Pcs + pbuf * PCS + c * KC + kg * 8;
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
+            {
               const f4_t v0 = *(const f4_t*)(src + 8 * hf), v1 = *(const f4_t*)(src + 8 * hf + 4);
               const int k0 = kc + kg * 8 + 4 * hf;
               const bool o0 = k0 < nd, o1 = k0 + 1 < nd, o2 = k0 + 2 < nd, o3 = k0 + 3 < nd;
@@ -477,6 +476,10 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
             }
           }
         };
+        auto convert = [&](int kc, int rbuf, int pbuf) {
+          convert_half(kc, rbuf, pbuf, 0);
+          convert_half(kc, rbuf, pbuf, 1);
+        };
         // factor pieces of this wave's two row tiles (w and w + NW of the block) for the panel at kc:
         // lane (l16, lq) holds row l16, k = 8 lq .. 8 lq + 7 of each piece plane (Re, then Im). The
         // matrix-core step ks takes k = 8 lq + ks from every lane group (bf16: one step over all 32
@@ -485,18 +488,24 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
         using ureg_t = typename std::conditional<MODE == M_F32, f4_t, u4_t>::type;
         constexpr int UPV = MODE == M_F32 ? 2 : NP;       // 16-byte registers per (row tile, Re/Im)
         ureg_t ucur[RT][2][UPV];
-        auto load_u = [&](int kc) {
+        // one half (h = 0: Re, 1: Im) of the factor pieces: NFL / 2 loads. The Re half of the
+        // next panel is requested in the middle of the current one, once its last product with
+        // the Re half has been issued, the Im half at its end: each half has half a panel of
+        // products to land in.
+        auto load_u_h = [&](int kc, int h) {
 #pragma unroll
           for (int ii = 0; ii < RT; ++ii) {
             const long row0 = (long)(r0 + 16 * (w + NW * ii)) * pi.ldu + kc;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-              for (int v = 0; v < UPV; ++v) {
-                const long e = MODE == M_F32 ? h * plane + row0 + 4 * v : (h * NP + v) * plane + row0;
-                ucur[ii][h][v] = buf_load<ureg_t>(urs, u_lane, (uint32_t)(e * C::ESZ));
-              }
+            for (int v = 0; v < UPV; ++v) {
+              const long e = MODE == M_F32 ? h * plane + row0 + 4 * v : (h * NP + v) * plane + row0;
+              ucur[ii][h][v] = buf_load<ureg_t>(urs, u_lane, (uint32_t)(e * C::ESZ));
+            }
           }
+        };
+        auto load_u = [&](int kc) {
+          load_u_h(kc, 0);
+          load_u_h(kc, 1);
         };
         // A operand of step ks, piece pa, from the registers above
         auto uop = [&](int ii, int h, int ks, int pa) -> op_t {
@@ -538,9 +547,18 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           // A: raw panel p + NRAW into the buffer panel p came in (converted before the last barrier)
           const bool issued = p + NRAW < np;
           if (issued) issue_raw(kc + NRAW * KC, p % NRAW);
-          // B: this panel's factor landed (only the raw loads just issued may still fly)
-          if (issued) wait_vm<NIW>();
-          else wait_vm<0>();
+          // B: the Re half of this panel's factor landed (its Im half and the raw loads just
+          // issued may still fly)
+          if (issued) wait_vm<NIW + NFL / 2>();
+          else wait_vm<NFL / 2>();
+          // the middle of the panel: the Im half landed (only the raw loads issued above may
+          // still fly), then the Re half of the next panel's factor into the registers the
+          // products with the Re half no longer read
+          auto mid = [&]() {
+            if (issued) wait_vm<NIW>();
+            else wait_vm<0>();
+            if (p + 1 < np) load_u_h(kc + KC, 0);
+          };
           // C: [Yr|Yi] += Ur [Ar|Ai] + Ui [-Ai|Ar] over the panel
           const int na = n_active(kc);
           // per-panel lane addresses from an opaque lane copy (see contract): the B operand of
@@ -556,6 +574,9 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           const uint32_t nmask = xpart == 0 ? (MODE == M_F32 ? 0x80000000u : 0x80008000u) : 0u;
           // the panel's products for NA active row tiles (NA known at compile time: the loop
           // below is straight-line code with no per-instruction branches)
+          // the next panel's conversion (VALU and LDS work of its own) goes between the
+          // products, in two halves, so that it runs while the matrix cores work
+          const bool conv = p + 1 < np;
           auto panel = [&](auto na_c) {
             constexpr int NA = decltype(na_c)::value;
 #pragma unroll
@@ -585,20 +606,32 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
                                       bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
                 // keep the scheduler from hoisting later operand loads (register pressure)
                 __builtin_amdgcn_sched_barrier(0);
+                if (ks == KC / KS - 1 && (hj == NCT / 2 || hj == NCT + NCT / 2) && conv) {
+                  convert_half(kc + KC, (p + 1) % NRAW, (p + 1) & 1, hj == NCT / 2 ? 0 : 1);
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                if (ks == KC / KS - 1 && hj == NCT - 1) {
+                  mid();
+                  __builtin_amdgcn_sched_barrier(0);
+                }
               }
             }
           };
-          if (na > 0) panel(std::integral_constant<int, RT>{});
+          if (na > 0) {
+            panel(std::integral_constant<int, RT>{});
+          } else {
+            mid();
+            if (conv) convert(kc + KC, (p + 1) % NRAW, (p + 1) & 1);
+          }
           if (p + 1 < np) {
-            // E: next panel's pieces from its raw panel (landed and visible since the last
-            // barrier) into the other piece buffer; D: next panel's factor (after the
-            // conversion, so that the two never hold registers at once)
-            convert(kc + KC, (p + 1) % NRAW, (p + 1) & 1);
-            load_u(kc + KC);
+            // (E, the next panel's pieces from its raw panel -- landed and visible since the
+            // last barrier -- into the other piece buffer, ran between the products above)
+            // D: the Im half of the next panel's factor, after the products that read this one's
+            load_u_h(kc + KC, 1);
             // F: own part of raw panel p + 2 landed, for the conversion after the next barrier.
-            // Loads issued after it: NRAW = 3 -> factor p + 1 (issued one panel earlier... no:
-            // the factor of this panel, issued at the end of the last one), raw p + 3 (A above,
-            // if issued) and factor p + 1 (D above); NRAW = 2 -> factor p + 1.
+            // Loads issued after it: NRAW = 3 -> both halves of this panel's factor (the middle
+            // and the end of the last panel), raw p + 3 (A above, if issued) and both halves of
+            // the next panel's; NRAW = 2 -> both halves of the next panel's factor.
             if (p + 2 < np) {
               if constexpr (NRAW == 3) {
                 if (issued) wait_vm<NIW + 2 * NFL>();
