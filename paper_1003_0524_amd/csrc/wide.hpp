@@ -40,12 +40,20 @@ struct WideCfg {
   static constexpr int KC = 32;                       // k of a K panel
   static constexpr int NCT = NB8M, NCC = 8 * NCT;     // band tiles (8 complex columns each), columns
   static constexpr int ESZ = (int)sizeof(lds_t), EPV = 16 / ESZ;
-  static constexpr int APL = NCC * KC;                // one piece plane of a panel: [column][k]
-  static constexpr int PCS = NPL * APL;               // one piece buffer (elements)
   static constexpr int RAWP = NCC * KC * 8;           // bytes of a raw complex64 panel
   static constexpr int NI = (RAWP + 1023) / 1024;     // 1 KB direct loads per panel
   static constexpr int NIW = (NI + NW - 1) / NW;      // per wavefront (the extra ones land in a trash KB)
   static constexpr int RAW_B = NI * 1024;
+  static constexpr size_t BUDGET = 163840 - 16 * 64 - 256;
+  static constexpr size_t DACC_B = (size_t)NW * NCC * 2 * sizeof(double);
+  // column pitch of a piece plane: KC plus a 16-byte skew, so that the operand reads of eight
+  // consecutive columns meet distinct LDS banks, where two piece buffers so padded still fit
+  // beside two raw panels (not for the six-product mode's wide instances)
+  static constexpr bool SKEW = (size_t)2 * RAW_B + 1024 + (size_t)2 * 2 * NP * NCC * (KC + EPV) * ESZ + DACC_B <=
+                               BUDGET;
+  static constexpr int KCP = SKEW ? KC + EPV : KC;
+  static constexpr int APL = NCC * KCP;               // one piece plane of a panel: [column][k]
+  static constexpr int PCS = NPL * APL;               // one piece buffer (elements)
   // factor loads per wavefront and panel: each lane takes 8 consecutive k of a row per piece
   // plane (one 16-byte load for bf16 pieces, two for FP32)
   static constexpr int NFL = RT * 2 * (MODE == M_F32 ? 2 : NP);
@@ -55,8 +63,7 @@ struct WideCfg {
   static constexpr int LDRS = GR + EPV;
   static constexpr int SP_MP = 0, SP_CF = SP_MP + CB * MPC * 16, SP_ST = SP_CF + MAXT * GR * 16;
   static constexpr size_t SPARSE_B = (size_t)SP_ST + (size_t)NPL * NCC * LDRS * ESZ;
-  static constexpr size_t DACC_B = (size_t)NW * NCC * 2 * sizeof(double);
-  static constexpr size_t BUDGET = 163840 - 16 * MAXCK - 256;
+  static_assert(MAXCK == 64, "the LDS budget above reserves 64 chunk descriptors");
   // Gram stage of the dense rows: GS rows at a time (rows contiguous per column)
   static constexpr int GS = (BM >= 128 && (size_t)NPL * NCC * (128 + EPV) * ESZ + DACC_B <= BUDGET) ? 128 : 64;
   static constexpr int LDR = GS + EPV;
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
   using accv_t = typename Traits<MODE>::accv_t;
   using op_t = decltype(lds_operand<MODE>((const lds_t*)nullptr));
   constexpr int NW = C::NW, NT = C::NT, NP = C::NP, KS = C::KS, KPL = C::KPL, NPL = C::NPL;
-  constexpr int NCC = C::NCC, NCT = C::NCT, KC = C::KC, APL = C::APL, PCS = C::PCS, RT = C::RT;
+  constexpr int NCC = C::NCC, NCT = C::NCT, KC = C::KC, KCP = C::KCP, APL = C::APL, PCS = C::PCS, RT = C::RT;
   constexpr int BM = C::BM, GR = C::GR, GS = C::GS, LDR = C::LDR, NIW = C::NIW, NI = C::NI;
   constexpr int NRAW = C::NRAW, NFL = C::NFL;
 
@@ -464,7 +471,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           if (tid < NCC * KG) {
             const int c = tid / KG, kg = tid % KG;
             const float* src = (const float*)(Raw + rbuf * C::RAW_B + (c * KC + kg * 8) * 8);
-            lds_t* dst = Pcs + pbuf * PCS + c * KC + kg * 8;
+            lds_t* dst = Pcs + pbuf * PCS + c * KCP + kg * 8;
             {
               const f4_t v0 = *(const f4_t*)(src + 8 * hf), v1 = *(const f4_t*)(src + 8 * hf + 4);
               const int k0 = kc + kg * 8 + 4 * hf;
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           int lx = lane;
           asm volatile("" : "+v"(lx));
           const int xpart = (lx >> 3) & 1;
-          const lds_t* Pl = Pcs + (p & 1) * PCS + (lx & 7) * KC + 8 * (lx >> 4);
+          const lds_t* Pl = Pcs + (p & 1) * PCS + (lx & 7) * KCP + 8 * (lx >> 4);
           const lds_t* B0 = Pl + xpart * NP * APL;
           const lds_t* B1 = Pl + (1 - xpart) * NP * APL;
           // -Im for the real-part lanes of the h = 1 operand: a sign-bit mask, no branch
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
                 const lds_t* Bh = h == 0 ? B0 : B1;
 #pragma unroll
                 for (int p2 = 0; p2 < NP; ++p2) {
-                  b[p2] = lds_operand<MODE>(Bh + p2 * APL + j * 8 * KC + ks);
+                  b[p2] = lds_operand<MODE>(Bh + p2 * APL + j * 8 * KCP + ks);
                   if (h == 1) b[p2] = sign_flip(b[p2], nmask);
                 }
               };
