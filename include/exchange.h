@@ -132,8 +132,17 @@ typedef struct {
 
 typedef struct {
   const void *const *E;     /* [n_q] -> N_d(q)^2 complex128, column-major, Hermitian     */
-  const void *D;            /* concat over channels of (nrad_c-1)^2 complex128, col-major */
-  const void *C;            /* concat over channels of (nrad_c-1) complex128              */
+  const void *const *D;     /* [n_q] -> concat over channels of (nrad_c-1)^2 complex128,
+                               column-major: the multipole-free blocks D_c of v(q)
+                               (Sec. III.C, Fig. 1). Entries may alias: when all n_q
+                               pointers are equal (the blocks do not depend on q, as a
+                               function with no multipole produces no potential outside
+                               its sphere) one copy is kept; otherwise one per q.
+                               NULL (or NULL entries) allowed only without such functions */
+  const void *const *C;     /* [n_q] -> concat over channels of (nrad_c-1) complex128: the
+                               couplings C_c of each block to its channel's multipole
+                               function; aliasing as for D (one copy only when both D and
+                               C alias across q)                                         */
   int32_t on_device;        /* 0: host pointers, 1: device pointers (copied either way)   */
 } exc_coulomb;
 

@@ -58,8 +58,8 @@ class _Desc(ctypes.Structure):
 
 
 class _Coulomb(ctypes.Structure):
-    _fields_ = [("E", ctypes.POINTER(ctypes.c_void_p)), ("D", ctypes.c_void_p), ("C", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32)]
+    _fields_ = [("E", ctypes.POINTER(ctypes.c_void_p)), ("D", ctypes.POINTER(ctypes.c_void_p)),
+                ("C", ctypes.POINTER(ctypes.c_void_p)), ("on_device", ctypes.c_int32)]
 
 
 _lib = None
@@ -139,10 +139,14 @@ class Exchange:
     def __init__(self, n_bands: Sequence[int], n_pw: Sequence[int], ch_nrad: Sequence[int],
                  n_occ: int, E: Sequence[np.ndarray], D: Sequence[np.ndarray], C: Sequence[np.ndarray],
                  w_q: Optional[Sequence[float]] = None, precision: str = "fp64", form: str = "herk",
-                 batched: bool = True, device: int = 0, inversion: bool = False, w_kq=None):
+                 batched: bool = True, device: int = 0, inversion: bool = False, w_kq=None,
+                 D_q=None, C_q=None):
         """inversion=True: real v and real bands; M packs bands 2j, 2j+1 as the real and imaginary
         parts of column j (``synth.pack_real_pairs``) and V(k) comes back real (Im = 0).
-        w_kq: [n_k][n_q] pair weights (0 leaves the pair out and its q block out of M(k))."""
+        w_kq: [n_k][n_q] pair weights (0 leaves the pair out and its q block out of M(k)).
+        D, C: the channel blocks of every q; D_q, C_q (lists over q of such lists) instead give
+        each q its own (blocks of different q may be the same objects). E given as CUDA
+        tensors: the blocks are taken from device memory (D and C copied there first)."""
         import torch
         if not torch.cuda.is_available():
             raise ExchangeError(-5, "no GPU visible: the exchange library runs only on a HIP device")
@@ -173,14 +177,42 @@ class Exchange:
                      PRECISIONS[precision], FORMS[form], 1 if batched else 0, device,
                      1 if self.inversion else 0,
                      wkq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if wkq_arr is not None else None)
-        e_host = [np.ascontiguousarray(np.asarray(e, dtype=np.complex128).T) for e in E]  # column-major
-        e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.ctypes.data for e in e_host])
-        d_cat = np.concatenate([np.asarray(d, np.complex128).T.ravel() for d in D] + [np.zeros(0, np.complex128)])
-        c_cat = np.concatenate([np.asarray(c, np.complex128).ravel() for c in C] + [np.zeros(0, np.complex128)])
-        d_cat = np.ascontiguousarray(d_cat)
-        c_cat = np.ascontiguousarray(c_cat)
-        coul = _Coulomb(e_ptrs, d_cat.ctypes.data if d_cat.size else None,
-                        c_cat.ctypes.data if c_cat.size else None, 0)
+        def cat(blocks, tr):
+            return np.ascontiguousarray(np.concatenate(
+                [(np.asarray(b, np.complex128).T if tr else np.asarray(b, np.complex128)).ravel() for b in blocks]
+                + [np.zeros(0, np.complex128)]))
+        if D_q is None:
+            d_cats, c_cats = [cat(D, True)], [cat(C, False)]
+            d_of, c_of = [0] * self.n_q, [0] * self.n_q
+        else:
+            # one copy per distinct set of blocks: q that share their blocks share a pointer
+            d_cats, c_cats, d_of, c_of, seen = [], [], [], [], {}
+            for q in range(self.n_q):
+                key = (id(D_q[q]), id(C_q[q]))
+                if key not in seen:
+                    seen[key] = len(d_cats)
+                    d_cats.append(cat(D_q[q], True))
+                    c_cats.append(cat(C_q[q], False))
+                d_of.append(seen[key])
+                c_of.append(seen[key])
+        on_dev = all(isinstance(e, torch.Tensor) and e.is_cuda for e in E)
+        if on_dev:
+            # blocks already in device memory: copied on the device (no host round trip)
+            e_keep = [e.to(torch.complex128).T.contiguous() for e in E]         # column-major
+            e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.data_ptr() for e in e_keep])
+            d_keep = [torch.from_numpy(x).to(E[0].device) for x in d_cats]
+            c_keep = [torch.from_numpy(x).to(E[0].device) for x in c_cats]
+            dp = [x.data_ptr() if x.numel() else None for x in d_keep]
+            cp = [x.data_ptr() if x.numel() else None for x in c_keep]
+            torch.cuda.synchronize()          # the copies above have landed before init reads them
+        else:
+            e_keep = [np.ascontiguousarray(np.asarray(e, dtype=np.complex128).T) for e in E]   # column-major
+            e_ptrs = (ctypes.c_void_p * self.n_q)(*[e.ctypes.data for e in e_keep])
+            dp = [x.ctypes.data if x.size else None for x in d_cats]
+            cp = [x.ctypes.data if x.size else None for x in c_cats]
+        d_ptrs = (ctypes.c_void_p * self.n_q)(*[dp[i] for i in d_of])
+        c_ptrs = (ctypes.c_void_p * self.n_q)(*[cp[i] for i in c_of])
+        coul = _Coulomb(e_ptrs, d_ptrs, c_ptrs, 1 if on_dev else 0)
         torch.cuda.set_device(device)
         ctx = ctypes.c_void_p()
         st = self.lib.exchange_init(ctypes.byref(desc), ctypes.byref(coul), _stream_handle(torch, device),

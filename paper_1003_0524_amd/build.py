@@ -47,5 +47,39 @@ def build(verbose: bool = False, only=None) -> None:
         os.replace(tmp, out)
 
 
+ASAN_LIB = os.path.join(HERE, "libexchange_asan.so")
+
+
+def asan_runtime() -> str:
+    """The compiler's AddressSanitizer runtime (to preload into a host process)."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    hits = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")) +
+                  glob.glob(os.path.join(root, "lib", "clang", "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("no libclang_rt.asan-x86_64.so next to hipcc")
+    return hits[-1]
+
+
+def build_asan(out: str = ASAN_LIB) -> str:
+    """The exchange library with its host code under AddressSanitizer (device code as usual),
+    for running the ABI's argument checks under the sanitizer on a machine without a GPU."""
+    src = os.path.join(HERE, "csrc", "exchange.hip")
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-result", "-Wno-unused-value", "-I" + os.path.join(ROOT, "include"), src, "-o", out + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise RuntimeError("hipcc failed for the sanitizer build")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True, only=sys.argv[1:] or None)
+    if sys.argv[1:] == ["--asan"]:
+        print(build_asan())
+    else:
+        build(verbose=True, only=sys.argv[1:] or None)

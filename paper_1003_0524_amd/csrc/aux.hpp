@@ -41,6 +41,7 @@ struct SparseArgs {
   const int64_t* ch_coef;    // [n_ch] offset of the channel's square block in coef
   const double2* coef;       // HERK: L_c (lower, col-major); GEMM: D_c (col-major)
   const double2* cvec;       // [n_s] HERK: l_c = L_c^{-1} C_c; GEMM: C_c
+  int64_t coef_qs, cvec_qs;  // elements between the copies of q and q + 1 (0: one copy for all q)
   void* ws;                  // output rows
   double* dsp;               // HERK, reduced precision: sum_r |Y_s[r][n]|^2 per column
 };
@@ -50,6 +51,8 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
   extern __shared__ double2 scol[];          // [4 waves][n_s + n_ch]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const PairInfo pi = a.pairs[blockIdx.y];
+  const double2* coef = a.coef + pi.q * a.coef_qs;      // this q's channel blocks
+  const double2* cvec = a.cvec + pi.q * a.cvec_qs;
   const int col = blockIdx.x * 4 + w;
   const bool active = col < a.n_occ * pi.nb;
   const int nrow = a.n_s + a.n_ch;
@@ -74,20 +77,20 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
     double2* out = (double2*)a.ws;
     for (int r = lane; r < a.n_s; r += 64) {
       const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-      const double2* cf = a.coef + a.ch_coef[c];
+      const double2* cf = coef + a.ch_coef[c];
       double2 y = make_double2(0.0, 0.0);
       if (FORM == 1) {
         for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
       } else {
         for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], S[s + j]));
       }
-      out[wcol + r] = cadd(y, cmul(a.cvec[r], S[a.n_s + c]));
+      out[wcol + r] = cadd(y, cmul(cvec[r], S[a.n_s + c]));
     }
     if (FORM == 0) {
       for (int c = lane; c < a.n_ch; c += 64) {
         const int s = a.ch_off[c], b = a.ch_len[c];
         double2 x = make_double2(0.0, 0.0);
-        for (int j = 0; j < b; ++j) x = cadd(x, cmulc(a.cvec[s + j], S[s + j]));
+        for (int j = 0; j < b; ++j) x = cadd(x, cmulc(cvec[s + j], S[s + j]));
         out[wcol + a.n_s + c] = x;
       }
     }
@@ -102,9 +105,9 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
       double2 y = make_double2(0.0, 0.0);
       if (r < a.n_s) {
         const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-        const double2* cf = a.coef + a.ch_coef[c];
+        const double2* cf = coef + a.ch_coef[c];
         for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
-        y = cadd(y, cmul(a.cvec[r], S[a.n_s + c]));
+        y = cadd(y, cmul(cvec[r], S[a.n_s + c]));
         dsum += y.x * y.x + y.y * y.y;
       }
       put_real<MODE>(out + r, pi.ldw, y.x);
@@ -320,11 +323,16 @@ __global__ __launch_bounds__(256) void energy_sum_kernel(const double* e_k, cons
 // diagonal entry. With one multipole function per channel the Schur
 // complement E - C^H D^{-1} C changes only those diagonal entries.
 // ---------------------------------------------------------------------------
+// blockIdx.y: the copy of the channel blocks (one per q when they depend on q), strides in
+// elements between copies.
 __global__ void chan_chol_kernel(int n_ch, const int32_t* ch_off, const int32_t* ch_len,
                                  const int64_t* ch_coef, double2* L, double2* lvec,
-                                 double* schur, int* info) {
+                                 double* schur, int* info, int64_t coef_qs, int64_t cvec_qs) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_ch) return;
+  L += blockIdx.y * coef_qs;
+  lvec += blockIdx.y * cvec_qs;
+  schur += (long)blockIdx.y * n_ch;
   const int b = ch_len[c], s = ch_off[c];
   double2* A = L + ch_coef[c];
   for (int j = 0; j < b; ++j) {
@@ -371,7 +379,8 @@ struct CholArgs {
   const int32_t* nd;
   const int32_t* lda;
   int32_t n_ch;
-  const double* schur;    // [n_ch] or nullptr
+  const double* schur;    // [n_ch] (per q: [n_q][n_ch]) or nullptr
+  int32_t schur_qs;       // n_ch when the channel blocks depend on q, else 0
   int* info;              // [n_q] first failing pivot (1-based), 0 = ok
 };
 
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
   double2* A = a.A + a.a_off[q];
   if (tid == 0) s_fail = 0;
   if (a.schur)
-    for (int c = tid; c < a.n_ch && c < n; c += 256) A[c + (long)c * lda].x -= a.schur[c];
+    for (int c = tid; c < a.n_ch && c < n; c += 256) A[c + (long)c * lda].x -= a.schur[(long)q * a.schur_qs + c];
   __syncthreads();
   for (int jb = 0; jb < n; jb += NB) {
     const int nbk = min(NB, n - jb);
@@ -521,7 +530,10 @@ __global__ __launch_bounds__(256) void prep_factor_kernel(const double2* src, co
 // last chunk). Lanes that hold consecutive rows then read consecutive entries.
 __global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, const int4* rowinfo,
                                                        const int4* chunks, int nchunk, int mt, int gr,
-                                                       double2* out) {
+                                                       double2* out, int64_t coef_qs) {
+  // blockIdx.y: the copy of the channel blocks (its padded runs follow the previous copy's)
+  coef += blockIdx.y * coef_qs;
+  out += (long)blockIdx.y * nchunk * mt * gr;
   // out[chunk][t][rr] = L_c[i+t][i] of the chunk's row rr (entry i of channel c), zero past the run
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)nchunk * mt * gr) return;

@@ -194,6 +194,7 @@ struct exc_ctx {
   std::vector<int> ch_off, ch_len;
   std::vector<int64_t> ch_coef;
   int64_t coef_total = 0;
+  int nqc = 1;                        // copies of the channel blocks (n_q when they depend on q)
   // device-resident Coulomb data
   double2* d_coef = nullptr;
   double2* d_cvec = nullptr;
@@ -613,6 +614,8 @@ SparseArgs sparse_args(exc_ctx* c, int dtype, int k) {
   s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max; s.ns_pad = c->ns_pad;
   s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
   s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
+  s.coef_qs = c->nqc > 1 ? c->coef_total : 0;
+  s.cvec_qs = c->nqc > 1 ? c->n_s : 0;
   s.ws = ws_base(c, k); s.dsp = c->sv ? c->sv->dsp : c->d_dsp;
   return s;
 }
@@ -627,6 +630,9 @@ FusedArgs fused_args(exc_ctx* c, int dtype) {
   f.row_chan = c->d_row_chan; f.ch_off = c->d_ch_off; f.ch_len = c->d_ch_len; f.ch_coef = c->d_ch_coef;
   f.coef = c->d_coef; f.cvec = c->d_cvec; f.rowinfo = c->d_rowinfo; f.coefpad = c->d_coefpad;
   f.schunk = c->d_schunk; f.n_schunk = c->n_schunk;
+  f.coef_qs = c->nqc > 1 ? c->coef_total : 0;
+  f.cvec_qs = c->nqc > 1 ? c->n_s : 0;
+  f.pad_qs = c->nqc > 1 ? (int64_t)std::max(1, c->n_schunk) * kChunkRows * kRunPad : 0;
   f.gpart = c->sv ? c->sv->gpart : c->d_gpart;
   f.dpart = c->sv ? c->sv->dpart : c->d_dpart;
   f.gstride = c->gstride; f.dstride = c->dstride;
@@ -1226,19 +1232,25 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   // ---- Coulomb blocks to the device ----
   {
     const hipMemcpyKind kind = cv->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    ITRY(dalloc(c, &c->d_coef, (size_t)c->coef_total));
-    ITRY(dalloc(c, &c->d_cvec, (size_t)c->n_s));
-    if (c->coef_total) {
-      if (!cv->D) { fail(c, EXC_EINVAL, "coulomb.D is NULL"); return bail(EXC_EINVAL); }
-      IHIP(hipMemcpy(c->d_coef, cv->D, c->coef_total * 16, kind));
-    }
+    // channel blocks: one copy when every q points at the same D and C, else one per q
     if (c->n_s) {
-      if (!cv->C) { fail(c, EXC_EINVAL, "coulomb.C is NULL"); return bail(EXC_EINVAL); }
-      IHIP(hipMemcpy(c->d_cvec, cv->C, (size_t)c->n_s * 16, kind));
+      if (!cv->D || !cv->C) { fail(c, EXC_EINVAL, "coulomb.D or coulomb.C is NULL"); return bail(EXC_EINVAL); }
+      bool alias = true;
+      for (int q = 0; q < c->n_q; ++q) {
+        if (!cv->D[q] || !cv->C[q]) { fail(c, EXC_EINVAL, "coulomb.D[%d] or coulomb.C[%d] is NULL", q, q); return bail(EXC_EINVAL); }
+        alias = alias && cv->D[q] == cv->D[0] && cv->C[q] == cv->C[0];
+      }
+      c->nqc = alias ? 1 : c->n_q;
+    }
+    ITRY(dalloc(c, &c->d_coef, (size_t)c->coef_total * c->nqc));
+    ITRY(dalloc(c, &c->d_cvec, (size_t)c->n_s * c->nqc));
+    for (int i = 0; i < c->nqc && c->n_s; ++i) {
+      if (c->coef_total) IHIP(hipMemcpy(c->d_coef + (size_t)i * c->coef_total, cv->D[i], c->coef_total * 16, kind));
+      IHIP(hipMemcpy(c->d_cvec + (size_t)i * c->n_s, cv->C[i], (size_t)c->n_s * 16, kind));
     }
     if (c->real_v) {                  // only the real parts of v are read
-      if (c->coef_total) IHIP(hipMemset2D((char*)c->d_coef + 8, 16, 0, 8, (size_t)c->coef_total));
-      if (c->n_s) IHIP(hipMemset2D((char*)c->d_cvec + 8, 16, 0, 8, (size_t)c->n_s));
+      if (c->coef_total) IHIP(hipMemset2D((char*)c->d_coef + 8, 16, 0, 8, (size_t)c->coef_total * c->nqc));
+      if (c->n_s) IHIP(hipMemset2D((char*)c->d_cvec + 8, 16, 0, 8, (size_t)c->n_s * c->nqc));
     }
     ITRY(upload(c, &c->d_row_chan, row_chan));
     {
@@ -1254,12 +1266,12 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       c->n_schunk = (int)ck.size();
       if (ck.empty()) ck.push_back(make_int4(0, 0, 0, 0));
       ITRY(upload(c, &c->d_schunk, ck));
-      ITRY(dalloc(c, &c->d_coefpad, (size_t)ck.size() * kChunkRows * kRunPad));
+      ITRY(dalloc(c, &c->d_coefpad, (size_t)ck.size() * kChunkRows * kRunPad * c->nqc));
     }
     ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));
     ITRY(upload(c, &c->d_ch_len, std::vector<int32_t>(c->ch_len.begin(), c->ch_len.end())));
     ITRY(upload(c, &c->d_ch_coef, c->ch_coef));
-    ITRY(dalloc(c, &c->d_schur, (size_t)std::max(1, c->n_ch)));
+    ITRY(dalloc(c, &c->d_schur, (size_t)std::max(1, c->n_ch) * c->nqc));
 
     // dense blocks: a column-major workspace per q (factored in place for HERK)
     std::vector<int64_t> e_off(c->n_q);
@@ -1282,6 +1294,12 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         if (e != hipSuccess) { cleanup(); fail(c, EXC_EHIP, "copy of E[%d]: %s", q, hipGetErrorString(e)); return bail(EXC_EHIP); }
       }
     }
+    // device-to-device copies need not have finished when hipMemcpy returns: the kernels
+    // below run on `stream`
+    if (cv->on_device) {
+      const hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) { cleanup(); fail(c, EXC_EHIP, "copy of the blocks: %s", hipGetErrorString(e)); return bail(EXC_EHIP); }
+    }
     if ((s = upload(c, &d_eoff, e_off)) != EXC_OK || (s = upload(c, &d_uoff, c->u_off)) != EXC_OK ||
         (s = upload(c, &d_nd, nd32)) != EXC_OK || (s = upload(c, &d_eld, e_ld)) != EXC_OK ||
         (s = upload(c, &d_ldu, ldu32)) != EXC_OK || (s = dalloc(c, &d_info, (size_t)c->n_q + 1)) != EXC_OK) {
@@ -1293,10 +1311,12 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     if (s != EXC_OK) { cleanup(); return bail(s); }
     if (c->form == EXC_FORM_CHOL_HERK) {
       if (c->n_ch)
-        hipLaunchKernelGGL(chan_chol_kernel, dim3((c->n_ch + 63) / 64), dim3(64), 0, st, c->n_ch,
+        hipLaunchKernelGGL(chan_chol_kernel, dim3((c->n_ch + 63) / 64, c->nqc), dim3(64), 0, st, c->n_ch,
                            c->d_ch_off, c->d_ch_len, c->d_ch_coef, c->d_coef, c->d_cvec,
-                           c->d_schur, d_info + c->n_q);
-      CholArgs ca{d_E, d_eoff, d_nd, d_eld, c->n_ch, c->n_ch ? c->d_schur : nullptr, d_info};
+                           c->d_schur, d_info + c->n_q, c->nqc > 1 ? c->coef_total : (int64_t)0,
+                           c->nqc > 1 ? (int64_t)c->n_s : (int64_t)0);
+      CholArgs ca{d_E, d_eoff, d_nd, d_eld, c->n_ch, c->n_ch ? c->d_schur : nullptr,
+                  c->nqc > 1 ? c->n_ch : 0, d_info};
       hipLaunchKernelGGL(dense_chol_kernel, dim3(c->n_q), dim3(256), 0, st, ca);
     }
     dim3 pg(64, c->n_q);
@@ -1329,8 +1349,9 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
     if (c->n_s > 0) {
       // the fused kernel's padded runs of the (now factored) channel coefficients
       const long ne = (long)std::max(1, c->n_schunk) * kChunkRows * kRunPad;
-      hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, c->d_coef,
-                         c->d_rowinfo, c->d_schunk, c->n_schunk, kRunPad, kChunkRows, c->d_coefpad);
+      hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256), c->nqc), dim3(256), 0, st, c->d_coef,
+                         c->d_rowinfo, c->d_schunk, c->n_schunk, kRunPad, kChunkRows, c->d_coefpad,
+                         c->nqc > 1 ? c->coef_total : (int64_t)0);
       IHIP(hipGetLastError());
       IHIP(hipStreamSynchronize(st));
     }

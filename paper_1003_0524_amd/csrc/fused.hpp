@@ -111,6 +111,8 @@ struct FusedArgs {
   int32_t n_schunk;               //  {first row, rows, longest run, first multipole row}
   const double2* coefpad;         // per chunk, [MAXT][64]: the first MAXT entries of each row's
                                   // run (transposed), zero padded
+  int64_t coef_qs, cvec_qs, pad_qs;   // elements between the copies of q and q + 1 of coef,
+                                      // cvec and coefpad (0: one copy for all q)
   const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
                                   // {index in coef of conj-coefficient run L_c[i..b-1][i], b - i,
                                   //  multipole row n_s + c, 0}
@@ -396,12 +398,12 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
           if (lane < ci.y) {
             const int4 ri = a.rowinfo[ci.x + lane];
             d.cs = ri.x; d.len = ri.y; d.mloc = ri.z - ci.w;
-            d.lc = a.cvec[ci.x + lane];
+            d.lc = a.cvec[pi.q * a.cvec_qs + ci.x + lane];
           }
         };
         u4_t cfn[CFL];                                // the next chunk's coefficient table
         auto load_coef = [&](int ck) {
-          const u4_t* src = (const u4_t*)(a.coefpad + (long)ck * MAXT * GR);
+          const u4_t* src = (const u4_t*)(a.coefpad + pi.q * a.pad_qs + (long)ck * MAXT * GR);
 #pragma unroll
           for (int i = 0; i < CFL; ++i) cfn[i] = src[tid + NT * i];
         };
@@ -509,7 +511,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
           const int T = min(ci.z, MAXT);
           for (int t = 0; t < T; ++t) term(Cf[t * GR + lane]);
           for (int t = MAXT; t < ci.z; ++t)           // runs longer than the staged table
-            term(t < rd.len ? a.coef[rd.cs + t] : make_double2(0.0, 0.0));
+            term(t < rd.len ? a.coef[pi.q * a.coef_qs + rd.cs + t] : make_double2(0.0, 0.0));
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
             const int c = cb0 + w + NW * j;

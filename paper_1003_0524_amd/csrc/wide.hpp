@@ -295,14 +295,14 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           if (lane < ci.y) {
             const int4 ri = a.rowinfo[ci.x + lane];
             d.cs = ri.x; d.len = ri.y; d.mloc = ri.z - ci.w;
-            d.lc = a.cvec[ci.x + lane];
+            d.lc = a.cvec[pi.q * a.cvec_qs + ci.x + lane];
           }
         };
         constexpr int CFN = MAXT * GR;                  // coefficient table entries (16 B)
         constexpr int CFL = (CFN + NT - 1) / NT;
         u4_t cfn[CFL];
         auto load_coef = [&](int ck) {
-          const u4_t* src = (const u4_t*)(a.coefpad + (long)ck * MAXT * GR);
+          const u4_t* src = (const u4_t*)(a.coefpad + pi.q * a.pad_qs + (long)ck * MAXT * GR);
 #pragma unroll
           for (int i = 0; i < CFL; ++i)
             if (tid + NT * i < CFN) cfn[i] = src[tid + NT * i];
@@ -382,7 +382,8 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
           };
           const int Tn = min(ci.z, MAXT);
           for (int t = 0; t < Tn; ++t) term(Cf[t * GR + lane]);
-          for (int t = MAXT; t < ci.z; ++t) term(t < rd.len ? a.coef[rd.cs + t] : make_double2(0.0, 0.0));
+          for (int t = MAXT; t < ci.z; ++t)
+            term(t < rd.len ? a.coef[pi.q * a.coef_qs + rd.cs + t] : make_double2(0.0, 0.0));
 #pragma unroll
           for (int j = 0; j < CPW; ++j) {
             const int c = cb0 + w + NW * j;
