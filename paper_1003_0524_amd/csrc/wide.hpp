@@ -21,6 +21,8 @@
 #pragma once
 #include "fused.hpp"
 
+#include <utility>
+
 namespace exc {
 
 // x with the sign bits of `mask` flipped (per 32-bit word; bf16 pairs: 0x80008000)
@@ -28,6 +30,71 @@ __device__ __forceinline__ float sign_flip(float x, uint32_t mask) {
   return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ mask);
 }
 __device__ __forceinline__ u4_t sign_flip(u4_t x, uint32_t mask) { return x ^ mask; }
+
+// Gram tile schedule of the wide kernel: the upper triangle of NCT x NCT band tiles is split into
+// units -- a row pair m (band tiles 2m, 2m + 1) times a band-tile range [j0, j1) -- at most two per
+// wavefront. Per 32 rows a unit reads its two row operands once and each column operand once for both
+// rows, where the round robin (tile w + 8 s) reads both operands of every tile. The units were found by
+// a search over segmentations of the row pairs' ranges, assigned longest first to the least loaded
+// wavefront: 12 tiles per wavefront for 13 band tiles (17 for 16), as many as the round robin, with at
+// most 10 (13) operand reads per 32 rows instead of 24 (34).
+struct GramUnits { int u[8][2][3]; };
+constexpr GramUnits gram_units(int nct) {
+  return nct == 13 ? GramUnits{{{{0, 6, 12}, {-1, 0, 0}}, {{0, 0, 6}, {6, 12, 13}}, {{1, 2, 8}, {-1, 0, 0}},
+                                {{2, 4, 10}, {-1, 0, 0}}, {{3, 6, 12}, {-1, 0, 0}}, {{1, 8, 13}, {3, 12, 13}},
+                                {{4, 8, 13}, {0, 12, 13}}, {{2, 10, 13}, {5, 10, 13}}}}
+                   : GramUnits{{{{0, 0, 9}, {-1, 0, 0}}, {{1, 2, 11}, {-1, 0, 0}}, {{2, 4, 13}, {-1, 0, 0}},
+                                {{3, 6, 15}, {-1, 0, 0}}, {{4, 8, 16}, {3, 15, 16}}, {{0, 9, 16}, {7, 14, 16}},
+                                {{5, 10, 16}, {2, 13, 16}}, {{1, 11, 16}, {6, 12, 16}}}};
+}
+template <int NCT>
+struct GramSched {
+  static constexpr bool ON = NCT == 13 || NCT == 16;
+  static constexpr GramUnits G = gram_units(NCT);
+  static constexpr bool tile_ok(int r, int j) { return r < NCT && j >= r; }
+  // slot of tile (row 2m + r, column j0 + jj) of unit k of wavefront w: tiles in unit order, then
+  // column order, then row order
+  static constexpr int slot(int w, int k, int jj, int r) {
+    int s = 0;
+    for (int kk = 0; kk <= k; ++kk) {
+      const int m = G.u[w][kk][0];
+      if (m < 0) continue;
+      for (int j = G.u[w][kk][1]; j < G.u[w][kk][2]; ++j)
+        for (int rr = 0; rr < 2; ++rr) {
+          if (kk == k && j == G.u[w][k][1] + jj && rr == r) return s;
+          if (tile_ok(2 * m + rr, j)) ++s;
+        }
+    }
+    return -1;
+  }
+  struct Table { int tp[8][32]; };
+  static constexpr Table table() {
+    Table t{};
+    for (int w = 0; w < 8; ++w) {
+      for (int s = 0; s < 32; ++s) t.tp[w][s] = -1;
+      int s = 0;
+      for (int k = 0; k < 2; ++k) {
+        const int m = G.u[w][k][0];
+        if (m < 0) continue;
+        for (int j = G.u[w][k][1]; j < G.u[w][k][2]; ++j)
+          for (int r = 0; r < 2; ++r)
+            if (tile_ok(2 * m + r, j)) t.tp[w][s++] = j * (j + 1) / 2 + 2 * m + r;   // tp = J(J+1)/2 + I
+      }
+    }
+    return t;
+  }
+  static constexpr Table T = table();
+};
+
+template <int I0, class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I0 + I>{}), ...);
+}
+// f(integral_constant<int, i>) for i = B .. E-1
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (E > B) static_for_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
 
 template <int MODE, int NB8M, int RTW = 2>
 struct WideCfg {
@@ -212,50 +279,170 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
     for (int s = 0; s < C::NPW; ++s) gacc[s] = accv_t{0, 0, 0, 0};
     acc_t* gp = (acc_t*)a.gpart + (long)wi.slot * a.gstride;
     for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
-    const uint64_t wkeep = tile_keep_bits(a.tmask, pi.k, w, NW, C::NPW);
+    using GU = GramSched<NCT>;
+    // the unit schedule of the Gram tiles (else the round robin): measured faster for the fp32
+    // instances (SrTiO3-like step 756 -> 669 ms); with bf16 pieces the extra registers it holds in
+    // the block-sparse phase cost more than its operand reuse saves
+    constexpr bool UNITS = GU::ON && MODE == M_F32 && C::NPW <= 32;
+    // tile of this wavefront's Gram slot s (band-tile pair index tp = J(J+1)/2 + I; -1: none)
+    auto slot_tp = [&](int s) -> int {
+      if constexpr (UNITS) return GU::T.tp[w][s];
+      else return w + NW * s;
+    };
+    uint64_t wkeep = 0;
+    if constexpr (UNITS) {
+#pragma unroll
+      for (int s2 = 0; s2 < C::NPW; ++s2) {
+        const int tp = slot_tp(s2);
+        bool keep = tp >= 0 && tp < npt;
+        if (keep && a.tmask) keep = (a.tmask[3 * pi.k + (tp >> 6)] >> (tp & 63)) & 1;
+        if (keep) wkeep |= 1ull << s2;
+      }
+    } else {
+      wkeep = tile_keep_bits(a.tmask, pi.k, w, NW, C::NPW);
+#pragma unroll
+      for (int s2 = 0; s2 < C::NPW; ++s2)
+        if (w + NW * s2 >= npt) wkeep &= ~(1ull << s2);
+    }
 
     // ---- contraction of ROWS staged rows (pitch `pitch`) into this wave's Gram tiles ----
-    auto contract = [&](const lds_t* S, int ng, auto rows_c, int pitch) {
+    // use_units (with UNITS): the unit schedule's operand reuse; else tile by tile in the same
+    // slot order
+    auto contract = [&](const lds_t* S, int ng, auto rows_c, int pitch, auto use_units) {
       constexpr int ROWS = decltype(rows_c)::value;
       // lane-derived addresses from an opaque copy of the lane index: formed afresh per call
       // instead of being hoisted out of the row-block loops and kept live (or spilled)
       int lx = lane;
       asm volatile("" : "+v"(lx));
       const lds_t* Sl = S + (((lx >> 3) & 1) * NP) * NCC * pitch + (lx & 7) * pitch + KPL * (lx >> 4);
+      constexpr int KSN = ROWS / KS;
+      static_assert(KSN % 2 == 0, "steps in pairs");
+      // the operands of each (tile, step) are requested one step ahead, across tiles too: the
+      // last step of a tile requests the first of the next (a tile past the triangle or masked
+      // out reads band tile 0 and skips its products)
+      auto bases = [&](int s, int g, const lds_t*& A_, const lds_t*& B_) {
+        const int tp = slot_tp(s);
+        int I = 0, J = 0;
+        if (tp >= 0 && tp < npt) tp_to_ij(tp, I, J);
+        A_ = Sl + (g * nb8 + I * 8) * pitch;
+        B_ = Sl + (g * nb8 + J * 8) * pitch;
+      };
+      auto ld = [&](const lds_t* A_, const lds_t* B_, int ks, op_t (&a_)[NP], op_t (&b_)[NP]) {
 #pragma unroll
-      for (int s = 0; s < C::NPW; ++s) {
-        const int tp = w + NW * s;
-        if (tp >= npt || !((wkeep >> s) & 1)) continue;
-        int I, J;
-        tp_to_ij(tp, I, J);
-        accv_t acc = gacc[s];
-        for (int g = 0; g < ng; ++g) {
-          const lds_t* SA = Sl + (g * nb8 + I * 8) * pitch;
-          const lds_t* SB = Sl + (g * nb8 + J * 8) * pitch;
-          // operands of step ks + 1 requested before the products of step ks
-          op_t ao[2][NP], bo[2][NP];
-          auto ld = [&](int ks, op_t (&a_)[NP], op_t (&b_)[NP]) {
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-              a_[p] = lds_operand<MODE>(SA + p * NCC * pitch + ks * KS);
-              b_[p] = lds_operand<MODE>(SB + p * NCC * pitch + ks * KS);
-            }
-          };
-          ld(0, ao[0], bo[0]);
-          static_assert((ROWS / KS) % 2 == 0, "steps in pairs");
+        for (int p = 0; p < NP; ++p) {
+          a_[p] = lds_operand<MODE>(A_ + p * NCC * pitch + ks * KS);
+          b_[p] = lds_operand<MODE>(B_ + p * NCC * pitch + ks * KS);
+        }
+      };
+      if constexpr (UNITS && decltype(use_units)::value) {
+        // per 32 rows: each unit's two row operands once, each column operand once for both rows
+        // (the next column's requested before this one's products)
+        auto run = [&](auto wc) {
+          constexpr int W = decltype(wc)::value;
+          for (int g = 0; g < ng; ++g) {
+            const lds_t* Sg = Sl + g * nb8 * pitch;
 #pragma unroll 1
-          for (int ks = 0; ks < ROWS / KS; ks += 2) {
+            for (int ks = 0; ks < KSN; ++ks) {
+              auto opnd = [&](int bt, op_t (&o)[NP]) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              if (ks + u + 1 < ROWS / KS) ld(ks + u + 1, ao[u ^ 1], bo[u ^ 1]);
+                for (int p = 0; p < NP; ++p) o[p] = lds_operand<MODE>(Sg + bt * 8 * pitch + p * NCC * pitch + ks * KS);
+              };
+              static_for<0, 2>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int m = GU::G.u[W][k][0], j0 = GU::G.u[W][k][1], j1 = GU::G.u[W][k][2];
+                if constexpr (m >= 0) {
+                  op_t a0[NP], a1[NP], bb[2][NP];
+                  opnd(2 * m, a0);
+                  if constexpr (2 * m + 1 < NCT) opnd(2 * m + 1, a1);
+                  opnd(j0, bb[0]);
+                  static_for<0, j1 - j0>([&](auto jc) {
+                    constexpr int jj = decltype(jc)::value, j = j0 + jj;
+                    if constexpr (jj + 1 < j1 - j0) opnd(j + 1, bb[(jj + 1) & 1]);
+                    if (j < nbt) {                                          // uniform
+                      static_for<0, 2>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        if constexpr (GU::tile_ok(2 * m + r, j)) {
+                          constexpr int sl = GU::slot(W, k, jj, r);
+                          if ((wkeep >> sl) & 1) {
+                            accv_t acc = gacc[sl];
 #pragma unroll
-              for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
-                acc = mfma(ao[u][NP == 1 ? 0 : prod_a(NP, pr)], bo[u][NP == 1 ? 0 : prod_b(NP, pr)], acc);
+                            for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+                              acc = mfma((r == 0 ? a0 : a1)[NP == 1 ? 0 : prod_a(NP, pr)],
+                                         bb[jj & 1][NP == 1 ? 0 : prod_b(NP, pr)], acc);
+                            gacc[sl] = acc;
+                          }
+                        }
+                      });
+                    }
+                  });
+                }
+              });
             }
           }
+        };
+        switch (w) {
+          case 0: run(std::integral_constant<int, 0>{}); break;
+          case 1: run(std::integral_constant<int, 1>{}); break;
+          case 2: run(std::integral_constant<int, 2>{}); break;
+          case 3: run(std::integral_constant<int, 3>{}); break;
+          case 4: run(std::integral_constant<int, 4>{}); break;
+          case 5: run(std::integral_constant<int, 5>{}); break;
+          case 6: run(std::integral_constant<int, 6>{}); break;
+          default: run(std::integral_constant<int, 7>{}); break;
         }
-        gacc[s] = acc;
-        __builtin_amdgcn_sched_barrier(0);
+        return;
+      }
+      if constexpr (NP == 3) {
+        // six-product mode: one tile at a time (two tiles' operands in flight do not fit)
+#pragma unroll
+        for (int s = 0; s < C::NPW; ++s) {
+          if (!((wkeep >> s) & 1)) continue;
+          accv_t acc = gacc[s];
+          for (int g = 0; g < ng; ++g) {
+            const lds_t *SA, *SB;
+            bases(s, g, SA, SB);
+#pragma unroll 1
+            for (int ks = 0; ks < KSN; ++ks) {
+              op_t ao[NP], bo[NP];
+              ld(SA, SB, ks, ao, bo);
+#pragma unroll
+              for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr) acc = mfma(ao[prod_a(NP, pr)], bo[prod_b(NP, pr)], acc);
+            }
+          }
+          gacc[s] = acc;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+      }
+      for (int g = 0; g < ng; ++g) {
+        op_t ao[2][NP], bo[2][NP];
+        const lds_t *SA, *SB;
+        bases(0, g, SA, SB);
+        ld(SA, SB, 0, ao[0], bo[0]);
+#pragma unroll
+        for (int s = 0; s < C::NPW; ++s) {
+          const bool valid = (wkeep >> s) & 1;                           // uniform
+          const lds_t *nA = SA, *nB = SB;
+          if (s + 1 < C::NPW) bases(s + 1, g, nA, nB);
+          accv_t acc = gacc[s];
+#pragma unroll 1
+          for (int ks = 0; ks < KSN; ks += 2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if (ks + u + 1 < KSN) ld(SA, SB, ks + u + 1, ao[u ^ 1], bo[u ^ 1]);
+              else if (s + 1 < C::NPW) ld(nA, nB, 0, ao[u ^ 1], bo[u ^ 1]);
+              if (valid) {
+#pragma unroll
+                for (int pr = 0; pr < Traits<MODE>::NPROD; ++pr)
+                  acc = mfma(ao[u][NP == 1 ? 0 : prod_a(NP, pr)], bo[u][NP == 1 ? 0 : prod_b(NP, pr)], acc);
+              }
+            }
+          }
+          gacc[s] = acc;
+          SA = nA;
+          SB = nB;
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     };
 
@@ -408,7 +595,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
                 load_coef(ck + 2);
               }
             }
-            contract(Ss, ng, std::integral_constant<int, GR>{}, LDRS);
+            contract(Ss, ng, std::integral_constant<int, GR>{}, LDRS, std::true_type{});
             __syncthreads();
           }
         };
@@ -500,14 +687,18 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
         // next panel is requested in the middle of the current one, once its last product with
         // the Re half has been issued, the Im half at its end: each half has half a panel of
         // products to land in.
+        // A tile that starts at or past N_d reads zeros: its rows may lie past the factor's
+        // padded order, and only the per-lane offset is checked against the buffer's size.
         auto load_u_h = [&](int kc, int h) {
 #pragma unroll
           for (int ii = 0; ii < RT; ++ii) {
-            const long row0 = (long)(r0 + 16 * (w + NW * ii)) * pi.ldu + kc;
+            const int tr = r0 + 16 * (w + NW * ii);
+            const bool live = tr < nd;                    // uniform
+            const long row0 = (long)tr * pi.ldu + kc;
 #pragma unroll
             for (int v = 0; v < UPV; ++v) {
               const long e = MODE == M_F32 ? h * plane + row0 + 4 * v : (h * NP + v) * plane + row0;
-              ucur[ii][h][v] = buf_load<ureg_t>(urs, u_lane, (uint32_t)(e * C::ESZ));
+              ucur[ii][h][v] = buf_load<ureg_t>(urs, live ? u_lane : 0x80000000u, live ? (uint32_t)(e * C::ESZ) : 0u);
             }
           }
         };
@@ -686,7 +877,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
             }
           }
           __syncthreads();
-          contract(Ys, ng, std::integral_constant<int, GS>{}, LDR);
+          contract(Ys, ng, std::integral_constant<int, GS>{}, LDR, std::true_type{});
         }
       }
       // ---- this n'' chunk's Gram tiles into the item's partial slot (stored by the first
@@ -696,8 +887,8 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
       // of every n''
 #pragma unroll
       for (int s = 0; s < C::NPW; ++s) {
-        const int tp = w + NW * s;
-        if (tp < npt) {
+        const int tp = slot_tp(s);
+        if (tp >= 0 && tp < npt) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             acc_t* d = gp + (tp * 4 + i) * 64 + lane;
