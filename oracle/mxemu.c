@@ -25,8 +25,11 @@
  * only the entries j >= i (a Gram matrix whose lower triangle is the mirror).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 static inline float add_rne(float acc, double s) {
   /* acc + s rounded once to binary32 (s is exact in binary64; the sum in binary64
@@ -61,26 +64,58 @@ static inline float instr_bf16(float acc, const float* a, const float* b, int n)
   return acc;
 }
 
-/* kind: 0 = FP32 16x16x4 (chunk 4), 1 = BF16 16x16x32 (chunk 32) */
-void mx_gemm(int kind, int nterm, const float* const* A, const float* const* Bt, int M, int N, int K,
-             const int* kbeg, int upper, float* C) {
-  const int ch = kind == 0 ? 4 : 32;
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int i = 0; i < M; ++i) {
-    const int k0 = kbeg ? kbeg[i] : 0;
-    for (int j = upper ? i : 0; j < N; ++j) {
-      float acc = C[(long)i * N + j];
-      for (int c = k0; c < K; c += ch) {
-        const int n = c + ch <= K ? ch : K - c;
-        for (int t = 0; t < nterm; ++t) {
-          const float* a = A[t] + (long)i * K + c;
-          const float* b = Bt[t] + (long)j * K + c;
-          acc = kind == 0 ? instr_f32(acc, a, b, n) : instr_bf16(acc, a, b, n);
+/* kind: 0 = FP32 16x16x4 (chunk 4), 1 = BF16 16x16x32 (chunk 32). Rows are spread over POSIX
+   threads (MXEMU_THREADS, default: the online processors, at most 64): plain threads, so that no
+   second OpenMP runtime meets the host process's own. */
+typedef struct {
+  int kind, nterm, M, N, K, upper, t, nt;
+  const float* const* A;
+  const float* const* Bt;
+  const int* kbeg;
+  float* C;
+} mx_job;
+
+static void* mx_rows(void* arg) {
+  const mx_job* J = (const mx_job*)arg;
+  const int ch = J->kind == 0 ? 4 : 32;
+  for (int i = J->t; i < J->M; i += J->nt) {
+    const int k0 = J->kbeg ? J->kbeg[i] : 0;
+    for (int j = J->upper ? i : 0; j < J->N; ++j) {
+      float acc = J->C[(long)i * J->N + j];
+      for (int c = k0; c < J->K; c += ch) {
+        const int n = c + ch <= J->K ? ch : J->K - c;
+        for (int t = 0; t < J->nterm; ++t) {
+          const float* a = J->A[t] + (long)i * J->K + c;
+          const float* b = J->Bt[t] + (long)j * J->K + c;
+          acc = J->kind == 0 ? instr_f32(acc, a, b, n) : instr_bf16(acc, a, b, n);
         }
       }
-      C[(long)i * N + j] = acc;
+      J->C[(long)i * J->N + j] = acc;
     }
   }
+  return 0;
+}
+
+void mx_gemm(int kind, int nterm, const float* const* A, const float* const* Bt, int M, int N, int K,
+             const int* kbeg, int upper, float* C) {
+  int nt = (int)sysconf(_SC_NPROCESSORS_ONLN);
+  const char* ev = getenv("MXEMU_THREADS");
+  if (ev && atoi(ev) > 0) nt = atoi(ev);
+  if (nt < 1) nt = 1;
+  if (nt > 64) nt = 64;
+  if (nt > M) nt = M > 0 ? M : 1;
+  mx_job jobs[64];
+  pthread_t th[64];
+  for (int t = 0; t < nt; ++t) {
+    mx_job j = {kind, nterm, M, N, K, upper, t, nt, A, Bt, kbeg, C};
+    jobs[t] = j;
+  }
+  int started = 0;
+  for (int t = 1; t < nt; ++t)
+    if (pthread_create(&th[t], 0, mx_rows, &jobs[t]) == 0) started = t; else break;
+  mx_rows(&jobs[0]);
+  for (int t = 1; t <= started; ++t) pthread_join(th[t], 0);
+  for (int t = started + 1; t < nt; ++t) mx_rows(&jobs[t]);     /* any thread that did not start */
 }
 
 /* One instruction on a single output (the probe cases): acc + sum_k a[k] b[k], n <= chunk. */

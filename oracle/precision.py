@@ -83,10 +83,10 @@ _mx = None
 
 
 def build_mxemu(force: bool = False) -> str:
-    """Compile mxemu.c (gcc, OpenMP) next to this file; returns the library path."""
+    """Compile mxemu.c (gcc, POSIX threads) next to this file; returns the library path."""
     if force or not os.path.exists(_MX_LIB) or os.path.getmtime(_MX_LIB) < os.path.getmtime(_MX_SRC):
         tmp = _MX_LIB + f".{os.getpid()}.tmp"
-        subprocess.run(["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _MX_SRC, "-lm"], check=True)
+        subprocess.run(["gcc", "-O3", "-shared", "-fPIC", "-o", tmp, _MX_SRC, "-lm", "-lpthread"], check=True)
         os.replace(tmp, _MX_LIB)
     return _MX_LIB
 
@@ -291,7 +291,12 @@ def vx_k_emulated(m_blocks, L_list, w_q, mode: str, n_s, plan=None) -> np.ndarra
         raise ValueError(mode)
     ns = [int(n_s)] * len(m_blocks) if np.isscalar(n_s) else [int(x) for x in n_s]
     Y = emulated_rows(m_blocks, L_list, mode, ns)
-    return emulated_gram(Y, w_q, mode, ns, m_blocks[0].shape[0], plan)
+    if not all(np.all(np.isfinite(y)) for y in Y):
+        raise FloatingPointError(f"emulated rows not finite ({mode})")
+    V = emulated_gram(Y, w_q, mode, ns, m_blocks[0].shape[0], plan)
+    if not np.all(np.isfinite(V)):
+        raise FloatingPointError(f"emulated V not finite ({mode}, plan {plan})")
+    return V
 
 
 def normalised_eig_error(V: np.ndarray, V_ref: np.ndarray, rho_max: float) -> float:
