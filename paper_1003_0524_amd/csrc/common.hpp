@@ -152,6 +152,12 @@ __device__ __forceinline__ f4_t mfma(u4_t a, u4_t b, f4_t c) {
                                                    __builtin_bit_cast(bf8_t, b), c, 0, 0, 0);
 }
 
+// x with the sign bits of `mask` flipped (per 32-bit word; bf16 pairs: 0x80008000): a per-lane
+// negation without a branch
+__device__ __forceinline__ float sign_flip(float x, uint32_t mask) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ mask);
+}
+__device__ __forceinline__ u4_t sign_flip(u4_t x, uint32_t mask) { return x ^ mask; }
 __device__ __forceinline__ double negate(double x) { return -x; }
 __device__ __forceinline__ float negate(float x) { return -x; }
 __device__ __forceinline__ u4_t negate(u4_t x) { return x ^ 0x80008000u; }

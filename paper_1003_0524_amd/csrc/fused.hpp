@@ -642,11 +642,14 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             if (r0 + 16 * (w + 4 * ii) < min(kc + KC, nd)) n = ii + 1;
           return n;
         };
+        // tiles past the panel's triangle (or past N_d) read zeros through an out-of-range
+        // per-lane offset: the products below run over every tile with no branch, and theirs add
+        // exact zeros
         auto load_u = [&](int kc, op_t (&u)[RTW][KC / KS][2][NP]) {
           const int na = n_active(kc);
 #pragma unroll
           for (int ii = 0; ii < RTW; ++ii) {
-            if (ii >= na) break;
+            const bool act = ii < na;                     // uniform
             const long row0 = (long)(r0 + 16 * (w + 4 * ii)) * pi.ldu + kc;
 #pragma unroll
             for (int ks = 0; ks < KC / KS; ++ks)
@@ -654,8 +657,9 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
               for (int h = 0; h < (REALF ? 1 : 2); ++h)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
-                  u[ii][ks][h][p] = buf_load<op_t>(urs, u_lane,
-                                                   (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ));
+                  u[ii][ks][h][p] = buf_load<op_t>(
+                      urs, act ? u_lane : 0x80000000u,
+                      act ? (uint32_t)(((h * NP + p) * plane + row0 + ks * KS) * C::ESZ) : 0u);
           }
         };
         const int np = (kend - kc0) / KC;                 // K panels of this row block
@@ -679,6 +683,8 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
             issue_raw(kc + KC, 0);
           }
           const int na = n_active(kc);                // uniform
+          // -Im of the h = 1 operand where no -Im plane is staged: a sign-bit mask, no branch
+          const uint32_t nmask = part == 0 ? (MODE == M_F32 ? 0x80000000u : 0x80008000u) : 0u;
           // [Yr|Yi] += Br [Ar|Ai] + Bi [-Ai|Ar]: the B operand of step (h, j) is plane
           // part (h = 0) or, for h = 1, -Im (part 0) or Re (part 1); one step ahead
 #pragma unroll
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
 #pragma unroll
               for (int p = 0; p < NP; ++p) {
                 b[p] = lds_operand<MODE>(Apl + (pl * NP + p) * APL + (j * 8 + c8) * LDK + kofs);
-                if (!C::NEGP && h == 1 && part == 0) b[p] = negate(b[p]);
+                if (!C::NEGP && h == 1) b[p] = sign_flip(b[p], nmask);
               }
             };
             op_t bA[NP], bB[NP];
@@ -707,7 +713,7 @@ __global__ __launch_bounds__(256, OCC) void fused_kernel(FusedArgs a) {
               for (int pr = 0; pr < C::T::NPROD; ++pr)
 #pragma unroll
                 for (int ii = 0; ii < RTW; ++ii)
-                  if (ii < na)
+                  if (MODE != M_F32 || ii < na)   // (fp32: its cheaper products of zero tiles still cost more)
                     acc[ii][j] = mfma(ucur[ii][ks][h][NP == 1 ? 0 : prod_a(NP, pr)],
                                       bc[NP == 1 ? 0 : prod_b(NP, pr)], acc[ii][j]);
             }

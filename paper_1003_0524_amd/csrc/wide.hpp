@@ -25,11 +25,6 @@
 
 namespace exc {
 
-// x with the sign bits of `mask` flipped (per 32-bit word; bf16 pairs: 0x80008000)
-__device__ __forceinline__ float sign_flip(float x, uint32_t mask) {
-  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ mask);
-}
-__device__ __forceinline__ u4_t sign_flip(u4_t x, uint32_t mask) { return x ^ mask; }
 
 // Gram tile schedule of the wide kernel: the upper triangle of NCT x NCT band tiles is split into
 // units -- a row pair m (band tiles 2m, 2m + 1) times a band-tile range [j0, j1) -- at most two per
