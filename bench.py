@@ -46,6 +46,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6, "bf16x6": 2516.6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "plain": "f64"}
 HBM_PEAK_GBS = 8000.0
 MIXED = ("fp32", "bf16x3", "bf16x6")
+# the FP64 forms are timed over fewer steps when the requested count would take longer than this
+SLOW_FORM_BUDGET_S = 20.0
 WORKLOADS = {
     "c4": "SrTiO3-like simple cubic cell (a = 7.38 bohr), 6x6x6 Gamma-centred q mesh (216 q), 20 irreducible k, "
           "N_MB(q) uniform in [2000, 2600] (1200 multipole-free MT functions in 180 (atom, L, M) channels of "
@@ -161,11 +163,22 @@ class Bench:
         return [o.view(nb, nb).T.cpu().numpy() for o, nb in zip(self.outs, self.cfg.n_bands)]
 
     # one step on resident inputs: V(k) for every k and E_x, both left in device memory
-    def timed(self, ex, steps, warmup, m_in, kernel_timing=False):
+    def timed(self, ex, steps, warmup, m_in, kernel_timing=False, budget_s=None):
+        """Mean ms per step over `steps` steps after `warmup` untimed ones. With `budget_s`, a form whose
+        warm-up step shows that `steps` steps would take longer is timed over fewer (at least 3); the
+        count used is left in `self.last_steps`."""
         torch = self.torch
+        for w in range(max(1, warmup)):
+            t0 = time.perf_counter()
+            ex.matrix_all(m_in, self.outs)
+            ex.energy_device(self.e_dev)
+            torch.cuda.synchronize()
+            t_warm = time.perf_counter() - t0
+        if budget_s is not None and t_warm * steps > budget_s:
+            steps = max(3, int(budget_s / t_warm))
+        self.last_steps = steps
         if kernel_timing:
-            ex.timing(steps)          # re-captures the graph: before the warm-up
-        for _ in range(max(1, warmup)):
+            ex.timing(steps)          # re-captures the graph: one more untimed step after it
             ex.matrix_all(m_in, self.outs)
             ex.energy_device(self.e_dev)
         torch.cuda.synchronize()
@@ -264,12 +277,12 @@ class Bench:
                 ms, energy, per_k = self.timed_streamed(ex, "c128")
                 kt = None
             else:
-                st = max(3, steps // 10) if mode == "plain" else steps
-                ms, energy, kt = self.timed(ex, st, max(1, warmup // 5) if mode == "plain" else warmup, m128,
-                                            kernel_timing=(mode != "plain"))
+                ms, energy, kt = self.timed(ex, steps, warmup, m128, kernel_timing=(mode != "plain"),
+                                            budget_s=SLOW_FORM_BUDGET_S)
             V = self.v_host()
             results[mode] = self.record(ex, ms, init_ms, energy, kt, V, "c128")
             results[mode]["streamed"] = self.streamed
+            results[mode]["steps"] = None if self.streamed else self.last_steps
             ex.close()
             log(f"[bench] {self.name} {mode}: {ms:.3f} ms/step, E_x = {energy:.8f}, error {results[mode]['err_eig_ha']}")
         del m128
@@ -288,6 +301,7 @@ class Bench:
                 V = self.v_host()
                 r = self.record(ex, ms, init_ms, energy, kt, V, "c64" if self.mdt_mixed == "c64" else "c128")
                 r["tune_s"] = round(tune_s, 2)
+                r["steps"] = self.last_steps
                 results[mode] = r
                 ex.close()
                 log(f"[bench] {self.name} {mode}: {ms:.4f} ms/step, main kernel {kt[0]:.4f} ms, config {r['cfg']}"
@@ -339,7 +353,8 @@ class Bench:
                                "err_eig_ha": r["err_eig_ha"], "err_normwise": r["err_norm"],
                                "main_kernel_ms": (round(r["kt"][0], 5) if r["kt"] else None),
                                "init_ms": round(r["init_ms"], 1), "config": r["cfg"], "fused": r["fused"],
-                               "tuned": r["tuned"], "m_streamed_per_k": r.get("streamed", False)}
+                               "tuned": r["tuned"], "m_streamed_per_k": r.get("streamed", False),
+                               "steps": r.get("steps")}
             if "tune_s" in r:
                 out["modes"][m]["tune_s"] = r["tune_s"]
         return head, out
@@ -531,6 +546,8 @@ def main() -> int:
         "batching_factor": summ.get("batching_factor"),
         "precision_factor": summ.get("precision_factor"),
     }
+    if args.workload == "c2" and not args.no_legs and not args.only and head in MIXED:
+        out.update(c2_legs(B, head, H["ms"], args))
     if not args.only:
         for name in [w for w in args.also.split(",") if w and w != args.workload]:
             B2 = Bench(args, torch, lib, synth)
@@ -639,7 +656,8 @@ def c2_legs(B, head, head_ms, args):
             "mode": head, "pairs": n_pairs, "pairs_full_mesh": cfg.n_k * cfg.n_q,
             "ms_per_step": round(ms_e, 5), "main_kernel_ms": round(kt_e[0], 5),
             "sparse_kernel_ms": round(kt_e[1], 5), "config": cfg_e, "fused": fused_e,
-            "items_per_band_chunk": split_e, "kpoints_per_s": round(cfg.n_k / (ms_e * 1e-3), 1),
+            "item_split": {0: "pair", 1: "pair x n'' chunk", 2: "pair x n'' chunk x row part"}.get(split_e, split_e),
+            "kpoints_per_s": round(cfg.n_k / (ms_e * 1e-3), 1),
             "speedup_vs_full_mesh": round(head_ms / ms_e, 3),
             "note": "V(k) summed over EIBZ(k) only; the rotation over the little group LG(k) that completes "
                     "the full sum (done in the LAPW basis) is not included in the time",

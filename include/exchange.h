@@ -314,9 +314,11 @@ void exchange_destroy(exc_ctx *ctx);
  *              exchange_gamma_term; what = 12: its number of terms
  *   what = 13: duration (ms, HIP events) of the product kernel of the last
  *              exchange_back_transform (waits for it)
- *   what = 14: 1 if the fused kernel's work items are (pair, n'' chunk) instead of
- *              pairs (chosen by the autotuner when few (k, q) pairs leave the GPU
- *              short of work), else 0
+ *   what = 14: how the fused kernel's work is split into items: 0 one item per (k, q)
+ *              pair, 1 one per (pair, n'' chunk), 2 one per (pair, n'' chunk, row part)
+ *              -- the block-sparse rows, or one dense row block (what = 19 rows); 1 and 2
+ *              are chosen by the autotuner when few pairs leave the GPU short of work
+ *              (one launch per k: at least 1)
  *   what = 15..18: how the reduced-precision main kernel accumulates the band
  *              contraction in binary32 (for error models; -1 in FP64 and for the
  *              unbatched GEMM form): 15 = band tiles per n'' pass; 16 = chain kind,
@@ -324,6 +326,7 @@ void exchange_destroy(exc_ctx *ctx);
  *              added into the item's binary32 partial, 2: one per n'' pass, added
  *              likewise, 3: a work item per n'' pass and row chunk (unbatched path);
  *              17 / 18 = rows per chunk in the block-sparse / dense rows
+ *   what = 19: rows of a dense row block of the fused kernel (-1 without it)
  *   what = 5, 6, 7: see exchange_timing
  */
 exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);

@@ -167,23 +167,36 @@ def gram_chains(plan: dict, nb: int, n_occ: int, n_s: int, n_mb: int):
 
     plan: kind 0 -- one chain per item; 1 -- one chain per row chunk of a pass, added into
     the item's binary32 partial; 2 -- one chain per pass, added likewise; 3 -- one item (and
-    chain) per pass and row chunk. nct: band tiles per pass; split: one item per pass (else
-    one per pair); rs, rd: rows per chunk in the block-sparse and the dense rows."""
+    chain) per pass and row chunk. nct: band tiles per pass; split: 0 one item per pair, 1 one
+    per pass, 2 one per pass and row part (the block-sparse rows, then dense row blocks of
+    rbm rows); rs, rd: rows per chunk in the block-sparse and the dense rows."""
     ngc = _ngc(nb, n_occ, plan["nct"])
     passes = [list(range(g, min(n_occ, g + ngc))) for g in range(0, n_occ, ngc)]
     chunks = [(r, min(n_s, r + plan["rs"])) for r in range(0, n_s, plan["rs"])]
     chunks += [(r, min(n_mb, r + plan["rd"])) for r in range(n_s, n_mb, plan["rd"])]
     if plan["kind"] == 3:
         return [[[(g, r0, r1) for g in p]] for p in passes for (r0, r1) in chunks]
-    item_passes = [[p] for p in passes] if plan.get("split") else [passes]
+    split = int(plan.get("split", 0))
+    # (passes, row chunks) of each item
+    if split == 2:
+        rbm = int(plan["rbm"])
+        assert rbm % plan["rd"] == 0, "a dense row part holds whole row chunks"
+        parts = [[c for c in chunks if c[0] < n_s]] if n_s > 0 else []
+        for d0 in range(n_s, n_mb, rbm):
+            parts.append([c for c in chunks if d0 <= c[0] < d0 + rbm])
+        work = [([p], part) for p in passes for part in parts]
+    elif split == 1:
+        work = [([p], chunks) for p in passes]
+    else:
+        work = [(passes, chunks)]
     items = []
-    for ps in item_passes:
+    for ps, ch in work:
         if plan["kind"] == 0:
-            items.append([[(g, r0, r1) for p in ps for (r0, r1) in chunks for g in p]])
+            items.append([[(g, r0, r1) for p in ps for (r0, r1) in ch for g in p]])
         elif plan["kind"] == 1:
-            items.append([[(g, r0, r1) for g in p] for p in ps for (r0, r1) in chunks])
+            items.append([[(g, r0, r1) for g in p] for p in ps for (r0, r1) in ch])
         else:
-            items.append([[(g, r0, r1) for (r0, r1) in chunks for g in p] for p in ps])
+            items.append([[(g, r0, r1) for (r0, r1) in ch for g in p] for p in ps])
     return items
 
 

@@ -258,13 +258,13 @@ class Exchange:
 
     def accumulation_plan(self):
         """How the reduced-precision main kernel accumulates the band contraction in
-        binary32 (exchange_query 14-18), as the error model of the tests takes it; None in
+        binary32 (exchange_query 14-19), as the error model of the tests takes it; None in
         FP64 and for the unbatched GEMM form."""
         kind = int(self.query(16))
         if kind < 0:
             return None
-        return {"kind": kind, "nct": int(self.query(15)), "split": bool(self.query(14)),
-                "rs": int(self.query(17)), "rd": int(self.query(18))}
+        return {"kind": kind, "nct": int(self.query(15)), "split": int(self.query(14)),
+                "rs": int(self.query(17)), "rd": int(self.query(18)), "rbm": int(self.query(19))}
 
     # -- API ---------------------------------------------------------------
     def matrix(self, k: int, M, out=None):

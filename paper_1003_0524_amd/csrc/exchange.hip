@@ -222,7 +222,8 @@ struct exc_ctx {
   const FusedKCfg* fcfg = nullptr;    // non-null: reduced-precision HERK through the fused kernel
   bool fused = false;
   bool fused_ok = false;              // the fused kernel can serve this context
-  int fsplit = 0;                     // fused batched items: 1 = one per n'' chunk (more, smaller items)
+  int fsplit = 0;                     // fused items: 1 = one per n'' chunk, 2 = one per n'' chunk and row
+                                      // part (more, smaller items)
   int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
   bool tune_done = false;
   size_t ws_bytes = 0;                // block-sparse workspace of all pairs (the batched graph)
@@ -407,12 +408,24 @@ void release(exc_ctx* c) {
   free_plan(c->bat);
 }
 
-// Relative cost of the fused kernel's work on ncols columns of a pair: the
-// block-sparse rows and their contraction, the triangular dense product, the
-// dense contraction.
-double fused_cost(const exc_ctx* c, const PairInfo& p, int ncols) {
-  const double contract = (double)(c->n_s + p.nd) * p.nb8 * p.nb8;
-  return contract + 4.0 * c->n_s * ncols + (double)p.nd * p.nd * ncols;
+// Dense rows per row block of a fused or wide instance (its row parts when items are
+// split by rows).
+int fused_bm(const FusedKCfg& k) { return k.nt == 512 ? 128 * k.RTW : 64 * k.RTW; }
+
+// Fused row parts of a pair: part 0 = the block-sparse rows, part 1 + j = dense row
+// block j. An item runs parts [rb0, rb1).
+int fused_parts(const exc_ctx* c, const PairInfo& p) {
+  const int bm = fused_bm(*c->fcfg);
+  return 1 + (p.nd + bm - 1) / bm;
+}
+// Relative cost of the fused kernel's work on ncols columns of a pair's row part: the
+// block-sparse rows and their contraction, or a dense row block's triangular product and
+// contraction.
+double fused_part_cost(const exc_ctx* c, const PairInfo& p, int ncols, int part) {
+  const double nb2 = (double)p.nb8 * p.nb8;
+  if (part == 0) return (double)c->n_s * nb2 + 4.0 * c->n_s * ncols;
+  const int bm = fused_bm(*c->fcfg), r0 = (part - 1) * bm, rows = std::min(bm, p.nd - r0);
+  return (double)rows * nb2 + (double)rows * (p.nd - r0) * ncols;
 }
 
 // The fused kernel's chunks of multipole-free rows: whole channels, at most kChunkRows
@@ -473,18 +486,35 @@ exc_status build_plan(exc_ctx* c, Plan& P, int split_rows) {
         w.slot = (int)P.items.size();
         double cs = 0;
         for (int g = g0; g < g1; g += ngc) {
-          if (c->fused) { cs += fused_cost(c, p, std::min(ngc, g1 - g) * p.nb8); continue; }
+          if (c->fused) {
+            for (int rb = rb0; rb < rb1; ++rb) cs += fused_part_cost(c, p, std::min(ngc, g1 - g) * p.nb8, rb);
+            continue;
+          }
           for (int rb = rb0; rb < rb1; ++rb) cs += block_cost(c, p, rb, std::min(ngc, g1 - g) * p.nb8);
         }
         P.items.push_back(w);
         P.slot_w.push_back(c->pair_w[pidx]);     // the pair's weight (w_kq, else w_q)
         cost.push_back(cs);
       };
-      if (!split_rows && !(c->fused && c->fsplit)) {
+      if (c->fused) {
+        // fused items: every row part of the pair (fsplit 0), of one n'' chunk (1), or one
+        // row part of one n'' chunk (2: the block-sparse rows, or one dense row block)
+        // (one launch per k: items per n'' chunk at least)
+        const int nparts = fused_parts(c, p), fs = std::max(c->fsplit, split_rows);
+        if (fs == 0) {
+          push(0, c->n_occ, 0, nparts);
+        } else {
+          for (int g = 0; g < c->n_occ; g += ngc) {
+            const int g1 = std::min(c->n_occ, g + ngc);
+            if (fs == 1) {
+              push(g, g1, 0, nparts);
+              continue;
+            }
+            for (int part = c->n_s > 0 ? 0 : 1; part < nparts; ++part) push(g, g1, part, part + 1);
+          }
+        }
+      } else if (!split_rows) {
         push(0, c->n_occ, 0, nrb);
-      } else if (c->fused) {
-        // the fused kernel runs every row of a column chunk: one item per n'' chunk
-        for (int g = 0; g < c->n_occ; g += ngc) push(g, std::min(c->n_occ, g + ngc), 0, nrb);
       } else {
         for (int g = 0; g < c->n_occ; g += ngc)
           for (int rb = 0; rb < nrb; ++rb) push(g, std::min(c->n_occ, g + ngc), rb, rb + 1);
@@ -1000,6 +1030,10 @@ exc_status autotune(exc_ctx* c, int dtype, hipStream_t st) {
     for (const auto& k : kFused)
       if (fused_fits(k, c->precision, c->nbt_max, c->real_v, dtype) &&
           std::min(c->n_occ, k.NCT / c->nbt_max) < c->n_occ) cands.push_back({&k, 1});
+  // items per n'' chunk and row part where even those leave the CUs short of work
+  if (c->fused_ok && (long)c->pairs.size() * c->n_occ < 4L * n_cu)
+    for (const auto& k : kFused)
+      if (fused_fits(k, c->precision, c->nbt_max, c->real_v, dtype)) cands.push_back({&k, 2});
   const std::string key = tune_key(c, dtype);
   const char* cache = getenv("EXC_TUNE_CACHE");
   if (cache) {
@@ -1467,7 +1501,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
 
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
-  if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = ev[0] == '1';   // (fixed-configuration runs)
+  if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = std::min(2, std::max(0, atoi(ev)));   // (fixed-configuration runs)
   if (c->plain_gemm) {
     // W of the largest pair (laid out as M), the split partials of A^H W, the V(k) accumulator
     std::vector<PairInfo> pp(c->pairs);
@@ -1896,7 +1930,8 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 10: *value = c->fused ? 1.0 : 0.0; return EXC_OK;
     case 11: *value = c->gamma_ms; return EXC_OK;
     case 12: *value = c->gamma_terms; return EXC_OK;
-    case 14: *value = c->fsplit; return EXC_OK;
+    case 14: *value = c->fused && !c->batched ? std::max(c->fsplit, 1) : c->fsplit; return EXC_OK;
+    case 19: *value = c->fused ? fused_bm(*c->fcfg) : -1; return EXC_OK;
     case 15:
     case 16:
     case 17:

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
 
     WorkItem wi = a.items[idx];
     wi.pair = uni(wi.pair); wi.g0 = uni(wi.g0); wi.g1 = uni(wi.g1); wi.ngc = uni(wi.ngc); wi.slot = uni(wi.slot);
+    wi.rb0 = uni(wi.rb0); wi.rb1 = uni(wi.rb1);
     PairInfo pi = a.pairs[wi.pair];
     pi.k = uni(pi.k); pi.nb = uni(pi.nb); pi.nmb = uni(pi.nmb); pi.nd = uni(pi.nd); pi.nb8 = uni(pi.nb8);
     pi.m_off = uni(pi.m_off); pi.u_off = uni(pi.u_off); pi.ldu = uni(pi.ldu);
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
       };
 
       // ================= multipole-free rows (block-sparse), as in fused_kernel =================
-      if (a.n_s > 0) {
+      if (a.n_s > 0 && wi.rb0 == 0) {
         constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, MPC = C::MPC;
         constexpr int LDRS = C::LDRS;
         const int nck = a.n_schunk;
@@ -611,7 +612,9 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
       }
 
       // ================= dense rows: row blocks of BM rows =================
-      for (int r0 = 0; r0 < nd; r0 += BM) {
+      // the item's row parts: [rb0, rb1), part 0 the block-sparse rows, part 1 + j dense row block j
+      const int r_lo = max(wi.rb0 - 1, 0) * BM, r_hi = min(nd, (wi.rb1 - 1) * BM);
+      for (int r0 = r_lo; r0 < r_hi; r0 += BM) {
         accv_t acc[RT][NCT];
 #pragma unroll
         for (int ii = 0; ii < RT; ++ii)

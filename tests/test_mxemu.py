@@ -110,10 +110,11 @@ def test_emulator_is_exact_on_integer_inputs(mode, plan):
 
 
 @pytest.mark.parametrize("kind", [0, 1, 2, 3])
-@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("split", [0, 1, 2])
 def test_gram_chains_cover_each_row_once(kind, split):
     nb, n_occ, n_s, nmb = 20, 7, 70, 200
-    items = pr.gram_chains({"kind": kind, "nct": 6, "split": split, "rs": 64, "rd": 48}, nb, n_occ, n_s, nmb)
+    plan = {"kind": kind, "nct": 6, "split": split, "rs": 64, "rd": 48, "rbm": 96}
+    items = pr.gram_chains(plan, nb, n_occ, n_s, nmb)
     seen = np.zeros((n_occ, nmb), dtype=int)
     for item in items:
         for chain in item:
@@ -122,3 +123,10 @@ def test_gram_chains_cover_each_row_once(kind, split):
     assert np.all(seen == 1)
     if kind == 0:
         assert all(len(item) == 1 for item in items)
+    if split == 2 and kind != 3:
+        # an item per (pass, row part): the block-sparse rows, dense rows [70, 166), [166, 200)
+        n_pass = -(-n_occ // pr._ngc(nb, n_occ, 6))
+        assert len(items) == n_pass * 3
+        spans = sorted({(min(r0 for ch in it for _, r0, _ in ch), max(r1 for ch in it for _, _, r1 in ch))
+                        for it in items})
+        assert spans == [(0, 70), (70, 166), (166, 200)]

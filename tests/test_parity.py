@@ -230,16 +230,20 @@ def test_every_tuner_candidate_matches_oracle(name, precision, monkeypatch):
 
 @pytest.mark.parametrize("precision,cid", [("fp32", 150), ("bf16x3", 161), ("bf16x6", 170)])
 @pytest.mark.parametrize("name", ["small", "ragged"])
-def test_split_items_match_oracle(name, precision, cid, monkeypatch):
-    """Fused work items per (pair, n'' chunk) (the autotuner's candidates for few pairs)."""
+@pytest.mark.parametrize("split", [1, 2])
+def test_split_items_match_oracle(name, precision, cid, split, monkeypatch):
+    """Fused work items per (pair, n'' chunk) (split 1), or per (pair, n'' chunk, row part)
+    (split 2: the block-sparse rows, then each dense row block): the autotuner's candidates
+    for few pairs."""
     cfg = synth.make_config(name)
     nbt = max((nb + 7) // 8 for nb in cfg.n_bands)
     if nbt > 3:
         cid = {"fp32": 121, "bf16x3": 131, "bf16x6": 141}[precision]   # 8 band tiles
     monkeypatch.delenv("EXC_FUSED", raising=False)
     monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
-    monkeypatch.setenv("EXC_FUSED_SPLIT", "1")
+    monkeypatch.setenv("EXC_FUSED_SPLIT", str(split))
     cfg_, Vs = _run_all(name, precision, "herk", True)
+    assert _run_all.plan["split"] == split
     for k in range(cfg.n_k):
         ref = _oracle(name, k)
         pred = pr.normwise_error(_emulated(name, k, precision, _run_all.plan), ref)

@@ -97,15 +97,19 @@ def test_wide_instance_matches_oracle(name, precision, monkeypatch):
         _check(name, precision, Vs, plan, eig=name in ("c3", "c4"))
 
 
-@pytest.mark.parametrize("precision,cid", [("bf16x3", 181), ("fp32", 186)])
-def test_wide_split_items(precision, cid, monkeypatch):
+@pytest.mark.parametrize("name,precision,cid,split", [("ragged", "bf16x3", 181, 1), ("ragged", "fp32", 186, 1),
+                                                       ("ragged", "bf16x3", 181, 2), ("c3", "bf16x3", 181, 2),
+                                                       ("c3", "fp32", 186, 2)])
+def test_wide_split_items(name, precision, cid, split, monkeypatch):
+    """Work items per n'' chunk (split 1) or per n'' chunk and row part (split 2: the block-sparse
+    rows, then each 256-row dense block, every part in its own partial slot)."""
     monkeypatch.delenv("EXC_FUSED", raising=False)
     monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
-    monkeypatch.setenv("EXC_FUSED_SPLIT", "1")
-    print(f"[wide] ragged {precision} {cid} items per n'' chunk", flush=True)
-    Vs, got, plan = _run("ragged", precision)
-    assert got == cid
-    _check("ragged", precision, Vs, plan)
+    monkeypatch.setenv("EXC_FUSED_SPLIT", str(split))
+    print(f"[wide] {name} {precision} {cid} split {split}", flush=True)
+    Vs, got, plan = _run(name, precision)
+    assert got == cid and plan["split"] == split
+    _check(name, precision, Vs, plan, eig=name == "c3")
 
 
 def test_complex128_call_leaves_the_wide_instance(monkeypatch):
