@@ -206,6 +206,7 @@ struct exc_ctx {
   int4* d_rowinfo = nullptr;          // fused kernel: per multipole-free row (see FusedArgs)
   double2* d_coefpad = nullptr;       // fused kernel: padded coefficient runs (see FusedArgs)
   int4* d_schunk = nullptr;           // fused kernel: chunks of whole channels (see FusedArgs)
+  uint2* d_sgroup = nullptr;          // fused kernel: row groups of each chunk (see FusedArgs)
   std::vector<int4> h_schunk;
   int n_schunk = 0;
   int64_t* d_ch_coef = nullptr;
@@ -398,7 +399,7 @@ void release(exc_ctx* c) {
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
-                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_pairs, c->d_pair_w, c->d_pair_begin,
+                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_sgroup, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
                   c->d_gamma, c->d_gpartial, c->d_bt, c->d_tmask, c->d_ppairs, c->d_pw, c->d_pg,
@@ -659,7 +660,7 @@ FusedArgs fused_args(exc_ctx* c, int dtype) {
   f.U = c->d_U;
   f.row_chan = c->d_row_chan; f.ch_off = c->d_ch_off; f.ch_len = c->d_ch_len; f.ch_coef = c->d_ch_coef;
   f.coef = c->d_coef; f.cvec = c->d_cvec; f.rowinfo = c->d_rowinfo; f.coefpad = c->d_coefpad;
-  f.schunk = c->d_schunk; f.n_schunk = c->n_schunk;
+  f.schunk = c->d_schunk; f.n_schunk = c->n_schunk; f.sgroup = c->d_sgroup;
   f.coef_qs = c->nqc > 1 ? c->coef_total : 0;
   f.cvec_qs = c->nqc > 1 ? c->n_s : 0;
   f.pad_qs = c->nqc > 1 ? (int64_t)std::max(1, c->n_schunk) * kChunkRows * kRunPad : 0;
@@ -1300,6 +1301,23 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       c->n_schunk = (int)ck.size();
       if (ck.empty()) ck.push_back(make_int4(0, 0, 0, 0));
       ITRY(upload(c, &c->d_schunk, ck));
+      // row groups of each chunk: its kChunkRows rows (those past the chunk with run length 0)
+      // by decreasing run length, four at a time, {rows (one byte each), longest run}
+      std::vector<uint2> grp((size_t)ck.size() * (kChunkRows / 4));
+      for (size_t k = 0; k < ck.size(); ++k) {
+        std::vector<int> rows(kChunkRows), len(kChunkRows, 0);
+        for (int r = 0; r < kChunkRows; ++r) {
+          rows[r] = r;
+          if (r < ck[k].y) len[r] = ri[ck[k].x + r].y;
+        }
+        std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return len[x] > len[y]; });
+        for (int g = 0; g < kChunkRows / 4; ++g) {
+          uint32_t packed = 0;
+          for (int e = 0; e < 4; ++e) packed |= (uint32_t)rows[4 * g + e] << (8 * e);
+          grp[k * (kChunkRows / 4) + g] = make_uint2(packed, (uint32_t)len[rows[4 * g]]);
+        }
+      }
+      ITRY(upload(c, &c->d_sgroup, grp));
       ITRY(dalloc(c, &c->d_coefpad, (size_t)ck.size() * kChunkRows * kRunPad * c->nqc));
     }
     ITRY(upload(c, &c->d_ch_off, std::vector<int32_t>(c->ch_off.begin(), c->ch_off.end())));

@@ -116,6 +116,9 @@ struct FusedArgs {
   const int4* rowinfo;            // per multipole-free row r of channel c (r = first row + i):
                                   // {index in coef of conj-coefficient run L_c[i..b-1][i], b - i,
                                   //  multipole row n_s + c, 0}
+  const uint2* sgroup;            // per chunk, 16 groups of four of its 64 rows (rows past the chunk
+                                  // with run length 0) by decreasing run length: {rows (one byte
+                                  // each), longest run}
   void* gpart;
   double* dpart;
   int32_t gstride, dstride;

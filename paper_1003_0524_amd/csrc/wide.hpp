@@ -16,8 +16,9 @@
 //  * the factor pieces of the wavefront's rows come from L2 one panel ahead;
 //  * the Gram tiles of an n'' chunk stay in registers (at most 17 per wavefront) and
 //    go to the item's partial slot once per chunk (not once per 64 rows).
-// The block-sparse phase is fused_kernel's (chunks of whole channels, DPP lane
-// shifts), with 32 columns per step (four per wavefront).
+// The block-sparse phase takes fused_kernel's chunks of whole channels, with one
+// column per lane and each row's run of the triangle exactly (no padding to the
+// chunk's longest run), the chunk's values of M staged in LDS.
 #pragma once
 #include "fused.hpp"
 
@@ -119,13 +120,28 @@ struct WideCfg {
   // factor loads per wavefront and panel: each lane takes 8 consecutive k of a row per piece
   // plane (one 16-byte load for bf16 pieces, two for FP32)
   static constexpr int NFL = RT * 2 * (MODE == M_F32 ? 2 : NP);
-  // block-sparse phase
-  static constexpr int GR = 64, CB = 32, CPW = CB / NW, MPC = GR / CPW, MAXT = 12, MAXCK = 64;
-  static constexpr int NCB = (NCC + CB - 1) / CB;
+  // block-sparse phase: a chunk of at most GR rows (whole channels) and its at most MPC
+  // multipole rows; the chunk's M values are staged in LDS, XC columns at a time (all of the
+  // item's columns where they fit beside the Gram stage), rows [GR + MPC] x columns, with an
+  // odd pitch of XP complex64 values
+  static constexpr int GR = 64, MPC = 16, MAXT = 12, MAXCK = 64;
   static constexpr int LDRS = GR + EPV;
-  static constexpr int SP_MP = 0, SP_CF = SP_MP + CB * MPC * 16, SP_ST = SP_CF + MAXT * GR * 16;
-  static constexpr size_t SPARSE_B = (size_t)SP_ST + (size_t)NPL * NCC * LDRS * ESZ;
+  static constexpr size_t SS_B = (size_t)NPL * NCC * LDRS * ESZ;        // Gram stage of a chunk
+  static constexpr size_t SP_TAB = (size_t)MAXT * GR * 16 + 2 * GR * 16 + 256;   // coefficients, row info, l_c, row groups
+  static constexpr size_t xstage_b(int xc) { return ((size_t)(GR + MPC) * (xc + 1) * 8 + 15) / 16 * 16; }
+  static constexpr int XC = SP_TAB + xstage_b(NCC) + SS_B + DACC_B <= BUDGET ? NCC : 64;
+  static constexpr int XP = XC + 1;
+  static constexpr int NU = (XC + 63) / 64;          // 64-column groups of a stage (one column a lane)
+  static constexpr int NSTG = (NCC + XC - 1) / XC;   // stages of a chunk (at most)
+  static constexpr int NDR = (NCC + 63) / 64;        // FP64 |Y|^2 sums per lane
+  static constexpr int XLD = (XC * GR + NT - 1) / NT, XLM = (XC * MPC + NT - 1) / NT;   // loads per thread
+  static constexpr int SP_CF = 0, SP_RI = SP_CF + MAXT * GR * 16, SP_CV = SP_RI + GR * 16, SP_GT = SP_CV + GR * 16;
+  static constexpr int SP_X = SP_GT + 256;
+  static constexpr size_t SP_ST = (size_t)SP_X + xstage_b(XC);
+  static constexpr size_t SPARSE_B = SP_ST + SS_B;
   static_assert(MAXCK == 64, "the LDS budget above reserves 64 chunk descriptors");
+  static_assert(XC % NW == 0 && (XC == NCC || XC % 64 == 0), "whole columns per wavefront; 64-column stages");
+  static_assert(NDR <= 2 && NSTG <= 2, "at most two 64-column groups of a chunk");
   // Gram stage of the dense rows: GS rows at a time (rows contiguous per column)
   static constexpr int GS = (BM >= 128 && (size_t)NPL * NCC * (128 + EPV) * ESZ + DACC_B <= BUDGET) ? 128 : 64;
   static constexpr int LDR = GS + EPV;
@@ -146,7 +162,6 @@ struct WideCfg {
   static_assert(LDS_B <= BUDGET, "wide configuration exceeds the 160 KB of LDS");
   static_assert((size_t)2 * RAW_B + 1024 + PIECE_B + DACC_B <= BUDGET, "at least two raw panels in flight");
   static_assert(KC == 32 && GS % KS == 0 && GR % KS == 0, "whole MFMA steps; 8 k per lane a panel");
-  static_assert(CPW * MPC == 64 && CB % NW == 0, "one multipole block load per wavefront and step");
   static_assert(NCC * (KC / 8) <= NT, "one conversion unit per thread and panel");
 };
 
@@ -451,164 +466,228 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
         return (long)(gbase + g) * nb + n;
       };
 
-      // ================= multipole-free rows (block-sparse), as in fused_kernel =================
+      // ================= multipole-free rows (block-sparse) =================
+      // Per chunk of whole channels (at most GR rows and MPC multipole rows) the item's M values
+      // of the chunk's rows are staged in LDS, XC columns at a time, and each lane takes one
+      // column: a wavefront computes four rows of nearly equal run length at a time, each row r
+      // of channel c as Y_s[r] = l_c[i] A[multipole row of c] + sum_{t < len} conj(L_c[i+t][i])
+      // A[r + t] (the triangle without the padding to the chunk's longest run), its coefficients
+      // read from the chunk's table by every lane at one address, A[r + t] from the stage (one
+      // LDS read per term and column). The FP64 sums of |Y|^2 stay in registers, one per lane and column group. The
+      // next stage's values come to registers while the current one runs; the workgroup meets
+      // twice per stage (stage written, stage read) and once per chunk to contract its rows.
       if (a.n_s > 0 && wi.rb0 == 0) {
-        constexpr int CB = C::CB, CPW = C::CPW, NCB = C::NCB, MAXT = C::MAXT, MPC = C::MPC;
-        constexpr int LDRS = C::LDRS;
+        constexpr int MAXT = C::MAXT, MPC = C::MPC, XC = C::XC, XP = C::XP, NU = C::NU;
+        constexpr int NDR = C::NDR, XLD = C::XLD, XLM = C::XLM, LDRS = C::LDRS;
         const int nck = a.n_schunk;
-        const int ncb = (ncols + CB - 1) / CB;
-        const int nsteps = nck * ncb;
-        double2* Mp = (double2*)(smem + C::SP_MP + w * CPW * MPC * 16);
-        double2* Cf = (double2*)(smem + C::SP_CF);
+        const int nstg = (ncols + XC - 1) / XC;
+        double2* Cf = (double2*)(smem + C::SP_CF);            // [MAXT][GR] coefficient runs of the chunk
+        int4* RI = (int4*)(smem + C::SP_RI);                   // [GR] {run start in coef, run length, multipole row}
+        double2* CV = (double2*)(smem + C::SP_CV);             // [GR] l_c of each row
+        uint2* GT = (uint2*)(smem + C::SP_GT);                 // [GR / 4] row groups of the chunk
+        uint2* Xs = (uint2*)(smem + C::SP_X);                  // [GR + MPC][XP] complex64
         lds_t* Ss = (lds_t*)(smem + C::SP_ST);
-        double dreg[NCB][CPW];
+        double dreg[NDR];
 #pragma unroll
-        for (int b = 0; b < NCB; ++b)
-#pragma unroll
-          for (int j = 0; j < CPW; ++j) dreg[b][j] = 0.0;
-
-        struct RowData { double2 lc; int cs, len, mloc; };
+        for (int d = 0; d < NDR; ++d) dreg[d] = 0.0;
         auto chunk_info = [&](int ck) -> int4 {
           const int4 v = s_chunk[ck];
           return make_int4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
         };
-        auto load_rows = [&](const int4& ci, RowData& d) {
-          d.len = 0; d.cs = 0; d.mloc = 0;
-          d.lc = make_double2(0.0, 0.0);
-          if (lane < ci.y) {
-            const int4 ri = a.rowinfo[ci.x + lane];
-            d.cs = ri.x; d.len = ri.y; d.mloc = ri.z - ci.w;
-            d.lc = a.cvec[pi.q * a.cvec_qs + ci.x + lane];
-          }
-        };
-        constexpr int CFN = MAXT * GR;                  // coefficient table entries (16 B)
+        // the chunk's tables, one chunk ahead in registers: coefficients (all threads), row info
+        // (threads 0 .. GR-1), l_c (threads GR .. 2 GR - 1) and row groups (the next GR / 4)
+        constexpr int CFN = MAXT * GR;
         constexpr int CFL = (CFN + NT - 1) / NT;
         u4_t cfn[CFL];
-        auto load_coef = [&](int ck) {
+        u4_t tabn;
+        auto load_tab = [&](int ck) {
           const u4_t* src = (const u4_t*)(a.coefpad + pi.q * a.pad_qs + (long)ck * MAXT * GR);
 #pragma unroll
           for (int i = 0; i < CFL; ++i)
             if (tid + NT * i < CFN) cfn[i] = src[tid + NT * i];
+          const int4 ci = chunk_info(ck);
+          tabn = u4_t{0u, 0u, 0u, 0u};
+          if (tid < ci.y) {
+            const int4 ri = a.rowinfo[ci.x + tid];
+            tabn = u4_t{(uint32_t)ri.x, (uint32_t)ri.y, (uint32_t)(ri.z - ci.w), 0u};
+          } else if (tid >= GR && tid - GR < ci.y) {
+            tabn = __builtin_bit_cast(u4_t, a.cvec[pi.q * a.cvec_qs + ci.x + tid - GR]);
+          } else if (tid >= 2 * GR && tid < 2 * GR + GR / 4) {
+            const uint2 g = a.sgroup[(long)ck * (GR / 4) + tid - 2 * GR];
+            tabn = u4_t{g.x, g.y, 0u, 0u};
+          }
         };
-        auto store_coef = [&]() {
+        auto store_tab = [&]() {
 #pragma unroll
           for (int i = 0; i < CFL; ++i)
             if (tid + NT * i < CFN) ((u4_t*)Cf)[tid + NT * i] = cfn[i];
+          if (tid < GR) ((u4_t*)RI)[tid] = tabn;
+          else if (tid < 2 * GR) ((u4_t*)CV)[tid - GR] = tabn;
+          else if (tid < 2 * GR + GR / 4) GT[tid - 2 * GR] = make_uint2(tabn[0], tabn[1]);
         };
-        struct StepRegs { uint2 xn[CPW]; uint2 pn; };
-        auto fetch = [&](int st, StepRegs& X) {
-          const int4 ci = chunk_info(st / ncb);
-          const int cb0 = (st % ncb) * CB;
+        // one stage's M values to registers: rows (lane = row, XLD columns per thread) and
+        // multipole rows (16 lanes a column); columns past the item's read zero
+        uint2 xr[XLD], xm[XLM];
+        auto fetch = [&](int ck, int sg) {
+          const int4 ci = chunk_info(ck);
+          const int c0 = sg * XC;
 #pragma unroll
-          for (int j = 0; j < CPW; ++j) {
-            const int c = cb0 + w + NW * j;
+          for (int j = 0; j < XLD; ++j) {
+            const int cl = w + NW * j;                        // stage column
+            const int c = c0 + cl;
             int n = 0;
             const long col = col_index(c, n);
-            const bool ok = c < ncols && n < nb && lane < ci.y;
-            const uint32_t vx = ok ? (uint32_t)((col * pi.nmb + ci.x + lane) * esz) : 0x80000000u;
-            X.xn[j] = buf_load<uint2>(mrs, vx, 0u);
+            const bool ok = cl < XC && c < ncols && n < nb && lane < ci.y;
+            xr[j] = buf_load<uint2>(mrs, ok ? (uint32_t)((col * pi.nmb + ci.x + lane) * esz) : 0x80000000u, 0u);
           }
-          {
-            const int c = cb0 + w + NW * (lane / MPC);
+#pragma unroll
+          for (int j = 0; j < XLM; ++j) {
+            const int e = (w + NW * j) * 64 + lane;
+            const int cl = e / MPC, mr = e % MPC;
+            const int c = c0 + cl;
             int n = 0;
             const long col = col_index(c, n);
-            const bool ok = c < ncols && n < nb;
-            const uint32_t vm = ok ? (uint32_t)((col * pi.nmb + ci.w + lane % MPC) * esz) : 0x80000000u;
-            X.pn = buf_load<uint2>(mrs, vm, 0u);
+            const bool ok = cl < XC && c < ncols && n < nb;
+            xm[j] = buf_load<uint2>(mrs, ok ? (uint32_t)((col * pi.nmb + ci.w + mr) * esz) : 0x80000000u, 0u);
+          }
+        };
+        auto put_stage = [&]() {
+#pragma unroll
+          for (int j = 0; j < XLD; ++j) {
+            const int cl = w + NW * j;
+            if (cl < XC) Xs[lane * XP + cl] = xr[j];
+          }
+#pragma unroll
+          for (int j = 0; j < XLM; ++j) {
+            const int e = (w + NW * j) * 64 + lane;
+            const int cl = e / MPC, mr = e % MPC;
+            if (cl < XC) Xs[(GR + mr) * XP + cl] = xm[j];
           }
         };
         auto to_d2 = [&](uint2 v) -> double2 {
           return make_double2((double)__uint_as_float(v.x), (double)__uint_as_float(v.y));
         };
 
-        __syncthreads();
+        __syncthreads();                                      // earlier users of the LDS are done
         for (int e = tid; e < nck; e += NT) s_chunk[e] = a.schunk[e];
-        load_coef(0);
-        store_coef();
         __syncthreads();
-        int4 ci = chunk_info(0);
-        RowData rd, rd_next;
-        load_rows(ci, rd);
-        rd_next = rd;
-        if (nck > 1) {
-          load_rows(chunk_info(1), rd_next);
-          load_coef(1);
-        }
-        StepRegs SA, SB;
-        fetch(0, SA);
-        if (nsteps > 1) fetch(1, SB);
-
-        auto step = [&](int st, StepRegs& X) {
-          const int cbk = st % ncb, cb0 = cbk * CB;
-          double2 xs[CPW];
+        load_tab(0);
+        store_tab();
+        if (nck > 1) load_tab(1);
+        fetch(0, 0);
+        put_stage();
+        __syncthreads();                                      // first stage and tables visible
+        for (int ck = 0; ck < nck; ++ck) {
+          for (int sg = 0; sg < nstg; ++sg) {
+            // this lane's stage columns (a lane past the stage reads its last column, unused)
+            int xo[NU];
 #pragma unroll
-          for (int j = 0; j < CPW; ++j) xs[j] = to_d2(X.xn[j]);
-          Mp[lane] = to_d2(X.pn);
-          if (st + 2 < nsteps) fetch(st + 2, X);
-          __builtin_amdgcn_wave_barrier();
-          double2 y[CPW];
+            for (int u = 0; u < NU; ++u) xo[u] = min(u * 64 + lane, XC - 1);
+            // the chunk's row groups (four rows of nearly equal run length each; rows past the
+            // chunk have run length 0 and l_c = 0 and store the zeros the contraction reads),
+            // dealt to the wavefronts in snake order; the four rows run together to their longest
+            // run, the shorter ones on zero coefficients
+            constexpr int NG = GR / 4;
+            for (int rd = 0; rd * NW < NG; ++rd) {
+              const uint2 gv = GT[rd * NW + ((rd & 1) ? NW - 1 - w : w)];
+              const uint32_t packed = uni((int)gv.x);
+              const int trip = uni((int)gv.y);
+              int rr[4], len[4];
+              double2 y[4][NU];
 #pragma unroll
-          for (int j = 0; j < CPW; ++j) {
-            const double2 xm = Mp[j * MPC + rd.mloc];
-            y[j].x = rd.lc.x * xm.x - rd.lc.y * xm.y;
-            y[j].y = rd.lc.x * xm.y + rd.lc.y * xm.x;
-          }
-          auto term = [&](const double2 l) {
+              for (int e = 0; e < 4; ++e) {
+                rr[e] = (packed >> (8 * e)) & 0xFF;
+                const int4 ri = RI[rr[e]];
+                len[e] = uni(ri.y);
+                const int mloc = uni(ri.z);
+                const double2 lc = CV[rr[e]];
 #pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-              y[j].x = fma(l.x, xs[j].x, y[j].x);
-              y[j].y = fma(l.x, xs[j].y, y[j].y);
-              y[j].x = fma(l.y, xs[j].y, y[j].x);
-              y[j].y = fma(-l.y, xs[j].x, y[j].y);
-              xs[j] = shift_down1(xs[j]);
-            }
-          };
-          const int Tn = min(ci.z, MAXT);
-          for (int t = 0; t < Tn; ++t) term(Cf[t * GR + lane]);
-          for (int t = MAXT; t < ci.z; ++t)
-            term(t < rd.len ? a.coef[pi.q * a.coef_qs + rd.cs + t] : make_double2(0.0, 0.0));
-#pragma unroll
-          for (int j = 0; j < CPW; ++j) {
-            const int c = cb0 + w + NW * j;
-            if (c < NCC) {
-              put_real<MODE>(Ss + (0 * NP) * NCC * LDRS + c * LDRS + lane, NCC * LDRS, y[j].x);
-              put_real<MODE>(Ss + (1 * NP) * NCC * LDRS + c * LDRS + lane, NCC * LDRS, y[j].y);
-            }
-            const double d = y[j].x * y[j].x + y[j].y * y[j].y;
-#pragma unroll
-            for (int b = 0; b < NCB; ++b)
-              if (b == cbk) dreg[b][j] += d;
-          }
-          if (cbk == ncb - 1) {
-            __syncthreads();
-            const int ck = st / ncb;
-            if (ck + 1 < nck) {
-              store_coef();
-              ci = chunk_info(ck + 1);
-              rd = rd_next;
-              if (ck + 2 < nck) {
-                load_rows(chunk_info(ck + 2), rd_next);
-                load_coef(ck + 2);
+                for (int u = 0; u < NU; ++u) {
+                  const double2 xm_ = to_d2(Xs[(GR + mloc) * XP + xo[u]]);
+                  y[e][u].x = lc.x * xm_.x - lc.y * xm_.y;
+                  y[e][u].y = lc.x * xm_.y + lc.y * xm_.x;
+                }
               }
+              auto term = [&](int e, const double2 l, int row) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                  const double2 x = to_d2(Xs[row * XP + xo[u]]);
+                  y[e][u].x = fma(l.x, x.x, y[e][u].x);
+                  y[e][u].y = fma(l.x, x.y, y[e][u].y);
+                  y[e][u].x = fma(l.y, x.y, y[e][u].x);
+                  y[e][u].y = fma(-l.y, x.x, y[e][u].y);
+                }
+              };
+              // past a row's run its table entries are zero and its rows r + t < GR + MAXT stay in
+              // the stage
+              // per term: the four coefficients and 4 NU values requested together, then the FMAs
+              const int tn = min(trip, MAXT);
+              for (int t = 0; t < tn; ++t) {
+                double2 lv[4];
+                uint2 xv[4][NU];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  lv[e] = Cf[t * GR + rr[e]];
+#pragma unroll
+                  for (int u = 0; u < NU; ++u) xv[e][u] = Xs[(rr[e] + t) * XP + xo[u]];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                  for (int u = 0; u < NU; ++u) {
+                    const double2 x = to_d2(xv[e][u]);
+                    const double2 l = lv[e];
+                    y[e][u].x = fma(l.x, x.x, y[e][u].x);
+                    y[e][u].y = fma(l.x, x.y, y[e][u].y);
+                    y[e][u].x = fma(l.y, x.y, y[e][u].x);
+                    y[e][u].y = fma(-l.y, x.x, y[e][u].y);
+                  }
+              }
+              for (int t = MAXT; t < trip; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const int cs = uni(RI[rr[e]].x);
+                  term(e, t < len[e] ? a.coef[pi.q * a.coef_qs + cs + t] : make_double2(0.0, 0.0),
+                       min(rr[e] + t, GR + MPC - 1));
+                }
+              }
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                  const int cl = u * 64 + lane, c = sg * XC + cl;
+                  if (cl < XC && c < NCC) {
+                    put_real<MODE>(Ss + (0 * NP) * NCC * LDRS + c * LDRS + rr[e], NCC * LDRS, y[e][u].x);
+                    put_real<MODE>(Ss + (1 * NP) * NCC * LDRS + c * LDRS + rr[e], NCC * LDRS, y[e][u].y);
+                    const double d = y[e][u].x * y[e][u].x + y[e][u].y * y[e][u].y;
+#pragma unroll
+                    for (int dd = 0; dd < NDR; ++dd)
+                      if (dd == (sg * XC + u * 64) / 64) dreg[dd] += d;
+                  }
+                }
             }
-            contract(Ss, ng, std::integral_constant<int, GR>{}, LDRS, std::true_type{});
-            __syncthreads();
+            // the next stage's values are requested now and land during the barrier and the
+            // contraction (they are not held in registers during the rows above)
+            const bool more = sg + 1 < nstg || ck + 1 < nck;
+            if (sg + 1 < nstg) fetch(ck, sg + 1);
+            else if (ck + 1 < nck) fetch(ck + 1, 0);
+            __syncthreads();                                  // the stage is read (and the chunk's rows staged)
+            if (sg + 1 == nstg) {
+              if (ck + 1 < nck) {
+                store_tab();                                  // the next chunk's tables
+                if (ck + 2 < nck) load_tab(ck + 2);
+              }
+              contract(Ss, ng, std::integral_constant<int, GR>{}, LDRS, std::true_type{});
+            }
+            if (more) put_stage();
+            __syncthreads();                                  // next stage, tables visible; Gram stage free
           }
-        };
-        for (int st = 0; st < nsteps; st += 2) {
-          step(st, SA);
-          if (st + 1 < nsteps) step(st + 1, SB);
         }
 #pragma unroll
-        for (int b = 0; b < NCB; ++b)
-#pragma unroll
-          for (int j = 0; j < CPW; ++j) {
-            double d = dreg[b][j];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
-            const int c = b * CB + w + NW * j;
-            if (lane == 0 && c < NCC) Dacc[(w * NCC + c) * 2] += d;
-          }
+        for (int dd = 0; dd < NDR; ++dd) {
+          const int c = dd * 64 + lane;
+          if (c < NCC) Dacc[(w * NCC + c) * 2] += dreg[dd];
+        }
       }
 
       // ================= dense rows: row blocks of BM rows =================
