@@ -292,9 +292,9 @@ __global__ __launch_bounds__(512, 1) void wide_kernel(FusedArgs a) {
     for (int e = tid; e < NW * NCC * 2; e += NT) Dacc[e] = 0.0;
     using GU = GramSched<NCT>;
     // the unit schedule of the Gram tiles (else the round robin): measured faster for the fp32
-    // instances (SrTiO3-like step 756 -> 669 ms); with bf16 pieces the extra registers it holds in
-    // the block-sparse phase cost more than its operand reuse saves
-    constexpr bool UNITS = GU::ON && MODE == M_F32 && C::NPW <= 32;
+    // instances (SrTiO3-like step 756 -> 669 ms) and for bf16x3 (262 -> 258 ms); the six-product
+    // mode keeps one tile's operands at a time
+    constexpr bool UNITS = GU::ON && MODE != M_BF16X6 && C::NPW <= 32;
     // tile of this wavefront's Gram slot s (band-tile pair index tp = J(J+1)/2 + I; -1: none)
     auto slot_tp = [&](int s) -> int {
       if constexpr (UNITS) return GU::T.tp[w][s];
