@@ -384,8 +384,13 @@ struct CholArgs {
   int* info;              // [n_q] first failing pivot (1-based), 0 = ok
 };
 
-__global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
+// threads per q of the dense Cholesky (one row of the panel update per thread: more rows in
+// flight hide the latency of their loads)
+constexpr int kCholThreads = 512;
+__global__ __launch_bounds__(kCholThreads) void dense_chol_kernel(CholArgs a) {
+  constexpr int NTC = kCholThreads;
   constexpr int NB = 16, PC = 32;
+  static_assert(PC % 8 == 0, "panel stage: whole groups of eight values");
   __shared__ double2 Lp[NB][PC + 1];
   __shared__ double2 Ld[NB][NB + 1];
   __shared__ int s_fail;
@@ -394,46 +399,58 @@ __global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
   double2* A = a.A + a.a_off[q];
   if (tid == 0) s_fail = 0;
   if (a.schur)
-    for (int c = tid; c < a.n_ch && c < n; c += 256) A[c + (long)c * lda].x -= a.schur[(long)q * a.schur_qs + c];
+    for (int c = tid; c < a.n_ch && c < n; c += NTC) A[c + (long)c * lda].x -= a.schur[(long)q * a.schur_qs + c];
   __syncthreads();
   for (int jb = 0; jb < n; jb += NB) {
     const int nbk = min(NB, n - jb);
     // panel update: A[i][jb+jj] -= sum_{p<jb} A[i][p] conj(A[jb+jj][p]),  i >= jb
-    for (int i0 = jb; i0 < n; i0 += 256) {
+    for (int i0 = jb; i0 < n; i0 += NTC) {
       const int i = i0 + tid;
       double2 acc[NB];
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) acc[jj] = make_double2(0.0, 0.0);
       for (int p0 = 0; p0 < jb; p0 += PC) {
         __syncthreads();
-        for (int e = tid; e < NB * PC; e += 256) {
+        for (int e = tid; e < NB * PC; e += NTC) {
           const int jj = e / PC, pp = e % PC;
           Lp[jj][pp] = (jj < nbk && p0 + pp < jb) ? A[(jb + jj) + (long)(p0 + pp) * lda] : make_double2(0.0, 0.0);
         }
         __syncthreads();
         if (i < n) {
+          // eight values of the row requested together (past the panel's end: zeros, against the
+          // zero-filled stage), then their products
           const int pe = min(PC, jb - p0);
-          for (int pp = 0; pp < pe; ++pp) {
-            const double2 x = A[i + (long)(p0 + pp) * lda];
+          for (int pp0 = 0; pp0 < pe; pp0 += 8) {
+            double2 xv[8];
 #pragma unroll
-            for (int jj = 0; jj < NB; ++jj) {
-              const double2 y = Lp[jj][pp];
-              acc[jj].x += x.x * y.x + x.y * y.y;
-              acc[jj].y += x.y * y.x - x.x * y.y;
+            for (int u = 0; u < 8; ++u)
+              xv[u] = pp0 + u < pe ? A[i + (long)(p0 + pp0 + u) * lda] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const double2 x = xv[u];
+#pragma unroll
+              for (int jj = 0; jj < NB; ++jj) {
+                const double2 y = Lp[jj][pp0 + u];
+                acc[jj].x += x.x * y.x + x.y * y.y;
+                acc[jj].y += x.y * y.x - x.x * y.y;
+              }
             }
           }
         }
       }
       if (i < n) {
-        for (int jj = 0; jj < nbk; ++jj) {
-          double2* t = &A[i + (long)(jb + jj) * lda];
-          t->x -= acc[jj].x; t->y -= acc[jj].y;
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {           // (fixed bound: acc stays in registers)
+          if (jj < nbk) {
+            double2* t = &A[i + (long)(jb + jj) * lda];
+            t->x -= acc[jj].x; t->y -= acc[jj].y;
+          }
         }
       }
     }
     __syncthreads();
     // factor the diagonal block in LDS
-    for (int e = tid; e < NB * NB; e += 256) {
+    for (int e = tid; e < NB * NB; e += NTC) {
       const int r = e % NB, cc = e / NB;
       Ld[r][cc] = (r < nbk && cc < nbk) ? A[(jb + r) + (long)(jb + cc) * lda] : make_double2(0.0, 0.0);
     }
@@ -456,14 +473,18 @@ __global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
       }
     }
     __syncthreads();
-    for (int e = tid; e < nbk * nbk; e += 256) {
+    for (int e = tid; e < nbk * nbk; e += NTC) {
       const int r = e % nbk, cc = e / nbk;
       if (r >= cc) A[(jb + r) + (long)(jb + cc) * lda] = Ld[r][cc];
     }
     // rows below: x Ld^H = a  ->  x_j = (a_j - sum_{m<j} x_m conj(Ld[j][m])) / Ld[j][j]
-    for (int i = jb + nbk + tid; i < n; i += 256) {
+    for (int i = jb + nbk + tid; i < n; i += NTC) {
+      // an index offset of zero the compiler cannot see through: the block's values are read
+      // from LDS per row instead of being hoisted into (spilled) registers for all rows
+      int zb = 0;
+      asm volatile("" : "+v"(zb));
+      const double2* Lz = &Ld[0][0] + zb;
       double2 x[NB];
-#pragma unroll
       for (int j = 0; j < NB; ++j) x[j] = j < nbk ? A[i + (long)(jb + j) * lda] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -472,15 +493,16 @@ __global__ __launch_bounds__(256) void dense_chol_kernel(CholArgs a) {
 #pragma unroll
           for (int m = 0; m < NB; ++m) {
             if (m < j) {
-              t.x -= x[m].x * Ld[j][m].x + x[m].y * Ld[j][m].y;
-              t.y -= x[m].y * Ld[j][m].x - x[m].x * Ld[j][m].y;
+              const double2 l = Lz[j * (NB + 1) + m];
+              t.x -= x[m].x * l.x + x[m].y * l.y;
+              t.y -= x[m].y * l.x - x[m].x * l.y;
             }
           }
-          const double d = Ld[j][j].x;
+          const double d = Lz[j * (NB + 1) + j].x;
           x[j] = make_double2(t.x / d, t.y / d);
+          A[i + (long)(jb + j) * lda] = x[j];       // (stored here: x stays in registers)
         }
       }
-      for (int j = 0; j < nbk; ++j) A[i + (long)(jb + j) * lda] = x[j];
     }
     __syncthreads();
   }

@@ -1373,7 +1373,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
                            c->nqc > 1 ? (int64_t)c->n_s : (int64_t)0);
       CholArgs ca{d_E, d_eoff, d_nd, d_eld, c->n_ch, c->n_ch ? c->d_schur : nullptr,
                   c->nqc > 1 ? c->n_ch : 0, d_info};
-      hipLaunchKernelGGL(dense_chol_kernel, dim3(c->n_q), dim3(256), 0, st, ca);
+      hipLaunchKernelGGL(dense_chol_kernel, dim3(c->n_q), dim3(kCholThreads), 0, st, ca);
     }
     dim3 pg(64, c->n_q);
     const int f = c->form;
