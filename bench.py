@@ -481,6 +481,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-legs", action="store_true", help="skip the widening-row legs on the Si-like workload")
     ap.add_argument("--only", default=None, help="one mode of the headline workload only (profiling runs)")
+    ap.add_argument("--learned", action="store_true",
+                    help="also run the learned extrapolator's 30 outer iterations on the whole ZnO-like workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -516,6 +518,9 @@ def main() -> int:
     head, summ = B.summary(results)
     if head is None:
         head = next((m for m in ("fp64", "plain") if m in results and "ms" in results[m]), None)
+    if head is None:       # no mode met the error target and no FP64 form ran: the fastest one, flagged
+        head = min((m for m in results if "ms" in results[m]), key=lambda m: results[m]["ms"])
+        log(f"[bench] no mode of {args.workload} met the 1e-6 Ha target; reporting {head}")
     H = results[head]
     roof = B.roofline(results, head) if head in MIXED else None
     cpu = None
@@ -561,8 +566,49 @@ def main() -> int:
             if name == "c2" and not args.no_legs and h2 is not None:
                 s2.update(c2_legs(B2, h2, res2[h2]["ms"], args))
             out[name] = s2
+    if args.learned and not args.only:
+        out["learned_c3"] = learned_leg(torch, lib, synth)
     print(json.dumps(out))
     return 0
+
+
+def learned_leg(torch, lib, synth):
+    """The learned extrapolator on the whole ZnO-like workload (21 k x 144 q): 30 synthetic outer
+    iterations, 10 training pairs, the exact FP64 HERK path every 5th iteration as the judge."""
+    import numpy as np
+    import synth.scf as scf
+    from paper_1003_0524_amd import learned
+    cfg = synth.make_config("c3")
+    torch.cuda.empty_cache()
+    E, D, C = synth.coulomb_blocks(cfg)
+    ex = lib.Exchange(cfg.n_bands, cfg.n_pw, cfg.ch_nrad, cfg.n_occ, E, D, C, w_q=cfg.weights_q(),
+                      precision="fp64", form="herk", batched=True)
+    stamps = []
+    try:
+        feed = scf.make_feed_device(cfg, 30, torch.device("cuda"))
+
+        def on_iter(r):
+            torch.cuda.synchronize()
+            stamps.append((r.t, r.exact, time.perf_counter()))
+            log(f"[bench] learned t={r.t} {r.used}" + (f" err {r.err_pred:.3e} stale {r.err_stale:.3e}" if r.judged else ""))
+        xp = learned.Extrapolator(ex, n_blk=cfg.n_bands[0], epochs=1500, epochs_ft=300)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs, xp, _ = learned.run_outer(ex, feed, n_iter=30, tau=1e-4, xp=xp, on_iter=on_iter)
+    finally:
+        ex.close()
+        feed = None
+        torch.cuda.empty_cache()
+    dts = [(e, b - a) for (_, _, a), (_, e, b) in zip([(0, True, t0)] + stamps[:-1], stamps)]
+    judged = [r for r in recs if r.judged]
+    return {"workload": "c3 (all 21 k x 144 q)", "n_blk": cfg.n_bands[0], "iterations": len(recs), "exact": sum(r.exact for r in recs),
+            "predicted": sum(not r.exact for r in recs), "tau_ha": 1e-4,
+            "seconds_total": round(stamps[-1][2] - t0, 3),
+            "seconds_per_predicted_iteration": round(float(np.mean([d for e, d in dts if not e])), 4)
+            if any(not e for e, _ in dts) else None,
+            "judged": [{"t": r.t, "err_pred": r.err_pred, "err_stale": r.err_stale, "err_ridge": r.err_ridge,
+                        "err_pred_block": r.err_pred_block, "err_stale_block": r.err_stale_block,
+                        "accepted": r.accepted} for r in judged]}
 
 
 def c2_legs(B, head, head_ms, args):

@@ -376,7 +376,7 @@ exc_status exchange_timing(exc_ctx *ctx, int32_t n_slots);
 /* exchange_nn_init -- create (or replace) the context's network. Weights are
  * (2u - 1)/sqrt(fan_in) with u the top 53 bits / 2^53 of output number
  * (flat index) of the SplitMix64 stream started at seed; biases 0; Adam state
- * zero. EXC_EINVAL for sizes < 1 or beyond 65536 (hidden: 8192). */
+ * zero. EXC_EINVAL for sizes < 1 or beyond 65536 (hidden: 8192, out: 2^20). */
 exc_status exchange_nn_init(exc_ctx *ctx, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed);
 
 /* exchange_nn_params -- copy the n parameters out (set = 0) or in (set = 1;

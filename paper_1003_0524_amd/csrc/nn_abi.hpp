@@ -161,7 +161,7 @@ extern "C" {
 
 exc_status exchange_nn_init(exc_ctx* c, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed) {
   TRY(check_ctx(c));
-  if (in_dim < 1 || hidden < 1 || out_dim < 1 || in_dim > 65536 || hidden > 8192 || out_dim > 65536)
+  if (in_dim < 1 || hidden < 1 || out_dim < 1 || in_dim > 65536 || hidden > 8192 || out_dim > (1 << 20))
     return fail(c, EXC_EINVAL, "network sizes out of range (in %d, hidden %d, out %d)", in_dim, hidden, out_dim);
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipDeviceSynchronize());

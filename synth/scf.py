@@ -112,3 +112,40 @@ def make_feed(cfg: Config, n_iter: int, device, a0: float = 0.1, seed: int = 0):
         return Ms, P
 
     return feed
+
+
+def make_feed_device(cfg: Config, n_iter: int, device, a0: float = 0.1, seed: int = 0, dtype: str = "c64"):
+    """``make_feed`` for whole workloads: M_ref drawn on the GPU by the seeded generator
+    (the reference configuration's blocks, n_b reference bands in n''), and M_t(k, q) =
+    U_t(k')^H M_ref(k, q) formed on the GPU per pair into buffers reused across the
+    iterations (a complex product of (n_occ x n_b) by (n_b x n_b N_MB)). Returns feed(t) as
+    ``make_feed`` does; the M_t tensors of one call are overwritten by the next."""
+    import torch
+
+    from . import m_all_device
+
+    dev = torch.device(device)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    Us = occupied_sequence(cfg, n_iter, a0=a0, seed=seed)
+    rcfg = reference_config(cfg)
+    nb, no = cfg.n_bands[0], cfg.n_occ
+    mref = [m_all_device(rcfg, k, dtype, dev) for k in range(cfg.n_k)]
+    outs = [torch.empty(sum(no * nb * cfg.n_mb(q) for q in range(cfg.n_q)), dtype=tdt, device=dev)
+            for _ in range(cfg.n_k)]
+
+    def feed(t: int):
+        U = Us[t - 1]
+        Uh = [torch.from_numpy(np.ascontiguousarray(u.conj().T)).to(dev, tdt) for u in U]
+        for k in range(cfg.n_k):
+            o_ref = o_out = 0
+            for q in range(cfg.n_q):
+                nmb = cfg.n_mb(q)
+                src = mref[k][o_ref:o_ref + nb * nb * nmb].view(nb, nb * nmb)
+                dst = outs[k][o_out:o_out + no * nb * nmb].view(no, nb * nmb)
+                torch.matmul(Uh[k_prime(cfg, k, q)], src, out=dst)
+                o_ref += nb * nb * nmb
+                o_out += no * nb * nmb
+        P = torch.from_numpy(density_vector(density(U))).to(dev)
+        return outs, P
+
+    return feed
