@@ -8,7 +8,8 @@ Bars as in test_parity: normwise error within 4x the error model's prediction fo
 context's accumulation (plus 1e-12); on the full shapes also the normalised eigenvalue error
 <= 1e-6 Ha; Hermitian mirror and real diagonal exact. Work items per n'' chunk, and a
 complex128 call on a context fixed to a wide instance (which switches to an instance
-that reads complex128), are covered too.
+that reads complex128), are covered too, and so are the fused instances for up to eight band
+tiles at the ZnO-like shapes.
 """
 import functools
 import sys
@@ -120,3 +121,16 @@ def test_complex128_call_leaves_the_wide_instance(monkeypatch):
     Vs, got, plan = _run("small", "bf16x3", dt=np.complex128)
     assert got != 181
     _check("small", "bf16x3", Vs, plan)
+
+
+@pytest.mark.parametrize("cid", [162, 131])
+def test_fused_eight_band_tile_instances_on_the_zno_like_slice(cid, monkeypatch):
+    """The fused instances for up to 8 band tiles (162: two workgroups per CU; 131: one) at the
+    ZnO-like workload's full per-pair shapes (60 bands, N_MB up to 1399), complex64 M."""
+    monkeypatch.delenv("EXC_FUSED", raising=False)
+    monkeypatch.delenv("EXC_FUSED_SPLIT", raising=False)
+    monkeypatch.setenv("EXC_FUSED_CFG", str(cid))
+    print(f"[wide] c3 bf16x3 fused instance {cid}", flush=True)
+    Vs, got, plan = _run("c3", "bf16x3")
+    assert got == cid
+    _check("c3", "bf16x3", Vs, plan, eig=True)
