@@ -22,8 +22,13 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 //   HERK form: Y_c = L_c^H A_c + l_c a_{j(c)}   (rows of L^H A for v = L L^H)
 //   GEMM form: W_c = D_c A_c + C_c a_{j(c)},  X_c = C_c^H A_c (added to W row j(c))
 // One wavefront per column (k, q, n'', n): the column's MT and multipole rows
-// are staged in LDS with coalesced 16-byte loads, every row is computed in FP64
-// and written once, so the kernel is bound by HBM bandwidth. Output: double2
+// are staged in LDS with coalesced loads, eight in flight per lane, every row is
+// computed in FP64 and written once, so the kernel is bound by HBM bandwidth. In
+// the HERK form a workgroup is that one wavefront (no barrier ties columns
+// together, and the LDS of a workgroup is one column), and the row r = first + i
+// of channel c reads its coefficient run L_c[i..b-1][i] eight values per round of
+// loads from a copy of the runs stored entry by entry, so that the lanes of a
+// round (consecutive rows) read consecutive addresses. Output: double2
 // rows (FP64 mode), or (reduced-precision modes) the whole column packed into
 // the tile kernel's split planes [plane][row]: the sparse rows Y_s followed by
 // the dense rows of M, each part zero padded (this is also the conversion of M
@@ -41,52 +46,115 @@ struct SparseArgs {
   const int64_t* ch_coef;    // [n_ch] offset of the channel's square block in coef
   const double2* coef;       // HERK: L_c (lower, col-major); GEMM: D_c (col-major)
   const double2* cvec;       // [n_s] HERK: l_c = L_c^{-1} C_c; GEMM: C_c
+  const int4* rowinfo;       // [n_s] HERK: {start of the row's run in coef, run length b - i,
+                             //  multipole row n_s + c, 0}
+  const double2* runs;       // HERK: [run_max][runs_ld] entry t of row r's run conj-coefficients
+  int32_t run_max, runs_ld;  //  L_c[i + t][i] at runs[t * runs_ld + r] (zero past the run)
+  int64_t runs_qs;           //  elements between the copies of q and q + 1 (0: one copy)
   int64_t coef_qs, cvec_qs;  // elements between the copies of q and q + 1 (0: one copy for all q)
   void* ws;                  // output rows
   double* dsp;               // HERK, reduced precision: sum_r |Y_s[r][n]|^2 per column
 };
 
+// The column's nrow multipole-free and multipole rows to S: eight loads per lane
+// issued before the first LDS write (the last row stands in for rows past the end).
+__device__ __forceinline__ void stage_column(double2* S, const char* mb, long mcol, int nrow, int m_c64,
+                                             int lane) {
+  for (int r0 = 0; r0 < nrow; r0 += 8 * 64) {
+    double2 v[8];
+    if (m_c64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float2 f = ((const float2*)mb)[mcol + min(r0 + u * 64 + lane, nrow - 1)];
+        v[u] = make_double2(f.x, f.y);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ((const double2*)mb)[mcol + min(r0 + u * 64 + lane, nrow - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u * 64 + lane < nrow) S[r0 + u * 64 + lane] = v[u];
+  }
+}
+
+// HERK row r: Y_s[r] = sum_{t < len} conj(L_c[i + t][i]) A[r + t] + l_c[i] A[multipole row of c],
+// with ri = rowinfo[r] (len = ri.y, multipole row ri.z), cv = l_c[i] and run = the row's
+// entries of the runs table (stride ld, rmax entries). Every round issues its eight loads
+// unconditionally (indices clamped into the table and the run), the terms past the run add zero.
+__device__ __forceinline__ double2 herk_row(const double2* S, const double2* run, long ld, int rmax, int4 ri,
+                                            double2 cv, int r) {
+  double2 y = make_double2(0.0, 0.0);
+  for (int t0 = 0; t0 < ri.y; t0 += 8) {
+    double2 cf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cf[u] = run[min(t0 + u, rmax - 1) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = t0 + u < ri.y;
+      const double2 c = make_double2(in ? cf[u].x : 0.0, in ? cf[u].y : 0.0);
+      y = cadd(y, cmulc(c, S[r + min(t0 + u, ri.y - 1)]));
+    }
+  }
+  return cadd(y, cmul(cv, S[ri.z]));
+}
+
+// Y_s of the whole column (rows [0, nr), zero from n_s on), one row per lane per round;
+// the next round's row descriptors are requested before this round's coefficient runs.
+template <typename Put>
+__device__ __forceinline__ void herk_rows(const double2* S, const SparseArgs& a, const double2* runs,
+                                          const double2* cvec, int nr, int lane, Put put) {
+  const int n_s = a.n_s;
+  int4 ri = make_int4(0, 1, 0, 0);
+  double2 cv = make_double2(0.0, 0.0);
+  if (lane < n_s) { ri = a.rowinfo[lane]; cv = cvec[lane]; }
+  for (int r = lane; r < nr; r += 64) {
+    int4 rn = make_int4(0, 1, 0, 0);
+    double2 cn = make_double2(0.0, 0.0);
+    if (r + 64 < n_s) { rn = a.rowinfo[r + 64]; cn = cvec[r + 64]; }
+    put(r, r < n_s ? herk_row(S, runs + r, a.runs_ld, a.run_max, ri, cv, r) : make_double2(0.0, 0.0));
+    ri = rn;
+    cv = cn;
+  }
+}
+
 template <int FORM, int MODE>
 __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
-  extern __shared__ double2 scol[];          // [4 waves][n_s + n_ch]
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  extern __shared__ double2 scol[];          // HERK: [n_s + n_ch]; GEMM: [4 waves][n_s + n_ch]
+  const int w = FORM == 1 ? 0 : threadIdx.x >> 6, lane = threadIdx.x & 63;
   const PairInfo pi = a.pairs[blockIdx.y];
   const double2* coef = a.coef + pi.q * a.coef_qs;      // this q's channel blocks
   const double2* cvec = a.cvec + pi.q * a.cvec_qs;
-  const int col = blockIdx.x * 4 + w;
+  const double2* runs = a.runs + pi.q * a.runs_qs;      // (HERK)
+  const int col = FORM == 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + w;
   const bool active = col < a.n_occ * pi.nb;
   const int nrow = a.n_s + a.n_ch;
   double2* S = scol + (long)w * nrow;
-  if (active) {
-    const long mcol = pi.m_off + (long)col * pi.nmb;
-    const char* mb = (const char*)a.mtab[pi.k];
-    for (int r = lane; r < nrow; r += 64) {
-      if (a.m_c64) {
-        const float2 v = ((const float2*)mb)[mcol + r];
-        S[r] = make_double2(v.x, v.y);
-      } else {
-        S[r] = ((const double2*)mb)[mcol + r];
-      }
-    }
+  if (FORM == 1 && !active) return;
+  if (active && nrow > 0)
+    stage_column(S, (const char*)a.mtab[pi.k], pi.m_off + (long)col * pi.nmb, nrow, a.m_c64, lane);
+  if constexpr (FORM == 1) {
+    // LDS operations of one wavefront take effect in order: the rows just written are
+    // read below by other lanes of the same wavefront
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+    if (!active) return;                     // whole wavefronts leave; no barrier follows
   }
-  __syncthreads();
-  if (!active) return;                       // whole wavefronts leave; no barrier follows
   double dsum = 0.0;
   if constexpr (MODE == M_F64) {
     const long wcol = pi.ws_off + (long)col * pi.ldw;
     double2* out = (double2*)a.ws;
-    for (int r = lane; r < a.n_s; r += 64) {
-      const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-      const double2* cf = coef + a.ch_coef[c];
-      double2 y = make_double2(0.0, 0.0);
-      if (FORM == 1) {
-        for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
-      } else {
+    if constexpr (FORM == 1) {
+      herk_rows(S, a, runs, cvec, a.n_s, lane, [&](int r, double2 y) { out[wcol + r] = y; });
+    } else {
+      for (int r = lane; r < a.n_s; r += 64) {
+        const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
+        const double2* cf = coef + a.ch_coef[c];
+        double2 y = make_double2(0.0, 0.0);
         for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], S[s + j]));
+        out[wcol + r] = cadd(y, cmul(cvec[r], S[a.n_s + c]));
       }
-      out[wcol + r] = cadd(y, cmul(cvec[r], S[a.n_s + c]));
-    }
-    if (FORM == 0) {
       for (int c = lane; c < a.n_ch; c += 64) {
         const int s = a.ch_off[c], b = a.ch_len[c];
         double2 x = make_double2(0.0, 0.0);
@@ -101,18 +169,11 @@ __global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
     using lds_t = typename Traits<MODE>::lds_t;
     constexpr int NP = Traits<MODE>::NPIECE;
     lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
-    for (int r = lane; r < a.ns_pad; r += 64) {
-      double2 y = make_double2(0.0, 0.0);
-      if (r < a.n_s) {
-        const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-        const double2* cf = coef + a.ch_coef[c];
-        for (int j = i; j < b; ++j) y = cadd(y, cmulc(cf[j + (long)i * b], S[s + j]));
-        y = cadd(y, cmul(cvec[r], S[a.n_s + c]));
-        dsum += y.x * y.x + y.y * y.y;
-      }
+    herk_rows(S, a, runs, cvec, a.ns_pad, lane, [&](int r, double2 y) {
+      dsum += y.x * y.x + y.y * y.y;
       put_real<MODE>(out + r, pi.ldw, y.x);
       put_real<MODE>(out + (long)NP * pi.ldw + r, pi.ldw, y.y);
-    }
+    });
     const long mcol = pi.m_off + (long)col * pi.nmb + a.n_s;
     const char* mb = (const char*)a.mtab[pi.k];
     for (int d = lane; d < pi.ldw - a.ns_pad; d += 64) {
@@ -564,6 +625,24 @@ __global__ __launch_bounds__(256) void pad_runs_kernel(const double2* coef, cons
   double2 v = make_double2(0.0, 0.0);
   if (rr < ci.y) {
     const int4 ri = rowinfo[ci.x + rr];
+    if (t < ri.y) v = coef[ri.x + t];
+  }
+  out[e] = v;
+}
+
+// sparse_kernel's copy of the factored channel coefficients: out[t][r] (row stride ld) =
+// L_c[i+t][i] for the multipole-free row r (entry i of channel c) and t < b - i, zero beyond
+// and for the padding rows r >= n_s. blockIdx.y: the copy of the channel blocks.
+__global__ __launch_bounds__(256) void runs_by_row_kernel(const double2* coef, const int4* rowinfo, int n_s,
+                                                          int rmax, int ld, double2* out, int64_t coef_qs) {
+  coef += blockIdx.y * coef_qs;
+  out += (long)blockIdx.y * rmax * ld;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)rmax * ld) return;
+  const int r = (int)(e % ld), t = (int)(e / ld);
+  double2 v = make_double2(0.0, 0.0);
+  if (r < n_s) {
+    const int4 ri = rowinfo[r];
     if (t < ri.y) v = coef[ri.x + t];
   }
   out[e] = v;

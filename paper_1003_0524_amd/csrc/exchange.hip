@@ -209,6 +209,8 @@ struct exc_ctx {
   std::vector<int> ldu;
   int32_t *d_row_chan = nullptr, *d_ch_off = nullptr, *d_ch_len = nullptr;
   int4* d_rowinfo = nullptr;          // fused kernel: per multipole-free row (see FusedArgs)
+  double2* d_runs = nullptr;          // HERK sparse_kernel: coefficient runs by row (see SparseArgs)
+  int run_max = 0, runs_ld = 0;       //  longest run, rows per run entry (n_s rounded up to 8)
   double2* d_coefpad = nullptr;       // fused kernel: padded coefficient runs (see FusedArgs)
   int4* d_schunk = nullptr;           // fused kernel: chunks of whole channels (see FusedArgs)
   uint2* d_sgroup = nullptr;          // fused kernel: row groups of each chunk (see FusedArgs)
@@ -404,7 +406,7 @@ void release(exc_ctx* c) {
   c->ev_in = c->ev_out = nullptr;
   c->own = nullptr;
   void* ptrs[] = {c->d_coef, c->d_cvec, c->d_schur, c->d_U, c->d_row_chan, c->d_ch_off,
-                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_coefpad, c->d_schunk, c->d_sgroup, c->d_pairs, c->d_pair_w, c->d_pair_begin,
+                  c->d_ch_len, c->d_ch_coef, c->d_rowinfo, c->d_runs, c->d_coefpad, c->d_schunk, c->d_sgroup, c->d_pairs, c->d_pair_w, c->d_pair_begin,
                   c->d_ws, c->d_dsp, c->d_gpart, c->d_dpart, c->d_vres, c->d_voff, c->d_knb,
                   c->d_mtab, c->d_vtab, c->d_counter, c->d_mstage, c->d_eout, c->d_ewk, c->d_erho,
                   c->d_gamma, c->d_gpartial, c->d_bt, c->d_tmask, c->d_ppairs, c->d_pw, c->d_pg,
@@ -649,7 +651,9 @@ SparseArgs sparse_args(exc_ctx* c, int dtype, int k) {
   s.m_c64 = dtype == EXC_C64;
   s.n_s = c->n_s; s.n_ch = c->n_ch; s.n_occ = c->n_occ; s.nb_max = c->nb_max; s.ns_pad = c->ns_pad;
   s.row_chan = c->d_row_chan; s.ch_off = c->d_ch_off; s.ch_len = c->d_ch_len;
-  s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec;
+  s.ch_coef = c->d_ch_coef; s.coef = c->d_coef; s.cvec = c->d_cvec; s.rowinfo = c->d_rowinfo;
+  s.runs = c->d_runs; s.run_max = c->run_max; s.runs_ld = c->runs_ld;
+  s.runs_qs = c->nqc > 1 ? (int64_t)c->run_max * c->runs_ld : 0;
   s.coef_qs = c->nqc > 1 ? c->coef_total : 0;
   s.cvec_qs = c->nqc > 1 ? c->n_s : 0;
   s.ws = ws_base(c, k); s.dsp = c->sv ? c->sv->dsp : c->d_dsp;
@@ -707,7 +711,11 @@ hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGrap
   return hipGraphAddKernelNode(out, g, dep, dep ? 1 : 0, &p);
 }
 
-size_t sparse_lds_bytes(const exc_ctx* c) { return (size_t)4 * (c->n_s + c->n_ch) * sizeof(double2); }
+// sparse_kernel: one column per workgroup in the HERK form, four in the GEMM form
+bool sparse_herk(const exc_ctx* c) { return c->form == EXC_FORM_CHOL_HERK; }
+size_t sparse_lds_bytes(const exc_ctx* c) {
+  return (size_t)(sparse_herk(c) ? 1 : 4) * (c->n_s + c->n_ch) * sizeof(double2);
+}
 
 const void* sparse_fn(const exc_ctx* c) {
   if (c->form != EXC_FORM_CHOL_HERK) return (const void*)sparse_kernel<0, M_F64>;
@@ -729,8 +737,9 @@ bool cfg_sparse(exc_ctx* c, int dtype, int k, int pair0, int npairs, SparseArgs&
   s.pairs = c->d_pairs + pair0;
   // dsp is indexed by blockIdx.y: offset it to the first pair
   s.dsp = s.dsp ? s.dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
-  L.grid = dim3((c->n_occ * c->nb_max + 3) / 4, npairs);
-  L.block = dim3(256);
+  const int ncol = c->n_occ * c->nb_max;
+  L.grid = sparse_herk(c) ? dim3(ncol, npairs) : dim3((ncol + 3) / 4, npairs);
+  L.block = dim3(sparse_herk(c) ? 64 : 256);
   L.shmem = sparse_lds_bytes(c);
   L.fn = sparse_fn(c);
   L.arg = &s;
@@ -1302,6 +1311,11 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
         ri[r] = make_int4((int)(c->ch_coef[ch] + (int64_t)i * b + i), b - i, c->n_s + ch, 0);
       }
       ITRY(upload(c, &c->d_rowinfo, ri));
+      if (c->form == EXC_FORM_CHOL_HERK && c->n_s > 0) {
+        c->run_max = *std::max_element(c->ch_len.begin(), c->ch_len.end());
+        c->runs_ld = (c->n_s + 7) / 8 * 8;
+        ITRY(dalloc(c, &c->d_runs, (size_t)c->run_max * c->runs_ld * c->nqc));
+      }
       std::vector<int4> ck = c->h_schunk;
       c->n_schunk = (int)ck.size();
       if (ck.empty()) ck.push_back(make_int4(0, 0, 0, 0));
@@ -1409,6 +1423,13 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
       hipLaunchKernelGGL(pad_runs_kernel, dim3((unsigned)((ne + 255) / 256), c->nqc), dim3(256), 0, st, c->d_coef,
                          c->d_rowinfo, c->d_schunk, c->n_schunk, kRunPad, kChunkRows, c->d_coefpad,
                          c->nqc > 1 ? c->coef_total : (int64_t)0);
+      if (c->d_runs) {
+        // sparse_kernel's runs of the factored channel coefficients, row by row
+        const long nr = (long)c->run_max * c->runs_ld;
+        hipLaunchKernelGGL(runs_by_row_kernel, dim3((unsigned)((nr + 255) / 256), c->nqc), dim3(256), 0, st,
+                           c->d_coef, c->d_rowinfo, c->n_s, c->run_max, c->runs_ld, c->d_runs,
+                           c->nqc > 1 ? c->coef_total : (int64_t)0);
+      }
       IHIP(hipGetLastError());
       IHIP(hipStreamSynchronize(st));
     }
