@@ -21,14 +21,15 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 // channel and to the channel's multipole function.
 //   HERK form: Y_c = L_c^H A_c + l_c a_{j(c)}   (rows of L^H A for v = L L^H)
 //   GEMM form: W_c = D_c A_c + C_c a_{j(c)},  X_c = C_c^H A_c (added to W row j(c))
-// One wavefront per column (k, q, n'', n): the column's MT and multipole rows
-// are staged in LDS with coalesced loads, eight in flight per lane, every row is
-// computed in FP64 and written once, so the kernel is bound by HBM bandwidth. In
-// the HERK form a workgroup is that one wavefront (no barrier ties columns
-// together, and the LDS of a workgroup is one column), and the row r = first + i
-// of channel c reads its coefficient run L_c[i..b-1][i] eight values per round of
-// loads from a copy of the runs stored entry by entry, so that the lanes of a
-// round (consecutive rows) read consecutive addresses. Output: double2
+// The MT and multipole rows of a column (k, q, n'', n) are staged in LDS with
+// coalesced loads, every row is computed in FP64 and written once, so the kernel
+// is bound by HBM bandwidth. GEMM form: one wavefront per column, four per
+// workgroup. HERK form: a workgroup is one wavefront that takes NCW columns of a
+// pair at once (their loads all in flight together, no barrier), and the row
+// r = first + i of channel c reads its coefficient run L_c[i..b-1][i] once for
+// the NCW columns, eight values per round of loads, from a copy of the runs
+// stored entry by entry (the lanes of a round, consecutive rows, read
+// consecutive addresses). Output: double2
 // rows (FP64 mode), or (reduced-precision modes) the whole column packed into
 // the tile kernel's split planes [plane][row]: the sparse rows Y_s followed by
 // the dense rows of M, each part zero padded (this is also the conversion of M
@@ -78,119 +79,165 @@ __device__ __forceinline__ void stage_column(double2* S, const char* mb, long mc
   }
 }
 
-// HERK row r: Y_s[r] = sum_{t < len} conj(L_c[i + t][i]) A[r + t] + l_c[i] A[multipole row of c],
-// with ri = rowinfo[r] (len = ri.y, multipole row ri.z), cv = l_c[i] and run = the row's
-// entries of the runs table (stride ld, rmax entries). Every round issues its eight loads
-// unconditionally (indices clamped into the table and the run), the terms past the run add zero.
-__device__ __forceinline__ double2 herk_row(const double2* S, const double2* run, long ld, int rmax, int4 ri,
-                                            double2 cv, int r) {
-  double2 y = make_double2(0.0, 0.0);
-  for (int t0 = 0; t0 < ri.y; t0 += 8) {
-    double2 cf[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cf[u] = run[min(t0 + u, rmax - 1) * ld];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const bool in = t0 + u < ri.y;
-      const double2 c = make_double2(in ? cf[u].x : 0.0, in ? cf[u].y : 0.0);
-      y = cadd(y, cmulc(c, S[r + min(t0 + u, ri.y - 1)]));
+// HERK form: NCW columns (k, q, n'', n), n'' n consecutive, of one pair per single-wavefront
+// workgroup. The columns' rows go to LDS (complex128 M: straight from HBM, every load of
+// every column in flight at once; complex64 M: through registers), then each round of
+// 64 rows reads its coefficient runs once for all NCW columns.
+template <int MODE, int NCW>
+__device__ __forceinline__ void herk_columns(const SparseArgs& a, double2* scol) {
+  const int lane = threadIdx.x;
+  const PairInfo pi = a.pairs[blockIdx.y];
+  const int ncol = a.n_occ * pi.nb, c0 = (int)blockIdx.x * NCW;
+  if (c0 >= ncol) return;
+  const int nc = min(NCW, ncol - c0);                  // columns of this workgroup (the rest idle)
+  const int n_s = a.n_s, nrow = n_s + a.n_ch, nrp = (nrow + 63) & ~63;
+  const double2* cvec = a.cvec + pi.q * a.cvec_qs;
+  const double2* runs = a.runs + pi.q * a.runs_qs;
+  if (nrow > 0) {
+    const char* mb = (const char*)a.mtab[pi.k];
+    if (a.m_c64) {
+      for (int j = 0; j < nc; ++j)
+        stage_column(scol + j * nrp, mb, pi.m_off + (long)(c0 + j) * pi.nmb, nrow, 1, lane);
+    } else {
+      // rows past nrow read zero (offsets beyond the resource's size)
+      for (int j = 0; j < nc; ++j) {
+        const auto rs = make_rsrc(uni(mb + (pi.m_off + (long)(c0 + j) * pi.nmb) * 16), (uint32_t)nrow * 16);
+        for (int u = 0; u < nrp / 64; ++u) lds_load16(rs, scol + j * nrp + u * 64, (uint32_t)lane * 16, u * 1024);
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0): the columns have landed in LDS
     }
   }
-  return cadd(y, cmul(cv, S[ri.z]));
-}
-
-// Y_s of the whole column (rows [0, nr), zero from n_s on), one row per lane per round;
-// the next round's row descriptors are requested before this round's coefficient runs.
-template <typename Put>
-__device__ __forceinline__ void herk_rows(const double2* S, const SparseArgs& a, const double2* runs,
-                                          const double2* cvec, int nr, int lane, Put put) {
-  const int n_s = a.n_s;
+  // LDS operations of one wavefront take effect in order: the rows just written are
+  // read below by other lanes of the same wavefront
+  __builtin_amdgcn_wave_barrier();
+  const int nr = MODE == M_F64 ? n_s : a.ns_pad;       // FP64: Y_s; else the packed sparse part
+  double dsum[NCW];
+#pragma unroll
+  for (int j = 0; j < NCW; ++j) dsum[j] = 0.0;
   int4 ri = make_int4(0, 1, 0, 0);
   double2 cv = make_double2(0.0, 0.0);
   if (lane < n_s) { ri = a.rowinfo[lane]; cv = cvec[lane]; }
   for (int r = lane; r < nr; r += 64) {
+    // next round's row descriptors first
     int4 rn = make_int4(0, 1, 0, 0);
     double2 cn = make_double2(0.0, 0.0);
     if (r + 64 < n_s) { rn = a.rowinfo[r + 64]; cn = cvec[r + 64]; }
-    put(r, r < n_s ? herk_row(S, runs + r, a.runs_ld, a.run_max, ri, cv, r) : make_double2(0.0, 0.0));
+    // Y_s[r] = sum_{t < len} conj(L_c[i + t][i]) A[r + t] + l_c[i] A[multipole row of c]:
+    // eight loads of the run per round, unconditional (indices clamped into the table and
+    // the run), the terms past the run add zero
+    double2 y[NCW];
+#pragma unroll
+    for (int j = 0; j < NCW; ++j) y[j] = make_double2(0.0, 0.0);
+    if (r < n_s) {
+      const double2* run = runs + r;
+      for (int t0 = 0; t0 < ri.y; t0 += 8) {
+        double2 cf[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cf[u] = run[(long)min(t0 + u, a.run_max - 1) * a.runs_ld];
+        int sr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool in = t0 + u < ri.y;
+          cf[u] = make_double2(in ? cf[u].x : 0.0, in ? cf[u].y : 0.0);
+          sr[u] = r + min(t0 + u, ri.y - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < NCW; ++j) {
+          double2 sv[8];                     // the column's eight rows, all requested at once
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sv[u] = scol[j * nrp + sr[u]];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) y[j] = cadd(y[j], cmulc(cf[u], sv[u]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NCW; ++j) y[j] = cadd(y[j], cmul(cv, scol[j * nrp + ri.z]));
+    }
+#pragma unroll
+    for (int j = 0; j < NCW; ++j) {
+      if (j >= nc) break;
+      const int col = c0 + j;
+      if constexpr (MODE == M_F64) {
+        ((double2*)a.ws)[pi.ws_off + (long)col * pi.ldw + r] = y[j];
+      } else {
+        using lds_t = typename Traits<MODE>::lds_t;
+        constexpr int NP = Traits<MODE>::NPIECE;
+        lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
+        dsum[j] += y[j].x * y[j].x + y[j].y * y[j].y;
+        put_real<MODE>(out + r, pi.ldw, y[j].x);
+        put_real<MODE>(out + (long)NP * pi.ldw + r, pi.ldw, y[j].y);
+      }
+    }
     ri = rn;
     cv = cn;
   }
-}
-
-template <int FORM, int MODE>
-__global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
-  extern __shared__ double2 scol[];          // HERK: [n_s + n_ch]; GEMM: [4 waves][n_s + n_ch]
-  const int w = FORM == 1 ? 0 : threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const PairInfo pi = a.pairs[blockIdx.y];
-  const double2* coef = a.coef + pi.q * a.coef_qs;      // this q's channel blocks
-  const double2* cvec = a.cvec + pi.q * a.cvec_qs;
-  const double2* runs = a.runs + pi.q * a.runs_qs;      // (HERK)
-  const int col = FORM == 1 ? (int)blockIdx.x : (int)blockIdx.x * 4 + w;
-  const bool active = col < a.n_occ * pi.nb;
-  const int nrow = a.n_s + a.n_ch;
-  double2* S = scol + (long)w * nrow;
-  if (FORM == 1 && !active) return;
-  if (active && nrow > 0)
-    stage_column(S, (const char*)a.mtab[pi.k], pi.m_off + (long)col * pi.nmb, nrow, a.m_c64, lane);
-  if constexpr (FORM == 1) {
-    // LDS operations of one wavefront take effect in order: the rows just written are
-    // read below by other lanes of the same wavefront
-    __builtin_amdgcn_wave_barrier();
-  } else {
-    __syncthreads();
-    if (!active) return;                     // whole wavefronts leave; no barrier follows
-  }
-  double dsum = 0.0;
-  if constexpr (MODE == M_F64) {
-    const long wcol = pi.ws_off + (long)col * pi.ldw;
-    double2* out = (double2*)a.ws;
-    if constexpr (FORM == 1) {
-      herk_rows(S, a, runs, cvec, a.n_s, lane, [&](int r, double2 y) { out[wcol + r] = y; });
-    } else {
-      for (int r = lane; r < a.n_s; r += 64) {
-        const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
-        const double2* cf = coef + a.ch_coef[c];
-        double2 y = make_double2(0.0, 0.0);
-        for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], S[s + j]));
-        out[wcol + r] = cadd(y, cmul(cvec[r], S[a.n_s + c]));
-      }
-      for (int c = lane; c < a.n_ch; c += 64) {
-        const int s = a.ch_off[c], b = a.ch_len[c];
-        double2 x = make_double2(0.0, 0.0);
-        for (int j = 0; j < b; ++j) x = cadd(x, cmulc(cvec[s + j], S[s + j]));
-        out[wcol + a.n_s + c] = x;
-      }
-    }
-  } else {
-    // pack the whole column into the tile kernel's split planes [plane][row]:
-    // rows [0, ns_pad) = Y_s (zero beyond n_s), rows [ns_pad, ldw) = the dense
-    // rows A_d of M (zero beyond N_d)
+  if constexpr (MODE != M_F64) {
+    // the dense rows A_d of M into the packed column (zero beyond N_d), and the FP64
+    // sums of |Y_s|^2 per column
     using lds_t = typename Traits<MODE>::lds_t;
     constexpr int NP = Traits<MODE>::NPIECE;
-    lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
-    herk_rows(S, a, runs, cvec, a.ns_pad, lane, [&](int r, double2 y) {
-      dsum += y.x * y.x + y.y * y.y;
-      put_real<MODE>(out + r, pi.ldw, y.x);
-      put_real<MODE>(out + (long)NP * pi.ldw + r, pi.ldw, y.y);
-    });
-    const long mcol = pi.m_off + (long)col * pi.nmb + a.n_s;
     const char* mb = (const char*)a.mtab[pi.k];
-    for (int d = lane; d < pi.ldw - a.ns_pad; d += 64) {
-      double2 x = make_double2(0.0, 0.0);
-      if (d < pi.nd) {
-        if (a.m_c64) {
-          const float2 v = ((const float2*)mb)[mcol + d];
-          x = make_double2(v.x, v.y);
-        } else {
-          x = ((const double2*)mb)[mcol + d];
+#pragma unroll
+    for (int j = 0; j < NCW; ++j) {
+      if (j >= nc) break;
+      const int col = c0 + j;
+      lds_t* out = (lds_t*)a.ws + pi.ws_off + (long)col * 2 * NP * pi.ldw;
+      const long mcol = pi.m_off + (long)col * pi.nmb + n_s;
+      for (int d = lane; d < pi.ldw - a.ns_pad; d += 64) {
+        double2 x = make_double2(0.0, 0.0);
+        if (d < pi.nd) {
+          if (a.m_c64) {
+            const float2 v = ((const float2*)mb)[mcol + d];
+            x = make_double2(v.x, v.y);
+          } else {
+            x = ((const double2*)mb)[mcol + d];
+          }
         }
+        put_real<MODE>(out + a.ns_pad + d, pi.ldw, x.x);
+        put_real<MODE>(out + (long)NP * pi.ldw + a.ns_pad + d, pi.ldw, x.y);
       }
-      put_real<MODE>(out + a.ns_pad + d, pi.ldw, x.x);
-      put_real<MODE>(out + (long)NP * pi.ldw + a.ns_pad + d, pi.ldw, x.y);
+      double ds = dsum[j];
+      for (int o = 32; o > 0; o >>= 1) ds += __shfl_xor(ds, o);
+      if (lane == 0) a.dsp[(long)blockIdx.y * a.n_occ * a.nb_max + col] = ds;
     }
-    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if (lane == 0) a.dsp[(long)blockIdx.y * a.n_occ * a.nb_max + col] = dsum;
+  }
+}
+
+// HERK form: herk_columns (one wavefront per workgroup). GEMM form (FP64 only): four
+// wavefronts, one column each.
+template <int FORM, int MODE, int NCW = 1>
+__global__ __launch_bounds__(256) void sparse_kernel(SparseArgs a) {
+  extern __shared__ double2 scol[];          // HERK: [NCW][nrow rounded up to 64]; GEMM: [4 waves][nrow]
+  if constexpr (FORM == 1) {
+    herk_columns<MODE, NCW>(a, scol);
+  } else {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const PairInfo pi = a.pairs[blockIdx.y];
+    const double2* coef = a.coef + pi.q * a.coef_qs;      // this q's channel blocks
+    const double2* cvec = a.cvec + pi.q * a.cvec_qs;
+    const int col = (int)blockIdx.x * 4 + w;
+    const bool active = col < a.n_occ * pi.nb;
+    const int nrow = a.n_s + a.n_ch;
+    double2* S = scol + (long)w * nrow;
+    if (active && nrow > 0)
+      stage_column(S, (const char*)a.mtab[pi.k], pi.m_off + (long)col * pi.nmb, nrow, a.m_c64, lane);
+    __syncthreads();
+    if (!active) return;                     // whole wavefronts leave; no barrier follows
+    const long wcol = pi.ws_off + (long)col * pi.ldw;
+    double2* out = (double2*)a.ws;
+    for (int r = lane; r < a.n_s; r += 64) {
+      const int c = a.row_chan[r], s = a.ch_off[c], b = a.ch_len[c], i = r - s;
+      const double2* cf = coef + a.ch_coef[c];
+      double2 y = make_double2(0.0, 0.0);
+      for (int j = 0; j < b; ++j) y = cadd(y, cmul(cf[i + (long)j * b], S[s + j]));
+      out[wcol + r] = cadd(y, cmul(cvec[r], S[a.n_s + c]));
+    }
+    for (int c = lane; c < a.n_ch; c += 64) {
+      const int s = a.ch_off[c], b = a.ch_len[c];
+      double2 x = make_double2(0.0, 0.0);
+      for (int j = 0; j < b; ++j) x = cadd(x, cmulc(cvec[s + j], S[s + j]));
+      out[wcol + a.n_s + c] = x;
+    }
   }
 }
 

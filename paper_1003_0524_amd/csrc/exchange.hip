@@ -711,19 +711,33 @@ hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGrap
   return hipGraphAddKernelNode(out, g, dep, dep ? 1 : 0, &p);
 }
 
-// sparse_kernel: one column per workgroup in the HERK form, four in the GEMM form
+// sparse_kernel: HERK form, one wavefront per workgroup taking sparse_ncw(c) columns
+// (as many as keep its LDS within 24 KiB: at least six workgroups per CU); GEMM form, four
+// wavefronts of one column each.
 bool sparse_herk(const exc_ctx* c) { return c->form == EXC_FORM_CHOL_HERK; }
+int sparse_ncw(const exc_ctx* c) {
+  if (!sparse_herk(c)) return 1;
+  const size_t col = (size_t)((c->n_s + c->n_ch + 63) / 64 * 64) * sizeof(double2);
+  return 4 * col <= 24576 ? 4 : (2 * col <= 24576 ? 2 : 1);
+}
 size_t sparse_lds_bytes(const exc_ctx* c) {
-  return (size_t)(sparse_herk(c) ? 1 : 4) * (c->n_s + c->n_ch) * sizeof(double2);
+  if (!sparse_herk(c)) return (size_t)4 * (c->n_s + c->n_ch) * sizeof(double2);
+  return (size_t)sparse_ncw(c) * ((c->n_s + c->n_ch + 63) / 64 * 64) * sizeof(double2);
 }
 
+template <int MODE>
+const void* sparse_herk_fn(int ncw) {
+  return ncw == 4 ? (const void*)sparse_kernel<1, MODE, 4>
+                  : (ncw == 2 ? (const void*)sparse_kernel<1, MODE, 2> : (const void*)sparse_kernel<1, MODE, 1>);
+}
 const void* sparse_fn(const exc_ctx* c) {
   if (c->form != EXC_FORM_CHOL_HERK) return (const void*)sparse_kernel<0, M_F64>;
+  const int ncw = sparse_ncw(c);
   switch (c->precision) {
-    case EXC_FP64: return (const void*)sparse_kernel<1, M_F64>;
-    case EXC_FP32: return (const void*)sparse_kernel<1, M_F32>;
-    case EXC_BF16X3: return (const void*)sparse_kernel<1, M_BF16X3>;
-    default: return (const void*)sparse_kernel<1, M_BF16X6>;
+    case EXC_FP64: return sparse_herk_fn<M_F64>(ncw);
+    case EXC_FP32: return sparse_herk_fn<M_F32>(ncw);
+    case EXC_BF16X3: return sparse_herk_fn<M_BF16X3>(ncw);
+    default: return sparse_herk_fn<M_BF16X6>(ncw);
   }
 }
 
@@ -738,7 +752,8 @@ bool cfg_sparse(exc_ctx* c, int dtype, int k, int pair0, int npairs, SparseArgs&
   // dsp is indexed by blockIdx.y: offset it to the first pair
   s.dsp = s.dsp ? s.dsp + (long)pair0 * c->n_occ * c->nb_max : nullptr;
   const int ncol = c->n_occ * c->nb_max;
-  L.grid = sparse_herk(c) ? dim3(ncol, npairs) : dim3((ncol + 3) / 4, npairs);
+  const int ncw = sparse_ncw(c);
+  L.grid = sparse_herk(c) ? dim3((ncol + ncw - 1) / ncw, npairs) : dim3((ncol + 3) / 4, npairs);
   L.block = dim3(sparse_herk(c) ? 64 : 256);
   L.shmem = sparse_lds_bytes(c);
   L.fn = sparse_fn(c);

@@ -33,31 +33,6 @@
 
 namespace exc {
 
-// Buffer loads: one scalar resource per item (base, size in bytes), a per-lane
-// 32-bit offset and a wave-uniform scalar offset, so that the many loads of a
-// K panel share one address register. Offsets at or beyond the size read zero.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-template <class OP>
-__device__ __forceinline__ OP buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(OP) == 16) {
-    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
-  } else if constexpr (sizeof(OP) == 8) {
-    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-  } else {
-    return __builtin_bit_cast(OP, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-  }
-}
-
-// 16 bytes per lane from a buffer straight into LDS: lane l writes lds + 16 l
-// (the LDS address must be wave-uniform). A device function, not a lambda: the
-// host pass of the compiler has no such builtin.
-__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t r, void* lds, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, (int)voff,
-                                           (int)soff, 0, 0);
-}
-
 // Lane l takes the value of lane l + 1 (the last lane takes zero): a whole-wavefront DPP
 // shift, per 32-bit half.
 __device__ __forceinline__ double shift_down1(double x) {
@@ -67,18 +42,6 @@ __device__ __forceinline__ double shift_down1(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 __device__ __forceinline__ double2 shift_down1(double2 v) { return make_double2(shift_down1(v.x), shift_down1(v.y)); }
-
-// Values the whole workgroup shares, moved to scalar registers: loads of them
-// are vector loads (the kernel also writes global memory), and buffer
-// resources built from vector registers would need a loop over lanes.
-__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ int64_t uni(int64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-template <class T>
-__device__ __forceinline__ T* uni(T* p) { return (T*)uni((int64_t)p); }
 
 // Work queues of the persistent launch: NQ queues (one per XCD: consecutive
 // workgroups are dispatched to the 8 XCDs in turn, so workgroup b serves queue
