@@ -344,7 +344,8 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
  * keeps the default choice; EXC_TUNE_CACHE=<file> looks the choice up / appends
  * it under a key of the problem's sizes; EXC_FUSED_CFG=<id> fixes a fused
  * instance (EXC_FUSED_SPLIT=1: an item per n'' chunk) and EXC_FUSED=0 the
- * block-sparse + tile path (neither is then tuned).
+ * block-sparse + tile path (neither is then tuned); EXC_SPARSE_NCW=1|2|4 fixes the
+ * columns each wavefront of the block-sparse kernel takes (HERK form).
  */
 
 /*

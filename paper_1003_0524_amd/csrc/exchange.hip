@@ -230,6 +230,7 @@ struct exc_ctx {
   const FusedKCfg* fcfg = nullptr;    // non-null: reduced-precision HERK through the fused kernel
   bool fused = false;
   bool fused_ok = false;              // the fused kernel can serve this context
+  int sncw = 1;                       // sparse_kernel (HERK form): columns per wavefront
   int fsplit = 0;                     // fused items: 1 = one per n'' chunk, 2 = one per n'' chunk and row
                                       // part (more, smaller items)
   int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
@@ -711,13 +712,18 @@ hipError_t add_node(hipGraph_t g, const KLaunch& L, hipGraphNode_t* dep, hipGrap
   return hipGraphAddKernelNode(out, g, dep, dep ? 1 : 0, &p);
 }
 
-// sparse_kernel: HERK form, one wavefront per workgroup taking sparse_ncw(c) columns
-// (as many as keep its LDS within 24 KiB: at least six workgroups per CU); GEMM form, four
-// wavefronts of one column each.
+// sparse_kernel: HERK form, one wavefront per workgroup taking c->sncw columns (set once by
+// pick_sparse_ncw); GEMM form, four wavefronts of one column each.
 bool sparse_herk(const exc_ctx* c) { return c->form == EXC_FORM_CHOL_HERK; }
-int sparse_ncw(const exc_ctx* c) {
-  if (!sparse_herk(c)) return 1;
+int sparse_ncw(const exc_ctx* c) { return sparse_herk(c) ? c->sncw : 1; }
+// As many columns (1, 2 or 4) as keep the workgroup's LDS within 24 KiB: at least six
+// workgroups per CU. EXC_SPARSE_NCW=1|2|4 fixes the count (fixed-configuration runs).
+int pick_sparse_ncw(const exc_ctx* c) {
   const size_t col = (size_t)((c->n_s + c->n_ch + 63) / 64 * 64) * sizeof(double2);
+  if (const char* ev = getenv("EXC_SPARSE_NCW")) {
+    const int n = atoi(ev);
+    if ((n == 1 || n == 2 || n == 4) && n * col <= 160 * 1024) return n;
+  }
   return 4 * col <= 24576 ? 4 : (2 * col <= 24576 ? 2 : 1);
 }
 size_t sparse_lds_bytes(const exc_ctx* c) {
@@ -1558,6 +1564,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   IHIP(hipMemset(c->d_tmask, 0xFF, (size_t)3 * c->n_k * sizeof(uint64_t)));   // every tile pair
   IHIP(hipMemset(c->d_gamma, 0, 4 * sizeof(double)));   // no Gamma-point shift until requested
 
+  c->sncw = pick_sparse_ncw(c);
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = std::min(2, std::max(0, atoi(ev)));   // (fixed-configuration runs)
