@@ -103,8 +103,8 @@ typedef struct {
   int32_t precision;        /* exc_precision                                             */
   int32_t form;             /* exc_form                                                  */
   int32_t batched;          /* exchange_matrix_all: 1 = one persistent launch over all
-                               (k,q) work captured in a HIP graph; 0 = one launch per
-                               (k,q) pair, no graph. Unbatched, the GEMM form runs per
+                               (k,q) work (EXC_GRAPH=1: replayed from a HIP graph); 0 =
+                               one launch per (k,q) pair. Unbatched, the GEMM form runs per
                                pair the block-sparse rows of W = v A, W_d = E A_d + X and
                                A^H W on FP64 matrix cores, and accumulates V(k) in FP64 in
                                the order of q                                            */
@@ -189,8 +189,9 @@ exc_status exchange_matrix_noalloc(exc_ctx *ctx, int32_t k, const void *M, int32
 /*
  * exchange_matrix_all -- V^x(k) for every irreducible k. M_k[k] and Vx_k[k] are
  * laid out as for exchange_matrix. With desc.batched = 1 all (k, q) work runs
- * in one persistent launch replayed from a HIP graph (re-captured when the
- * pointers change); otherwise one launch per (k, q) pair.
+ * in one persistent launch, followed by the FP64 q-sum, both enqueued on `stream`
+ * (EXC_GRAPH=1: replayed from a HIP graph, re-captured when the pointers change);
+ * otherwise one launch per (k, q) pair.
  */
 exc_status exchange_matrix_all(exc_ctx *ctx, const void *const *M_k, int32_t dtype,
                                int32_t on_device, void *const *Vx_k, void *stream);
@@ -345,16 +346,17 @@ exc_status exchange_query(const exc_ctx *ctx, int32_t what, double *value);
  * it under a key of the problem's sizes; EXC_FUSED_CFG=<id> fixes a fused
  * instance (EXC_FUSED_SPLIT=1: an item per n'' chunk) and EXC_FUSED=0 the
  * block-sparse + tile path (neither is then tuned); EXC_SPARSE_NCW=1|2|4 fixes the
- * columns each wavefront of the block-sparse kernel takes (HERK form).
+ * columns each wavefront of the block-sparse kernel takes (HERK form); EXC_GRAPH=1
+ * replays the batched launch from a HIP graph instead of enqueueing its kernels.
  */
 
 /*
  * exchange_timing -- live kernel timing of the batched exchange_matrix_all
- * path for benchmarks. n_slots > 0: the next captured graph carries event-
- * record nodes around the block-sparse kernel and the tile kernel, and each
- * replay records into its own slot of a pool of n_slots event triples (the
- * last n_slots replays are kept). n_slots = 0 switches timing off. Both
- * synchronise the device and drop the current graph. Read the means with
+ * path for benchmarks. n_slots > 0: events are recorded around the block-sparse
+ * kernel and the tile kernel (event-record nodes of the next captured graph with
+ * EXC_GRAPH=1), and each call records into its own slot of a pool of n_slots
+ * event triples (the last n_slots calls are kept). n_slots = 0 switches timing
+ * off. Both synchronise the device and drop the current graph. Read the means with
  * exchange_query: what = 5 tile kernel ms, 7 sparse kernel ms, 6 replays timed.
  */
 exc_status exchange_timing(exc_ctx *ctx, int32_t n_slots);

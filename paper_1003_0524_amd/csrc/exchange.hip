@@ -231,6 +231,8 @@ struct exc_ctx {
   bool fused = false;
   bool fused_ok = false;              // the fused kernel can serve this context
   int sncw = 1;                       // sparse_kernel (HERK form): columns per wavefront
+  bool direct = true;                 // batched path: kernels enqueued one by one (EXC_GRAPH=1: a graph)
+  bool t_sparse = false;              // (direct launches) the timed replays include a sparse kernel
   int fsplit = 0;                     // fused items: 1 = one per n'' chunk, 2 = one per n'' chunk and row
                                       // part (more, smaller items)
   int tuned = 0;                      // 0 default choice, 1 timed by the autotuner, 2 from the tune cache
@@ -917,6 +919,38 @@ exc_status run_k_plain_gemm(exc_ctx* c, int k, int dtype, hipStream_t st) {
   return EXC_OK;
 }
 
+// The kernels of the batched path launched one by one on st, in the graph's order, with the
+// timing events recorded on st (the default: the graph's launch leaves a longer gap before
+// its first kernel, 6-8 us more per step on the Si-like workload; EXC_GRAPH=1 uses the graph).
+exc_status launch_batched_direct(exc_ctx* c, int dtype, hipStream_t st) {
+  if (!c->fused) TRY(ensure_ws(c, c->ws_bytes));
+  const bool timed = c->t_slots > 0;
+  const int s = c->t_next;
+  SparseArgs sa;
+  KLaunch L;
+  c->t_sparse = false;
+  if (cfg_sparse(c, dtype, -1, 0, (int)c->pairs.size(), sa, L)) {
+    if (timed) HIPCHK(c, hipEventRecord(c->tpool[3 * s], st));
+    HIPCHK(c, enqueue(L, st));
+    c->t_sparse = true;
+  }
+  if (timed) HIPCHK(c, hipEventRecord(c->tpool[3 * s + 1], st));
+  MainArgs ta;
+  cfg_tile(c, dtype, -1, c->bat.d_items_lpt, c->bat.n_slots, true, ta, L);
+  HIPCHK(c, enqueue(L, st));
+  if (timed) HIPCHK(c, hipEventRecord(c->tpool[3 * s + 2], st));
+  ReduceArgs ra;
+  cfg_reduce(c, c->bat, 0, c->n_k, ra, L);
+  ra.counter = c->d_counter;
+  ra.n_counter = NQ_MAX;
+  HIPCHK(c, enqueue(L, st));
+  if (timed) {
+    c->t_next = (s + 1) % c->t_slots;
+    c->t_count = std::min(c->t_count + 1, c->t_slots);
+  }
+  return EXC_OK;
+}
+
 // The batched path as an explicit graph:
 //   [ev0] -> block-sparse rows -> [ev1] -> persistent tile (or fused) kernel ->
 //   [ev2] -> FP64 reduction, which also clears the persistent kernel's work
@@ -1565,6 +1599,7 @@ exc_status exchange_init(const exc_desc* d, const exc_coulomb* cv, void* stream,
   IHIP(hipMemset(c->d_gamma, 0, 4 * sizeof(double)));   // no Gamma-point shift until requested
 
   c->sncw = pick_sparse_ncw(c);
+  if (const char* ev = getenv("EXC_GRAPH")) c->direct = ev[0] != '1';
   if (sparse_lds_bytes(c) > 65536)
     IHIP(hipFuncSetAttribute(sparse_fn(c), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sparse_lds_bytes(c)));
   if (const char* ev = getenv("EXC_FUSED_SPLIT")) c->fsplit = std::min(2, std::max(0, atoi(ev)));   // (fixed-configuration runs)
@@ -1730,6 +1765,12 @@ exc_status exchange_matrix_all(exc_ctx* c, const void* const* M_k, int32_t dtype
       c->tune_done = true;
     }
     TRY(fit_dtype(c, dtype, st));                  // (a fixed or earlier choice may read complex64 only)
+    if (c->direct) {
+      TRY(set_tables(c, 0, c->n_k, M_k, Vx_k, st));
+      TRY(launch_batched_direct(c, dtype, st));
+      for (int k = 0; k < c->n_k; ++k) c->v_valid[k] = 1;
+      return EXC_OK;
+    }
     bool same = c->gexec && c->g_dtype == dtype;
     for (int k = 0; k < c->n_k && same; ++k)
       if (c->h_mtab[k] != M_k[k] || c->h_vtab[k] != Vx_k[k]) same = false;
@@ -1978,7 +2019,10 @@ exc_status exchange_query(const exc_ctx* c, int32_t what, double* value) {
     case 5:
     case 7: {
       // mean duration (ms) of the tile (5) or sparse (7) kernel over the timed replays
-      if (c->t_count == 0 || (what == 7 && !c->tnode[0])) { *value = 0.0; return EXC_OK; }
+      if (c->t_count == 0 || (what == 7 && !(c->direct ? c->t_sparse : c->tnode[0] != nullptr))) {
+        *value = 0.0;
+        return EXC_OK;
+      }
       double sum = 0.0;
       for (int s = 0; s < c->t_count; ++s) {
         hipEvent_t* e = const_cast<hipEvent_t*>(&c->tpool[3 * s]);

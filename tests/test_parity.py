@@ -141,19 +141,29 @@ def test_complex64_input(precision):
         assert pr.normwise_error(Vs[k], ref) <= tol
 
 
-def test_repeated_runs_are_bitwise_identical():
+def test_repeated_runs_are_bitwise_identical(monkeypatch):
+    """Repeated batched calls, with the kernels enqueued one by one (the default) and
+    replayed from a HIP graph (EXC_GRAPH=1), all give the same bits."""
     name = "ragged"
     cfg = _case(name)[0]
-    _say("[parity] determinism ragged bf16x3 batched graph replays")
-    ex = _ex(name, "bf16x3", "herk", True)
     Ms = [_m(cfg, k) for k in range(cfg.n_k)]
-    first = [V.cpu().numpy().copy() for V in ex.matrix_all(Ms)]
-    for _ in range(3):
-        torch.cuda.synchronize()
-        again = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
-        for a, b in zip(first, again):
+    ref = None
+    for graph in ("0", "1"):
+        monkeypatch.setenv("EXC_GRAPH", graph)
+        monkeypatch.setenv("EXC_TUNE", "0")      # the same (default) instance for both launch modes
+        _say(f"[parity] determinism ragged bf16x3 batched, EXC_GRAPH={graph}")
+        ex = _ex(name, "bf16x3", "herk", True)
+        first = [V.cpu().numpy().copy() for V in ex.matrix_all(Ms)]
+        for _ in range(3):
+            torch.cuda.synchronize()
+            again = [V.cpu().numpy() for V in ex.matrix_all(Ms)]
+            for a, b in zip(first, again):
+                assert np.array_equal(a, b)
+        ex.close()
+        if ref is None:
+            ref = first
+        for a, b in zip(ref, first):
             assert np.array_equal(a, b)
-    ex.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
