@@ -268,7 +268,7 @@ struct ReduceArgs {
 };
 
 // Slot groups per q-sum workgroup: group sg sums slots sg, sg + RED_SG, ... of its k
-// (one round of loads for up to 4 RED_SG slots), the groups are added in order.
+// (one round of loads for up to 6 RED_SG slots), the groups are added in order.
 constexpr int RED_SG = 16;
 
 // Position of G[row][col] of Gram tile tp in a partial slot written as
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(64 * RED_SG) void reduce_kernel(ReduceArgs a) {
   double re = 0.0, im = 0.0, dg = 0.0;
   const bool diag = (n == n2) && n < nb;
   // slots sg, sg + RED_SG, ... in order; UN slots' loads are issued before their adds
-  constexpr int UN = 4;
+  constexpr int UN = 6;
   const int s0 = a.slot_begin[k] + sg, s1 = a.slot_begin[k + 1];
   for (int sb = s0; sb < s1; sb += RED_SG * UN) {
     double wq[UN], grr[UN], gii[UN], gri[UN], gir[UN], dd[UN];
