@@ -296,35 +296,33 @@ __global__ __launch_bounds__(64 * RED_SG) void reduce_kernel(ReduceArgs a) {
   const int irr = gidx<ACC64>(tp, c, c2), iii = gidx<ACC64>(tp, c + 8, c2 + 8);
   const int iri = gidx<ACC64>(tp, c, c2 + 8), iir = gidx<ACC64>(tp, c + 8, c2);
   double re = 0.0, im = 0.0, dg = 0.0;
-  const bool diag = (n == n2) && n < nb;
-  // slots sg, sg + RED_SG, ... in order; UN slots' loads are issued before their adds
+  // slots sg, sg + RED_SG, ... in order; UN slots' loads are issued before their adds,
+  // unconditionally: a slot past the end reads the last slot of k and weighs it by zero
   constexpr int UN = 6;
   const int s0 = a.slot_begin[k] + sg, s1 = a.slot_begin[k + 1];
+  const bool use_d = a.use_d64 != 0;
+  const int nc = min(n, nb - 1);             // (the diagonal entry of this lane's column)
   for (int sb = s0; sb < s1; sb += RED_SG * UN) {
     double wq[UN], grr[UN], gii[UN], gri[UN], gir[UN], dd[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      const int s = sb + RED_SG * u;
-      wq[u] = grr[u] = gii[u] = gri[u] = gir[u] = dd[u] = 0.0;
-      if (s < s1) {
-        wq[u] = a.slot_w[s];
-        if (ACC64) {
-          const double* g = (const double*)a.gpart + (long)s * a.gstride;
-          grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
-        } else {
-          const float* g = (const float*)a.gpart + (long)s * a.gstride;
-          grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
-        }
-        if (diag && a.use_d64) dd[u] = a.dpart[(long)s * a.dstride + n];
+      const int s = sb + RED_SG * u, sc = min(s, s1 - 1);
+      const double w = a.slot_w[sc];
+      wq[u] = s < s1 ? w : 0.0;
+      if (ACC64) {
+        const double* g = (const double*)a.gpart + (long)sc * a.gstride;
+        grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
+      } else {
+        const float* g = (const float*)a.gpart + (long)sc * a.gstride;
+        grr[u] = g[irr]; gii[u] = g[iii]; gri[u] = g[iri]; gir[u] = g[iir];
       }
+      dd[u] = use_d ? a.dpart[(long)sc * a.dstride + nc] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      if (sb + RED_SG * u < s1) {
-        re += wq[u] * (grr[u] + gii[u]);
-        im += wq[u] * (gri[u] - gir[u]);
-        if (diag && a.use_d64) dg += wq[u] * dd[u];
-      }
+      re += wq[u] * (grr[u] + gii[u]);
+      im += wq[u] * (gri[u] - gir[u]);
+      dg += wq[u] * dd[u];
     }
   }
   red[sg][e][0] = re;
