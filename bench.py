@@ -38,6 +38,11 @@ import os
 import sys
 import time
 
+# Kernel arguments in device memory (a HIP runtime setting, read when HIP starts): each kernel of a
+# step then starts without reading its arguments from host memory; the Si-like step is 3-5 us
+# shorter with it. A value already in the environment is kept.
+os.environ.setdefault("HIP_FORCE_DEV_KERNARG", "1")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
