@@ -159,6 +159,7 @@ const FusedKCfg kFused[] = {
     WCFG(M_F32, 13, 2, 180),           WCFG(M_BF16X3, 13, 2, 181),        WCFG(M_BF16X6, 13, 2, 182),
     WCFG(M_F32, 16, 2, 183),           WCFG(M_BF16X3, 16, 2, 184),
     WCFG(M_F32, 13, 1, 186),           WCFG(M_BF16X3, 13, 1, 187),        WCFG(M_BF16X6, 13, 1, 188),
+    WCFG(M_F32, 8, 2, 189),            WCFG(M_BF16X3, 8, 2, 190),         WCFG(M_BF16X6, 8, 2, 191),
 };
 
 struct Plan {

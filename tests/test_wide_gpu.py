@@ -24,8 +24,8 @@ from _emulation import predicted
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-WIDE = {"fp32": [180, 186, 183], "bf16x3": [181, 187, 184], "bf16x6": [182, 188]}
-CAP = {180: 13, 181: 13, 182: 13, 183: 16, 184: 16, 186: 13, 187: 13, 188: 13}
+WIDE = {"fp32": [180, 186, 183, 189], "bf16x3": [181, 187, 184, 190], "bf16x6": [182, 188, 191]}
+CAP = {180: 13, 181: 13, 182: 13, 183: 16, 184: 16, 186: 13, 187: 13, 188: 13, 189: 8, 190: 8, 191: 8}
 
 
 @functools.lru_cache(maxsize=None)
